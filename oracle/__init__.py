@@ -1,0 +1,238 @@
+"""Plain CPU oracle for the exact Matern kernel MVM and the direct GP solve.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+baseline of the benchmark import this package.  It shares no code with the
+HIP library in ``paper_2508_01864_amd`` and never imports it.
+
+Contents (each function cites the passage it follows):
+
+* ``mvm``            dense FP64 y_j = sum_i K(z_j, x_i) v_i (Section 2, eq. Ky)
+                     with Neumaier-compensated rows, in C (``oracle.c``).
+* ``kernel_matrix``  dense K (eq. covariance_matrix), optionally + sigma^2 I.
+* ``cholesky`` / ``cholesky_solve``  textbook Cholesky of K + sigma^2 I and
+                     the direct solve of eq. gp_mean_system.
+* ``gls``            generalised least squares fixed effects (Section 3.2,
+                     the beta_GLS formula) with H = [1, x_1 .. x_d].
+* ``predict``        posterior mean h(z)^T beta + k_z^T alpha (eq. gp_mean,
+                     eq. gp_mean_2).
+* ``decomposition``  (sub-module) the paper's weighted-ECDF decomposition
+                     evaluated by brute-force masked sums (Props. 1-2 and the
+                     Matern examples of Section 2.3); used only to pin the
+                     dense oracle and the tie conventions on small inputs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+FORM_L1 = 0
+FORM_PRODUCT = 1
+FORMS = {"l1": FORM_L1, "product": FORM_PRODUCT, FORM_L1: FORM_L1, FORM_PRODUCT: FORM_PRODUCT}
+
+_lib = None
+
+
+class NotPositiveDefinite(RuntimeError):
+    """Raised when the Cholesky factorisation meets a non-positive pivot."""
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` into ``liboracle.so`` with gcc and OpenMP.
+
+    Generic x86-64-v3 code (AVX2 + FMA) so the library runs on any recent
+    host, and no fast-math (it would undo the compensated summation).
+    """
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O3", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared",
+               "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    """Load (building first if absent) the oracle shared library."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        P = ctypes.c_void_p
+        L.oracle_matern_profile.argtypes = [i32, dbl]
+        L.oracle_matern_profile.restype = dbl
+        L.oracle_profile_array.argtypes = [i32, i64, P, P]
+        L.oracle_profile_array.restype = i32
+        L.oracle_kernel.argtypes = [i32, P, P, i32, i32, dbl, dbl]
+        L.oracle_kernel.restype = dbl
+        mvm_args = [i64, i32, P, i64, i64, P, i64, i32, i32, dbl, dbl, P, i64, i32, P, i64, P]
+        L.oracle_mvm.argtypes = mvm_args
+        L.oracle_mvm.restype = i32
+        L.oracle_mvm_multi.argtypes = mvm_args
+        L.oracle_mvm_multi.restype = i32
+        L.oracle_kernel_matrix.argtypes = [i64, i32, P, i64, i64, P, i64, i32, i32, dbl, dbl,
+                                           dbl, i32, P, i64]
+        L.oracle_kernel_matrix.restype = i32
+        L.oracle_cholesky.argtypes = [i64, P, i64]
+        L.oracle_cholesky.restype = i32
+        L.oracle_cholesky_solve.argtypes = [i64, P, i64, P, i64, i32]
+        L.oracle_cholesky_solve.restype = i32
+        L.oracle_num_threads.argtypes = []
+        L.oracle_num_threads.restype = i32
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle uses (OMP_NUM_THREADS or all cores)."""
+    return int(lib().oracle_num_threads())
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _points(x) -> np.ndarray:
+    """Points as a Fortran-ordered (n, d) float64 array (column k = coordinate k)."""
+    x = np.asarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+    return np.asfortranarray(x)
+
+
+def profile(two_nu: int, r) -> np.ndarray:
+    """Matern profile k_nu(r) (Appendix C, eq. matern_1_2 / 3_2 / 5_2)."""
+    r = np.ascontiguousarray(np.asarray(r, dtype=np.float64))
+    out = np.empty_like(r)
+    lib().oracle_profile_array(int(two_nu), r.size, _ptr(r), _ptr(out))
+    return out
+
+
+def kernel(a, b, two_nu: int, form, ell: float, s2: float = 1.0) -> float:
+    """Scalar K(a, b) for two d-vectors (eq. L1_kernel / product_kernel, scaled)."""
+    a = np.ascontiguousarray(np.atleast_1d(np.asarray(a, dtype=np.float64)))
+    b = np.ascontiguousarray(np.atleast_1d(np.asarray(b, dtype=np.float64)))
+    return float(lib().oracle_kernel(a.size, _ptr(a), _ptr(b), int(two_nu), FORMS[form],
+                                     float(ell), float(s2)))
+
+
+def mvm(x, v, two_nu: int, form, ell: float, s2: float = 1.0, z=None,
+        with_abs: bool = False, shared_kernel: bool = False):
+    """Dense y = K(Z, X) v with compensated row sums (Section 2, eq. Ky / kde).
+
+    x: (n, d) sources; v: (n,) or (n, nrhs); z: (m, d) targets (default x).
+    Returns y (same trailing shape as v) and, if ``with_abs``, sum_i |K_ji v_i|.
+    ``shared_kernel`` evaluates each kernel entry once for all right-hand sides
+    (same arithmetic per column; faster at many columns).
+    """
+    x = _points(x)
+    n, d = x.shape
+    zz = x if z is None else _points(z)
+    if zz.shape[1] != d:
+        raise ValueError("z must have the same dimension as x")
+    m = zz.shape[0]
+    v = np.asarray(v, dtype=np.float64)
+    vec = v.ndim == 1
+    V = np.asfortranarray(v[:, None] if vec else v)
+    if V.shape[0] != n:
+        raise ValueError("v must have n rows")
+    nrhs = V.shape[1]
+    Y = np.zeros((m, nrhs), dtype=np.float64, order="F")
+    A = np.zeros((m, nrhs), dtype=np.float64, order="F")
+    fn = lib().oracle_mvm_multi if shared_kernel else lib().oracle_mvm
+    rc = fn(n, d, _ptr(x), max(n, 1), m, _ptr(zz), max(m, 1), int(two_nu), FORMS[form],
+            float(ell), float(s2), _ptr(V), max(n, 1), nrhs, _ptr(Y), max(m, 1), _ptr(A))
+    if rc != 0:
+        raise ValueError("oracle_mvm rejected its arguments")
+    if vec:
+        Y, A = Y[:, 0], A[:, 0]
+    return (Y, A) if with_abs else Y
+
+
+def kernel_matrix(x, two_nu: int, form, ell: float, s2: float = 1.0, z=None,
+                  sigma2: float = 0.0) -> np.ndarray:
+    """Dense K(Z, X) (eq. covariance_matrix); with z=None adds sigma2 on the diagonal."""
+    x = _points(x)
+    n, d = x.shape
+    zz = x if z is None else _points(z)
+    m = zz.shape[0]
+    K = np.empty((m, n), dtype=np.float64, order="F")
+    rc = lib().oracle_kernel_matrix(n, d, _ptr(x), max(n, 1), m, _ptr(zz), max(m, 1),
+                                    int(two_nu), FORMS[form], float(ell), float(s2),
+                                    float(sigma2), 1 if z is None else 0, _ptr(K), max(m, 1))
+    if rc != 0:
+        raise ValueError("oracle_kernel_matrix rejected its arguments")
+    return K
+
+
+def cholesky(a: np.ndarray) -> np.ndarray:
+    """Lower Cholesky factor of a symmetric positive definite matrix."""
+    L = np.array(a, dtype=np.float64, order="F", copy=True)
+    n = L.shape[0]
+    rc = lib().oracle_cholesky(n, _ptr(L), max(n, 1))
+    if rc != 0:
+        raise NotPositiveDefinite("non-positive pivot at column %d" % (rc - 1))
+    return np.tril(L)
+
+
+def cholesky_solve(L: np.ndarray, b) -> np.ndarray:
+    """Solve L L^T x = b by forward then back substitution."""
+    L = np.asfortranarray(L, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    vec = b.ndim == 1
+    B = np.array(b[:, None] if vec else b, dtype=np.float64, order="F", copy=True)
+    n, nrhs = B.shape
+    lib().oracle_cholesky_solve(n, _ptr(L), max(n, 1), _ptr(B), max(n, 1), nrhs)
+    return B[:, 0] if vec else B
+
+
+def gp_solve(x, y, two_nu: int, form, ell: float, s2: float, sigma2: float) -> np.ndarray:
+    """Direct alpha = (K + sigma^2 I)^{-1} y (eq. gp_mean_system) by Cholesky."""
+    A = kernel_matrix(x, two_nu, form, ell, s2, sigma2=sigma2)
+    return cholesky_solve(cholesky(A), y)
+
+
+def design_matrix(x) -> np.ndarray:
+    """Affine fixed-effects basis H = [1, x_1, ..., x_d] (eq. BetaLin; Section 3.2)."""
+    x = _points(x)
+    return np.column_stack([np.ones(x.shape[0]), x])
+
+
+def gls(x, y, two_nu: int, form, ell: float, s2: float, sigma2: float):
+    """Generalised least squares fixed effects (Section 3.2, beta_GLS).
+
+    beta = (H^T A^{-1} H)^{-1} H^T A^{-1} y with A = K + sigma^2 I, then the
+    centred solve alpha = A^{-1} (y - H beta) (the translation of Section 1).
+    Returns (beta, alpha).
+    """
+    H = design_matrix(x)
+    A = kernel_matrix(x, two_nu, form, ell, s2, sigma2=sigma2)
+    L = cholesky(A)
+    AiH = cholesky_solve(L, H)
+    Aiy = cholesky_solve(L, np.asarray(y, dtype=np.float64))
+    G = H.T @ AiH
+    beta = np.linalg.solve(G, H.T @ Aiy)
+    alpha = Aiy - AiH @ beta
+    return beta, alpha
+
+
+def ols(x, y) -> np.ndarray:
+    """Ordinary least squares beta = (H^T H)^{-1} H^T y (Algorithm 1, first step)."""
+    H = design_matrix(x)
+    return np.linalg.solve(H.T @ H, H.T @ np.asarray(y, dtype=np.float64))
+
+
+def predict(x, alpha, z, two_nu: int, form, ell: float, s2: float, beta=None) -> np.ndarray:
+    """Posterior mean k_z^T alpha + h(z)^T beta (eq. gp_mean, eq. gp_mean_2)."""
+    mean = mvm(x, alpha, two_nu, form, ell, s2, z=z)
+    if beta is not None:
+        mean = mean + design_matrix(z) @ np.asarray(beta, dtype=np.float64)
+    return mean
