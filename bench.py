@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Benchmark of the exact Matern kernel product and the GP solve built on it.
+
+Workload: d = 2, N = 100,000, nu = 3/2, product form, lengthscale 0.1,
+x ~ U[0,1]^2, y = sin(2 pi x1) cos(2 pi x2) + N(0, 0.1^2), sigma^2 = 0.01
+(synthetic, seeded).
+
+One step is one pass of the whole hot path with the inputs already in HBM:
+  plan build (sort, stored divide-and-conquer orders)  ->  one plain product
+  y = K v  ->  conjugate-gradient solve of (K + sigma^2 I) with the linear
+  fixed effects [1, x1, x2] (GLS), relative residual 1e-8  ->  posterior mean
+  at 1000 new points.
+`value` is the number of product point-columns (N x right-hand sides, summed
+over every product of the step) per second of step wall time.
+
+Also printed in the same JSON line:
+  roofline      the divide-and-conquer sweep kernel: algorithmic bytes per
+                launch (N x (4 + 16 x columns), one pass) over its average
+                duration, measured with HIP events on its stream during the
+                timed steps, against the 8 TB/s HBM peak;
+  mvm           the plain product alone at 1, 8 and 32 right-hand sides;
+  cpu_baseline  the dense FP64 CPU oracle timed on a bounded sample of target
+                rows of the same product (all host cores).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N = 100_000
+D = 2
+TWO_NU = 3
+ELL = 0.1
+SIGMA2 = 0.01
+RTOL = 1e-8
+NPREDICT = 1000
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def b_pass(n: int, cols: int) -> float:
+    """Algorithmic bytes of one divide-and-conquer pass: 4-byte order index plus,
+    per column, an 8-byte weight read and an 8-byte partial-sum write per point."""
+    return float(n) * (4.0 + 16.0 * cols)
+
+
+def cpu_baseline(x, v, seconds: float):
+    import oracle
+    oracle.build(force=False)
+    rows = 200
+    t0 = time.perf_counter()
+    oracle.mvm(x, v, TWO_NU, "product", ELL, z=x[:rows])
+    dt = time.perf_counter() - t0
+    rows = int(min(N, max(rows, rows * seconds / max(dt, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.mvm(x, v, TWO_NU, "product", ELL, z=x[:rows])
+    dt = time.perf_counter() - t0
+    return {"value": rows / dt, "unit": "points/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "dense FP64 product K v for %d of the %d target rows (nrhs=1, %.1f s), "
+                      "points/s = rows / time" % (rows, N, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mvm-reps", type=int, default=30)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mvm", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2508_01864_amd as mm
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p = workloads.config2()
+    rng = np.random.default_rng(20021)
+    z_np = rng.uniform(0.0, 1.0, size=(NPREDICT, D))
+    x = torch.as_tensor(p.x, device=dev)
+    y = torch.as_tensor(p.y, device=dev)
+    v = torch.as_tensor(p.v, device=dev)
+    z = torch.as_tensor(z_np, device=dev)
+    kern = mm.Kernel(TWO_NU, "product", ELL, 1.0)
+    L = mm.levels(N)
+
+    def step(profile: bool):
+        plan = mm.Plan(x, kern)
+        if profile:
+            plan.profile_enable(True)
+        y1 = plan.mvm(v)
+        alpha, beta, info = plan.cg_solve(y, SIGMA2, fixed_effects=True, rtol=RTOL, maxit=20000)
+        mean = plan.predict(alpha, z, beta=beta)
+        prof = plan.profile_read() if profile else (0.0, 0)
+        plan.close()
+        cols = 1 + 4 * info["iters"]        # plain product + CG columns (y, 1, x1, x2)
+        pts = N * cols + (N + NPREDICT)      # + predict on the union of points
+        sweep_bytes = L * (b_pass(N, 1) + info["iters"] * b_pass(N, 4))
+        return pts, info, prof, sweep_bytes, (y1, alpha, beta, mean)
+
+    for w in range(args.warmup):
+        log("warmup step %d" % w)
+        step(False)
+    torch.cuda.synchronize()
+
+    log("timed steps: %d" % args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot_pts = 0
+    tot_ms = 0.0
+    tot_launch = 0
+    tot_bytes = 0.0
+    iters = []
+    last = None
+    for s in range(args.steps):
+        pts, info, prof, sb, last = step(True)
+        tot_pts += pts
+        tot_ms += prof[0]
+        tot_launch += prof[1]
+        tot_bytes += sb
+        iters.append(info["iters"])
+        log("step %d: CG iters %d relres %.2e" % (s, info["iters"], info["relres_max"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = tot_pts / elapsed
+    avg_launch_ms = tot_ms / max(tot_launch, 1)
+    achieved = (tot_bytes / max(tot_launch, 1)) / (avg_launch_ms * 1e-3) / 1e9 if tot_launch else 0.0
+
+    # true residual of the last solve: ||y - H beta - (K + s I) alpha|| / ||y||
+    _, alpha, beta, _ = last
+    plan = mm.Plan(x, kern)
+    Ka = plan.mvm(alpha, shift=SIGMA2)
+    H = torch.cat([torch.ones(N, 1, dtype=torch.float64, device=dev), x], dim=1)
+    bt = torch.as_tensor(beta, device=dev)
+    true_res = float(torch.linalg.norm(y - H @ bt - Ka) / torch.linalg.norm(y))
+
+    mvm_rows = {}
+    if not args.no_mvm:
+        for nrhs in (1, 8, 32):
+            vv = torch.as_tensor(np.random.default_rng(7 + nrhs).standard_normal((nrhs, N)), device=dev)
+            yy = torch.empty_like(vv)
+            for _ in range(3):
+                plan.mvm_raw(vv, yy, nrhs)
+            plan.profile_enable(True)
+            plan.profile_read(reset=True)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.mvm_reps):
+                plan.mvm_raw(vv, yy, nrhs)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.mvm_reps
+            sms, scnt = plan.profile_read(reset=True)
+            plan.profile_enable(False)
+            sweep_ms = sms / max(scnt, 1) * L
+            mvm_rows[str(nrhs)] = {
+                "ms": round(ms, 4), "points_per_s": N * nrhs / (ms * 1e-3),
+                "sweep_ms": round(sweep_ms, 4),
+                "sweep_gbs": L * b_pass(N, nrhs) / (sweep_ms * 1e-3) / 1e9,
+            }
+            log("mvm nrhs=%d: %.3f ms (%.3e points/s)" % (nrhs, ms, N * nrhs / (ms * 1e-3)))
+    plan.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(p.x, p.v, args.cpu_seconds)
+
+    out = {
+        "metric": "Matern MVM points/s (N x nrhs) d=2 N=100k nu=3/2",
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "d=2 N=100000 nu=3/2 product ell=0.1 sigma2=0.01: plan build, "
+                               "K v, CG+GLS to 1e-8, predict 1000 points",
+                   "n": N, "d": D, "two_nu": TWO_NU, "form": "product", "lengthscale": ELL,
+                   "sigma2": SIGMA2, "rtol": RTOL, "npredict": NPREDICT},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "sweep_kernel (one divide-and-conquer pass)",
+                     "avg_launch_ms": avg_launch_ms, "launches": tot_launch},
+        "cpu_baseline": cpu,
+        "cg_iters": iters,
+        "true_relres": true_res,
+        "mvm": mvm_rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

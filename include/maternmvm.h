@@ -1,0 +1,208 @@
+/*
+ * maternmvm.h - C ABI of the exact fast Matern kernel matrix-vector product
+ * on AMD Instinct MI355X (gfx950), with the conjugate-gradient GP solve, the
+ * linear fixed-effects (GLS) estimate and the posterior-mean predictor built
+ * on it.
+ *
+ * Method (Langrene, Warin, Gruet et al., "Fast Gaussian process inference by
+ * exact Matern kernel decomposition", arXiv 2508.01864):
+ *   - the kernel sum  y_j = sum_i K(x_j, x_i) v_i  (Section 2, eq. Ky / kde)
+ *     is split over the 2^d sign orthants into weighted empirical CDFs
+ *     (eq. ECDFdelta; Proposition 1 for the L1 kernel, eq. L1_decomposition;
+ *     Proposition 2 for the product kernel, eq. product_decomposition),
+ *   - those CDFs are evaluated for every point at once by sorting (d = 1,
+ *     Section 2.1, fast sum updating) or by divide and conquer on presorted
+ *     coordinates (d >= 2, Section 2.2; the sorted subsets are computed once
+ *     and stored, then reused by every product).
+ * The result is exact up to floating-point rounding; it is not an
+ * approximation.
+ *
+ * Conventions common to every call
+ *   - All arithmetic is IEEE binary64.
+ *   - Pointers documented as "device" must point to memory of the device that
+ *     was current when the plan was created; "host" pointers are ordinary CPU
+ *     memory.  The library never frees caller memory.
+ *   - Matrices are column-major: element (i, c) of an n x k array with leading
+ *     dimension ld is at index c*ld + i.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue work on it and return without waiting, unless the
+ *     description says "synchronises".
+ *   - Every call returns an mm_status.  On error the outputs are unspecified,
+ *     no caller memory is freed, and mm_last_error() returns a message for the
+ *     calling thread.
+ *   - Point indices in inputs and outputs are the caller's order.
+ *   - A plan must not be used from two streams at the same time.
+ */
+#ifndef MATERNMVM_H
+#define MATERNMVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mm_plan_s *mm_plan;
+
+typedef enum {
+    MM_OK = 0,
+    MM_ERR_ARG = 1,        /* invalid argument (size, pointer, NaN, unsupported nu/d/form) */
+    MM_ERR_NOMEM = 2,      /* device allocation failed */
+    MM_ERR_HIP = 3,        /* a HIP runtime call failed */
+    MM_ERR_NOTPD = 4,      /* solve requested with a kernel form that is not positive definite */
+    MM_ERR_BREAKDOWN = 5,  /* conjugate gradients met p^T A p <= 0 */
+    MM_ERR_NOCONV = 6      /* conjugate gradients hit maxit before the tolerance */
+} mm_status;
+
+/* Multivariate kernel form (Section 2.2): L1 form k(||u||_1) (eq. L1_kernel)
+ * or product form prod_k k(|u_k|) (eq. product_kernel).  They coincide for
+ * nu = 1/2 (remark after eq. matern_l1_12) and for d = 1. */
+typedef enum { MM_FORM_L1 = 0, MM_FORM_PRODUCT = 1 } mm_form;
+
+/* Scaled Matern kernel  outputscale2 * k_nu(r / lengthscale)  (eq. scaled_kernel,
+ * Appendix C eq. matern_1_2 / matern_3_2 / matern_5_2) with nu = two_nu / 2.
+ *   two_nu        1, 3 or 5
+ *   form          MM_FORM_L1 or MM_FORM_PRODUCT
+ *   lengthscale   ell > 0, finite
+ *   outputscale2  varsigma^2 > 0, finite                                      */
+typedef struct {
+    int32_t two_nu;
+    int32_t form;
+    double lengthscale;
+    double outputscale2;
+} mm_kernel;
+
+/* Outcome of a conjugate-gradient solve. */
+typedef struct {
+    int32_t iters;           /* iterations performed (matrix-vector products of the loop) */
+    int32_t converged_cols;  /* columns whose relative residual reached rtol */
+    double relres_max;       /* max over columns of ||r_c|| / ||b_c|| at exit (recurrence) */
+} mm_solve_info;
+
+/* Library version string. */
+const char *mm_version(void);
+
+/* Human-readable name of a status code. */
+const char *mm_status_str(mm_status st);
+
+/* Detail message of the last error raised on the calling thread ("" if none). */
+const char *mm_last_error(void);
+
+/*
+ * Upper bound of the device memory a plan for n points in dimension d needs,
+ * including work buffers for products with up to nrhs right-hand sides.  Host
+ * only; intended for admission control.  Returns 0 for invalid arguments.
+ */
+size_t mm_plan_footprint_bytes(int64_t n, int32_t d, int32_t nrhs, const mm_kernel *kernel);
+
+/*
+ * Build the stored sorting outputs for a point set (Section 2.2: the sorted
+ * subsets for each coordinate are computed once and reused by every product).
+ *   x       device, n x d column-major with leading dimension ldx >= n
+ *   n       number of points, 1 <= n <= 2^30
+ *   d       dimension, 1, 2 or 3
+ *   kernel  host, the kernel (validated, copied)
+ *   stream  stream for the build kernels
+ *   out     host, receives the plan handle
+ * The plan keeps its own copy of the (reordered) coordinates, so x may be
+ * freed once the call's work on `stream` has completed.  Fails with
+ * MM_ERR_ARG if any coordinate is NaN or infinite (synchronises to check).
+ */
+mm_status mm_plan_create(const double *x, int64_t n, int32_t d, int64_t ldx,
+                         const mm_kernel *kernel, void *stream, mm_plan *out);
+
+/* Replace the kernel (nu, form, lengthscale, outputscale) of a plan; the
+ * stored sorting outputs are kept. */
+mm_status mm_plan_set_kernel(mm_plan plan, const mm_kernel *kernel);
+
+/* Point count and dimension of a plan (host). */
+mm_status mm_plan_info(mm_plan plan, int64_t *n, int32_t *d, mm_kernel *kernel);
+
+/* Release a plan and every device buffer it owns (synchronises the device
+ * with the plan's last stream).  NULL is accepted. */
+mm_status mm_plan_destroy(mm_plan plan);
+
+/*
+ * Exact kernel matrix-vector product with nrhs right-hand sides
+ * (Section 2, eq. Ky, evaluated by Prop. 1 or Prop. 2):
+ *     y = (K + diag_shift * I) v
+ * where K_ij = outputscale2 * k_nu(dist(x_i, x_j) / lengthscale).
+ *   v      device, n x nrhs column-major, leading dimension ldv >= n
+ *   y      device, n x nrhs column-major, leading dimension ldy >= n;
+ *          must not overlap v
+ *   nrhs   1 <= nrhs <= 256
+ *   diag_shift  added times v (e.g. the noise variance sigma^2); may be 0
+ */
+mm_status matern_mvm(mm_plan plan, const double *v, int64_t ldv, double *y, int64_t ldy,
+                     int32_t nrhs, double diag_shift, void *stream);
+
+/*
+ * Gaussian-process solve by conjugate gradients (Appendix A, Algorithm 2 with
+ * the identity preconditioner and a null initial guess), each iteration one
+ * product of the fast MVM:
+ *     alpha = (K + sigma2 I)^{-1} (y - H beta)
+ * With fixed_effects != 0 the mean is affine, m(x) = beta_0 + beta^T x
+ * (eq. BetaLin), H = [1, x_1, ..., x_d], and beta is the generalised least
+ * squares estimate of Section 3.2,
+ *     beta = (H^T A^{-1} H)^{-1} H^T A^{-1} y,   A = K + sigma2 I,
+ * obtained from one multi-column CG over [y, H]; otherwise beta = 0.
+ *   y        device, n targets (caller order)
+ *   sigma2   noise variance > 0
+ *   rtol     per-column stop test ||r_c|| <= rtol ||b_c|| on the recurrence residual
+ *   maxit    iteration limit >= 1
+ *   alpha    device, n outputs (caller order)
+ *   beta     host, d+1 outputs, or NULL when fixed_effects == 0
+ *   info     host, may be NULL
+ * The L1 form with nu >= 3/2 and d >= 2 is not positive definite and is
+ * refused with MM_ERR_NOTPD (the product form is; Appendix B).  Returns
+ * MM_ERR_NOCONV after maxit iterations and MM_ERR_BREAKDOWN on a non-positive
+ * curvature p^T A p; both still write the last iterate and info.
+ * Synchronises.
+ */
+mm_status gp_cg_solve(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects,
+                      double rtol, int32_t maxit, double *alpha, double *beta,
+                      mm_solve_info *info, void *stream);
+
+/*
+ * Multi-column conjugate gradients (Appendix A, Algorithm 2, identity
+ * preconditioner, null initial guess): X = (K + sigma2 I)^{-1} B.
+ *   B     device, n x nrhs column-major, leading dimension ldb >= n
+ *   X     device, n x nrhs column-major, leading dimension ldx >= n
+ *   nrhs  1 <= nrhs <= 64
+ * Columns are stopped independently (||r_c|| <= rtol ||b_c||).
+ * Same status rules and synchronisation as gp_cg_solve.
+ */
+mm_status gp_cg_solve_multi(mm_plan plan, const double *B, int64_t ldb, int32_t nrhs,
+                            double sigma2, double rtol, int32_t maxit, double *X, int64_t ldx,
+                            mm_solve_info *info, void *stream);
+
+/*
+ * Posterior mean at m new points (eq. gp_mean, eq. gp_mean_2):
+ *     mean(z) = sum_i alpha_i K(z, x_i) + h(z)^T beta,  h(z) = [1, z_1..z_d]
+ * computed exactly by the same decomposition on the union of the training
+ * and prediction points with zero weights on the latter.
+ *   alpha  device, n weights (caller order of the plan's points)
+ *   beta   host, d+1 coefficients, or NULL for a zero mean function
+ *   z      device, m x d column-major, leading dimension ldz >= m
+ *   mean   device, m outputs
+ * Synchronises (it builds and releases a temporary plan).
+ */
+mm_status gp_predict(mm_plan plan, const double *alpha, const double *beta, const double *z,
+                     int64_t m, int64_t ldz, double *mean, void *stream);
+
+/*
+ * Kernel-time accounting for measurement: when enabled, every divide-and-
+ * conquer sweep launch of this plan is bracketed by HIP events on its stream
+ * and mm_plan_profile_read() returns the summed elapsed milliseconds and the
+ * number of bracketed launches since the last reset (synchronises).
+ */
+mm_status mm_plan_profile_enable(mm_plan plan, int32_t enable);
+mm_status mm_plan_profile_read(mm_plan plan, double *sweep_ms, int64_t *sweep_launches,
+                               int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MATERNMVM_H */

@@ -1,0 +1,302 @@
+"""Exact fast Matern kernel products on AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding of ``libmaternmvm.so`` (C ABI in ``include/maternmvm.h``).
+It only marshals arguments: every step of the product, the solve and the
+prediction runs in the library's HIP kernels.  PyTorch supplies device memory
+and the current stream.  Importing works without a GPU; using a plan needs the
+built library and a GPU, and fails loudly otherwise.
+
+    >>> import torch, paper_2508_01864_amd as mm
+    >>> x = torch.rand(100_000, 2, dtype=torch.float64, device="cuda")
+    >>> plan = mm.Plan(x, mm.Kernel(two_nu=3, form="product", lengthscale=0.1))
+    >>> y = plan.mvm(torch.randn(100_000, dtype=torch.float64, device="cuda"))
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmaternmvm.so")
+
+MM_OK = 0
+MM_ERR_ARG = 1
+MM_ERR_NOMEM = 2
+MM_ERR_HIP = 3
+MM_ERR_NOTPD = 4
+MM_ERR_BREAKDOWN = 5
+MM_ERR_NOCONV = 6
+STATUS_NAMES = {0: "MM_OK", 1: "MM_ERR_ARG", 2: "MM_ERR_NOMEM", 3: "MM_ERR_HIP",
+                4: "MM_ERR_NOTPD", 5: "MM_ERR_BREAKDOWN", 6: "MM_ERR_NOCONV"}
+
+FORM_L1 = 0
+FORM_PRODUCT = 1
+_FORMS = {"l1": FORM_L1, "product": FORM_PRODUCT, FORM_L1: FORM_L1, FORM_PRODUCT: FORM_PRODUCT}
+
+
+class MaternError(RuntimeError):
+    """A library call returned a non-OK status."""
+
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), message))
+        self.status = status
+
+
+class _MMKernel(ctypes.Structure):
+    _fields_ = [("two_nu", ctypes.c_int32), ("form", ctypes.c_int32),
+                ("lengthscale", ctypes.c_double), ("outputscale2", ctypes.c_double)]
+
+
+class _MMSolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged_cols", ctypes.c_int32),
+                ("relres_max", ctypes.c_double)]
+
+
+# name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_SIGS = {
+    "mm_version": (ctypes.c_char_p, []),
+    "mm_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "mm_last_error": (ctypes.c_char_p, []),
+    "mm_plan_footprint_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.POINTER(_MMKernel)]),
+    "mm_plan_create": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                      ctypes.POINTER(_MMKernel), _P, ctypes.POINTER(_P)]),
+    "mm_plan_set_kernel": (ctypes.c_int, [_P, ctypes.POINTER(_MMKernel)]),
+    "mm_plan_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(_MMKernel)]),
+    "mm_plan_destroy": (ctypes.c_int, [_P]),
+    "matern_mvm": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int32,
+                                  ctypes.c_double, _P]),
+    "gp_cg_solve": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                   ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(_MMSolveInfo), _P]),
+    "gp_cg_solve_multi": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int32, _P, ctypes.c_int64,
+                                         ctypes.POINTER(_MMSolveInfo), _P]),
+    "gp_predict": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double), _P, ctypes.c_int64,
+                                  ctypes.c_int64, _P, _P]),
+    "mm_plan_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "mm_plan_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmaternmvm.so is not built (run __graft_entry__.build() or "
+                               "python -m paper_2508_01864_amd.build); there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def version() -> str:
+    return lib().mm_version().decode()
+
+
+def last_error() -> str:
+    return lib().mm_last_error().decode()
+
+
+def _check(st: int):
+    if st != MM_OK:
+        raise MaternError(st, last_error())
+
+
+@dataclass
+class Kernel:
+    """Scaled Matern kernel outputscale2 * k_nu(r / lengthscale), nu = two_nu / 2."""
+    two_nu: int = 3
+    form: str = "product"
+    lengthscale: float = 0.1
+    outputscale2: float = 1.0
+
+    def c(self) -> _MMKernel:
+        return _MMKernel(int(self.two_nu), _FORMS[self.form], float(self.lengthscale),
+                         float(self.outputscale2))
+
+
+def footprint_bytes(n: int, d: int, nrhs: int, kernel: Kernel) -> int:
+    """Upper bound of a plan's device memory (host-only; 0 for invalid arguments)."""
+    k = kernel.c()
+    return int(lib().mm_plan_footprint_bytes(int(n), int(d), int(nrhs), ctypes.byref(k)))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(int(s.cuda_stream))
+
+
+def _colmajor(t, n: int):
+    """(n,) or (n, k) float64 CUDA tensor -> contiguous (k, n) tensor (column-major n x k)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA tensor")
+    if t.dtype != torch.float64:
+        raise TypeError("expected float64")
+    if t.shape[0] != n:
+        raise ValueError("leading dimension must be %d (got %d)" % (n, t.shape[0]))
+    if t.dim() == 1:
+        return t.contiguous().view(1, n)
+    return t.t().contiguous()
+
+
+class Plan:
+    """Stored sorting outputs of a point set plus the kernel (mm_plan)."""
+
+    def __init__(self, x, kernel: Kernel, stream=None):
+        torch = _torch()
+        if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float64:
+            raise TypeError("x must be a float64 CUDA tensor of shape (n, d)")
+        if x.dim() == 1:
+            x = x.view(-1, 1)
+        self.n, self.d = int(x.shape[0]), int(x.shape[1])
+        self.kernel = kernel
+        self._x = x.t().contiguous()      # column-major n x d, ldx = n
+        self._h = ctypes.c_void_p()
+        k = kernel.c()
+        self._stream = stream
+        _check(lib().mm_plan_create(ctypes.c_void_p(self._x.data_ptr()), self.n, self.d, self.n,
+                                    ctypes.byref(k), _stream_ptr(stream), ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mm_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_kernel(self, kernel: Kernel):
+        k = kernel.c()
+        _check(lib().mm_plan_set_kernel(self._h, ctypes.byref(k)))
+        self.kernel = kernel
+
+    def mvm(self, v, shift: float = 0.0, out=None):
+        """y = (K + shift I) v for v of shape (n,) or (n, nrhs)."""
+        torch = _torch()
+        vc = _colmajor(v, self.n)
+        nrhs = vc.shape[0]
+        yc = out if out is not None else torch.empty_like(vc)
+        _check(lib().matern_mvm(self._h, ctypes.c_void_p(vc.data_ptr()), self.n,
+                                ctypes.c_void_p(yc.data_ptr()), self.n, nrhs, float(shift),
+                                _stream_ptr(self._stream)))
+        return yc.view(-1) if v.dim() == 1 else yc.t()
+
+    def mvm_raw(self, vc, yc, nrhs: int, shift: float = 0.0):
+        """Product on preallocated column-major buffers (no copies): vc, yc of shape (nrhs, n)."""
+        _check(lib().matern_mvm(self._h, ctypes.c_void_p(vc.data_ptr()), self.n,
+                                ctypes.c_void_p(yc.data_ptr()), self.n, int(nrhs), float(shift),
+                                _stream_ptr(self._stream)))
+
+    def cg_solve(self, y, sigma2: float, fixed_effects: bool = False, rtol: float = 1e-8,
+                 maxit: int = 20000, raise_on_error: bool = True):
+        """alpha = (K + sigma2 I)^{-1} (y - H beta) with the GLS beta when fixed_effects.
+        Returns (alpha, beta or None, info dict with iters / converged_cols / relres_max / status)."""
+        torch = _torch()
+        yc = _colmajor(y, self.n).view(-1)
+        alpha = torch.empty_like(yc)
+        beta = (ctypes.c_double * (self.d + 1))()
+        info = _MMSolveInfo()
+        st = lib().gp_cg_solve(self._h, ctypes.c_void_p(yc.data_ptr()), float(sigma2),
+                               1 if fixed_effects else 0, float(rtol), int(maxit),
+                               ctypes.c_void_p(alpha.data_ptr()),
+                               beta if fixed_effects else None, ctypes.byref(info),
+                               _stream_ptr(self._stream))
+        msg = last_error()
+        if st != MM_OK and raise_on_error:
+            raise MaternError(st, msg)
+        out = {"iters": info.iters, "converged_cols": info.converged_cols,
+               "relres_max": info.relres_max, "status": STATUS_NAMES[st]}
+        return alpha, (np.array(beta[:]) if fixed_effects else None), out
+
+    def cg_solve_multi(self, B, sigma2: float, rtol: float = 1e-8, maxit: int = 20000,
+                       raise_on_error: bool = True):
+        """X = (K + sigma2 I)^{-1} B for B of shape (n, k)."""
+        torch = _torch()
+        Bc = _colmajor(B, self.n)
+        k = Bc.shape[0]
+        Xc = torch.empty_like(Bc)
+        info = _MMSolveInfo()
+        st = lib().gp_cg_solve_multi(self._h, ctypes.c_void_p(Bc.data_ptr()), self.n, k,
+                                     float(sigma2), float(rtol), int(maxit),
+                                     ctypes.c_void_p(Xc.data_ptr()), self.n, ctypes.byref(info),
+                                     _stream_ptr(self._stream))
+        msg = last_error()
+        if st != MM_OK and raise_on_error:
+            raise MaternError(st, msg)
+        out = {"iters": info.iters, "converged_cols": info.converged_cols,
+               "relres_max": info.relres_max, "status": STATUS_NAMES[st]}
+        return (Xc.view(-1) if B.dim() == 1 else Xc.t()), out
+
+    def predict(self, alpha, z, beta=None):
+        """Posterior mean sum_i alpha_i K(z, x_i) + h(z)^T beta at z of shape (m, d)."""
+        torch = _torch()
+        ac = _colmajor(alpha, self.n).view(-1)
+        if z.dim() == 1:
+            z = z.view(-1, 1)
+        m = int(z.shape[0])
+        zc = z.t().contiguous()
+        mean = torch.empty(m, dtype=torch.float64, device=z.device)
+        bp = None
+        if beta is not None:
+            bb = np.asarray(beta, dtype=np.float64)
+            bp = (ctypes.c_double * len(bb))(*bb.tolist())
+        _check(lib().gp_predict(self._h, ctypes.c_void_p(ac.data_ptr()), bp,
+                                ctypes.c_void_p(zc.data_ptr()), m, m,
+                                ctypes.c_void_p(mean.data_ptr()), _stream_ptr(self._stream)))
+        return mean
+
+    def profile_enable(self, on: bool = True):
+        _check(lib().mm_plan_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self, reset: bool = True):
+        """(summed milliseconds, number) of the bracketed sweep launches."""
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _check(lib().mm_plan_profile_read(self._h, ctypes.byref(ms), ctypes.byref(cnt),
+                                          1 if reset else 0))
+        return ms.value, cnt.value
+
+
+def levels(n: int) -> int:
+    """ceil(log2 n): number of divide-and-conquer levels of a point set of size n."""
+    L = 0
+    while (1 << L) < n:
+        L += 1
+    return L
+
+
+def passes(n: int, d: int) -> int:
+    """Number of divide-and-conquer passes: 1 (d=1), L (d=2), L(L+1)/2 (d=3)."""
+    if n < 2:
+        return 0
+    L = levels(n)
+    return 1 if d == 1 else (L if d == 2 else L * (L + 1) // 2)

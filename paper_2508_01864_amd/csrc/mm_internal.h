@@ -1,0 +1,132 @@
+// Internal declarations shared by the HIP sources of libmaternmvm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/maternmvm.h"
+
+namespace mm {
+
+// ---------------------------------------------------------------------------
+// Error reporting (thread-local message returned by mm_last_error()).
+// ---------------------------------------------------------------------------
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define MM_HIP_TRY(expr)                                                        \
+    do {                                                                        \
+        hipError_t e_ = (expr);                                                 \
+        if (e_ != hipSuccess) {                                                 \
+            ::mm::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                            __FILE__, __LINE__);                                \
+            return (e_ == hipErrorOutOfMemory) ? MM_ERR_NOMEM : MM_ERR_HIP;     \
+        }                                                                       \
+    } while (0)
+
+#define MM_TRY(expr)                 \
+    do {                             \
+        mm_status s_ = (expr);       \
+        if (s_ != MM_OK) return s_;  \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Device buffers owned by a plan.
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+mm_status dev_alloc(DevBuf &b, size_t bytes);
+mm_status dev_reserve(DevBuf &b, size_t bytes);  // grow-only
+void dev_free(DevBuf &b);
+
+// ---------------------------------------------------------------------------
+// One divide-and-conquer pass: a segmented bidirectional scan over a stored
+// order of the points.
+//   d = 1: the single pass scans the canonical (x1-sorted) order.
+//   d = 2: level l; ord lists canonical indices, segments of 2^(l+1)
+//          positions (the x1-rank nodes), each sorted by x2.
+//   d = 3: level pair (l1, l2); ord lists positions q of the level-l1
+//          (x1, x2) order ord2, segments of 2^(l2+1) positions, sorted by x3.
+// ---------------------------------------------------------------------------
+struct Pass {
+    const int32_t *ord = nullptr;   // position -> canonical index (d=2) or q (d=3)
+    const int32_t *ord2 = nullptr;  // d=3: q -> canonical index of level l1
+    int l1 = -1;
+    int l2 = -1;
+    int seg_log2 = 0;               // segment size 2^seg_log2 positions
+};
+
+// Kernel constants derived from mm_kernel.
+struct KParams {
+    int P = 1;        // number of separable terms (nu + 1/2)
+    bool prod = true; // product form (also used for d = 1 and nu = 1/2)
+    double a = 1.0;   // sqrt(2 nu) / lengthscale
+    double s2 = 1.0;  // outputscale^2
+};
+
+KParams kparams(const mm_kernel &k, int d);
+
+}  // namespace mm
+
+// ---------------------------------------------------------------------------
+// The plan object behind mm_plan.
+// ---------------------------------------------------------------------------
+struct mm_plan_s {
+    int device = 0;
+    int64_t n = 0;
+    int d = 1;
+    int L = 0;                    // ceil(log2 n) divide-and-conquer levels
+    mm_kernel kernel{};
+    hipStream_t last_stream = nullptr;
+
+    mm::DevBuf xc;                // d x n canonical coordinates (SoA, x1-rank order)
+    mm::DevBuf perm;              // n int32: canonical index -> caller index
+    mm::DevBuf structure;         // all stored orders (int32)
+    std::vector<mm::Pass> passes;
+
+    // product work buffers (grow on demand)
+    mm::DevBuf vin;               // n x W point-major canonical input
+    mm::DevBuf yacc;              // n x W point-major canonical accumulator
+    mm::DevBuf agg;               // tile aggregates and carries
+    int64_t work_cols = 0;
+
+    // CG work buffers
+    mm::DevBuf cgbuf;
+    mm::DevBuf redbuf;
+
+    // measurement
+    bool profile = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+    size_t prof_used = 0;
+    double prof_ms = 0.0;
+    int64_t prof_launches = 0;
+};
+
+namespace mm {
+
+// sweep.hip
+mm_status profile_flush(mm_plan p, double *ms, int64_t *launches);
+mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int R, hipStream_t s);
+int rhs_block(const mm_kernel &k, int d, int nrhs);
+size_t sweep_agg_bytes(int64_t n, int d, int W, const mm_kernel &k);
+
+// mvm.hip helpers
+mm_status mvm_internal(mm_plan p, const double *vin, double *yout, int W, int nrhs,
+                       double shift, hipStream_t s);
+mm_status ensure_work(mm_plan p, int W);
+
+// permutation kernels
+void launch_gather_in(const double *v, int64_t ldv, int nrhs, const int32_t *perm, int64_t n,
+                      double *vin, int W, hipStream_t s);
+void launch_scatter_out(const double *vin, const double *yacc, int W, int nrhs,
+                        const int32_t *perm, int64_t n, double s2, double shift, double *y,
+                        int64_t ldy, hipStream_t s);
+
+}  // namespace mm
