@@ -14,10 +14,11 @@ One step is one pass of the whole hot path with the inputs already in HBM:
 over every product of the step) per second of step wall time.
 
 Also printed in the same JSON line:
-  roofline      the divide-and-conquer sweep kernel: algorithmic bytes per
-                launch (N x (4 + 16 x columns), one pass) over its average
-                duration, measured with HIP events on its stream during the
-                timed steps, against the 8 TB/s HBM peak;
+  roofline      the divide-and-conquer sweep kernel (one launch covers every
+                pass of a product): algorithmic bytes per launch
+                (passes x N x (4 + 16 x columns)) over its average duration,
+                measured with HIP events on its stream during the timed
+                steps, against the 8 TB/s HBM peak;
   mvm           the plain product alone at 1, 8 and 32 right-hand sides;
   cpu_baseline  the dense FP64 CPU oracle timed on a bounded sample of target
                 rows of the same product (all host cores).
@@ -111,7 +112,7 @@ def main():
         y1 = plan.mvm(v)
         alpha, beta, info = plan.cg_solve(y, SIGMA2, fixed_effects=True, rtol=RTOL, maxit=20000)
         mean = plan.predict(alpha, z, beta=beta)
-        prof = plan.profile_read() if profile else (0.0, 0)
+        prof = plan.profile_read() if profile else (0.0, 0, 0)
         plan.close()
         cols = 1 + 4 * info["iters"]        # plain product + CG columns (y, 1, x1, x2)
         pts = N * cols + (N + NPREDICT)      # + predict on the union of points
@@ -144,6 +145,8 @@ def main():
     elapsed = time.perf_counter() - t0
     value = tot_pts / elapsed
     avg_launch_ms = tot_ms / max(tot_launch, 1)
+    # algorithmic bytes per launch (total over the launches / their number) over the
+    # average launch duration
     achieved = (tot_bytes / max(tot_launch, 1)) / (avg_launch_ms * 1e-3) / 1e9 if tot_launch else 0.0
 
     # true residual of the last solve: ||y - H beta - (K + s I) alpha|| / ||y||
@@ -171,9 +174,9 @@ def main():
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / args.mvm_reps
-            sms, scnt = plan.profile_read(reset=True)
+            sms, scnt, _ = plan.profile_read(reset=True)
             plan.profile_enable(False)
-            sweep_ms = sms / max(scnt, 1) * L
+            sweep_ms = sms / max(scnt, 1)           # one launch covers all L passes
             mvm_rows[str(nrhs)] = {
                 "ms": round(ms, 4), "points_per_s": N * nrhs / (ms * 1e-3),
                 "sweep_ms": round(sweep_ms, 4),
@@ -206,7 +209,7 @@ def main():
                    "sigma2": SIGMA2, "rtol": RTOL, "npredict": NPREDICT},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "sweep_kernel (one divide-and-conquer pass)",
+                     "kernel": "sweep_kernel (all %d divide-and-conquer passes per launch)" % L,
                      "avg_launch_ms": avg_launch_ms, "launches": tot_launch},
         "cpu_baseline": cpu,
         "cg_iters": iters,

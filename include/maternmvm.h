@@ -192,14 +192,16 @@ mm_status gp_predict(mm_plan plan, const double *alpha, const double *beta, cons
                      int64_t m, int64_t ldz, double *mean, void *stream);
 
 /*
- * Kernel-time accounting for measurement: when enabled, every divide-and-
- * conquer sweep launch of this plan is bracketed by HIP events on its stream
- * and mm_plan_profile_read() returns the summed elapsed milliseconds and the
- * number of bracketed launches since the last reset (synchronises).
+ * Kernel-time accounting for measurement: when enabled, every launch of the
+ * divide-and-conquer sweep kernel of this plan (one launch covers a group of
+ * passes) is bracketed by HIP events on its stream.  mm_plan_profile_read()
+ * returns, since the last reset, the summed elapsed milliseconds, the number
+ * of bracketed launches and the number of passes they covered (any output
+ * pointer may be NULL; synchronises with the recorded events).
  */
 mm_status mm_plan_profile_enable(mm_plan plan, int32_t enable);
 mm_status mm_plan_profile_read(mm_plan plan, double *sweep_ms, int64_t *sweep_launches,
-                               int32_t reset);
+                               int64_t *sweep_passes, int32_t reset);
 
 #ifdef __cplusplus
 }

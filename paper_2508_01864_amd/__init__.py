@@ -82,6 +82,7 @@ _SIGS = {
                                   ctypes.c_int64, _P, _P]),
     "mm_plan_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "mm_plan_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_int64),
                                             ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
 }
 
@@ -278,12 +279,13 @@ class Plan:
         _check(lib().mm_plan_profile_enable(self._h, 1 if on else 0))
 
     def profile_read(self, reset: bool = True):
-        """(summed milliseconds, number) of the bracketed sweep launches."""
+        """(summed milliseconds, launches, passes covered) of the bracketed sweep launches."""
         ms = ctypes.c_double()
         cnt = ctypes.c_int64()
+        npass = ctypes.c_int64()
         _check(lib().mm_plan_profile_read(self._h, ctypes.byref(ms), ctypes.byref(cnt),
-                                          1 if reset else 0))
-        return ms.value, cnt.value
+                                          ctypes.byref(npass), 1 if reset else 0))
+        return ms.value, cnt.value, npass.value
 
 
 def levels(n: int) -> int:

@@ -335,14 +335,12 @@ mm_status ensure_work(mm_plan p, int W) {
     MM_TRY(dev_reserve(p->vin, vbytes));
     MM_TRY(dev_reserve(p->yacc, vbytes));
     MM_TRY(dev_reserve(p->agg, sweep_agg_bytes(p->n, p->d, W, p->kernel)));
+    MM_TRY(dev_reserve(p->part, sweep_part_bytes(p->n, (int)p->passes.size(), W)));
     return MM_OK;
 }
 
 // yacc <- sum over passes of the off-diagonal kernel sums of vin (unscaled)
 mm_status sweep_into(mm_plan p, const double *vin, double *yacc, int W, int R, hipStream_t s) {
-    hipLaunchKernelGGL(fill_kernel, dim3(grid1((int64_t)p->n * W)), dim3(BS), 0, s, yacc,
-                       (int64_t)p->n * W, 0.0);
-    MM_HIP_TRY(hipGetLastError());
     return sweep_all(p, vin, yacc, W, R, s);
 }
 
@@ -455,6 +453,9 @@ mm_status mm_plan_destroy(mm_plan plan) {
     dev_free(plan->vin);
     dev_free(plan->yacc);
     dev_free(plan->agg);
+    dev_free(plan->part);
+    dev_free(plan->pass_dev);
+    dev_free(plan->pass_xt);
     dev_free(plan->cgbuf);
     dev_free(plan->redbuf);
     for (auto &e : plan->prof_events) {
@@ -819,7 +820,8 @@ mm_status mm_plan_profile_enable(mm_plan plan, int32_t enable) {
     return MM_OK;
 }
 
-mm_status mm_plan_profile_read(mm_plan plan, double *sweep_ms, int64_t *sweep_launches, int32_t reset) {
+mm_status mm_plan_profile_read(mm_plan plan, double *sweep_ms, int64_t *sweep_launches,
+                               int64_t *sweep_passes, int32_t reset) {
     clear_error();
     if (!plan) {
         set_error("plan is NULL");
@@ -830,9 +832,11 @@ mm_status mm_plan_profile_read(mm_plan plan, double *sweep_ms, int64_t *sweep_la
     MM_TRY(profile_flush(plan, &ms, &cnt));
     if (sweep_ms) *sweep_ms = ms;
     if (sweep_launches) *sweep_launches = cnt;
+    if (sweep_passes) *sweep_passes = plan->prof_units;
     if (reset) {
         plan->prof_ms = 0.0;
         plan->prof_launches = 0;
+        plan->prof_units = 0;
     }
     return MM_OK;
 }

@@ -90,11 +90,15 @@ struct mm_plan_s {
     mm::DevBuf perm;              // n int32: canonical index -> caller index
     mm::DevBuf structure;         // all stored orders (int32)
     std::vector<mm::Pass> passes;
+    mm::DevBuf pass_dev;          // device table of the passes
+    mm::DevBuf pass_xt;           // indices of passes whose segments span tiles
+    std::vector<int> xt_host;
 
     // product work buffers (grow on demand)
     mm::DevBuf vin;               // n x W point-major canonical input
     mm::DevBuf yacc;              // n x W point-major canonical accumulator
-    mm::DevBuf agg;               // tile aggregates and carries
+    mm::DevBuf agg;               // tile aggregates and anchors
+    mm::DevBuf part;              // per-pass partial results of one pass group
     int64_t work_cols = 0;
 
     // CG work buffers
@@ -107,6 +111,7 @@ struct mm_plan_s {
     size_t prof_used = 0;
     double prof_ms = 0.0;
     int64_t prof_launches = 0;
+    int64_t prof_units = 0;       // passes covered by the bracketed launches
 };
 
 namespace mm {
@@ -116,6 +121,9 @@ mm_status profile_flush(mm_plan p, double *ms, int64_t *launches);
 mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int R, hipStream_t s);
 int rhs_block(const mm_kernel &k, int d, int nrhs);
 size_t sweep_agg_bytes(int64_t n, int d, int W, const mm_kernel &k);
+size_t sweep_part_bytes(int64_t n, int npass, int W);
+int group_passes(mm_plan p, int W);
+mm_status upload_pass_tables(mm_plan p);
 
 // mvm.hip helpers
 mm_status mvm_internal(mm_plan p, const double *vin, double *yout, int W, int nrhs,

@@ -442,6 +442,11 @@ size_t plan_footprint(int64_t n, int d, int nrhs, const mm_kernel &k) {
     size_t b = (size_t)d * n * 8 + (size_t)n * 4 + structure_ints(n, d) * 4;
     b += 2 * (size_t)n * W * 8;                       // product buffers
     b += sweep_agg_bytes(n, d, (int)W, k);
+    {
+        int L = ceil_log2(n);
+        const int npass = n < 2 ? 0 : (d == 1 ? 1 : (d == 2 ? L : L * (L + 1) / 2));
+        b += sweep_part_bytes(n, npass, (int)W);        // per-pass partial results
+    }
     b += (size_t)n * 8 * 8 * (size_t)(d + 2);          // CG vectors for the fixed-effects solve
     return b;
 }
@@ -571,6 +576,7 @@ mm_status plan_build(mm_plan p, const double *x, int64_t ldx, hipStream_t s) {
         set_error("HIP error while building the plan: %s", hipGetErrorString(e));
         return MM_ERR_HIP;
     }
+    MM_TRY(upload_pass_tables(p));
 #undef BUILD_TRY
     return MM_OK;
 }

@@ -82,23 +82,30 @@ constexpr int F_SEGSTART = 4;  // first position of a segment
 constexpr int F_SEGEND = 8;    // last position of a segment (or of the array)
 constexpr int F_VALID = 16;    // position < n
 
-// Kernel arguments for one pass.
+// One divide-and-conquer pass as the kernels see it (device table).
+struct PassDev {
+    const int32_t *ord;   // position -> canonical index (d = 2) or q (d = 3)
+    const int32_t *ord2;  // d = 3: q -> canonical index at level l1
+    int l1, l2;
+    int seg_log2;         // segments of 2^seg_log2 positions
+    int pad;
+};
+
+// Kernel arguments for one group of passes.
 struct SweepArgs {
     const double *xc;      // d x n canonical coordinates
-    const int32_t *ord;    // pass order
-    const int32_t *ord2;   // d = 3: level-l1 (x1, x2) order
+    const PassDev *passes; // every pass of the plan
+    const int32_t *xt;     // indices of the passes whose segments span several tiles
     const double *vin;     // n x W point-major canonical input
-    double *yacc;          // n x W point-major accumulator
-    double *aggF;          // tile aggregates (forward / backward)
-    double *aggB;
-    double *ancF;          // tile anchors: last / first scan coordinate
-    double *ancB;
-    const double *carF;    // tile carries from the tile scan
-    const double *carB;
+    double *ypart;         // G slabs of n x W: one partial result per pass of the group
+    double *agg;           // tile aggregates [2 dirs][G][ntile][nrb][NHALF][NSLOT]
+    double *anc;           // tile anchors [2 dirs][G][ntile]
     int64_t n;
-    int W;                 // leading width of vin / yacc (columns)
-    int l1, l2;
-    int seg_log2;
+    int64_t ntile;
+    int W;                 // leading width of vin / ypart (columns)
+    int g0;                // first pass of the group
+    int k0;                // first entry of xt inside the group
+    int G;                 // passes in the group
     double a;
 };
 
@@ -334,13 +341,17 @@ struct Smem {
     double geo[C::G > 0 ? C::G : 1][C::T];
     double waveF[NWAVE][C::NSLOT];
     double waveFx[NWAVE];
+    double car[2][C::NSLOT];   // carry from the other tiles of the segment, per direction
+    double carx[2];            // its anchor
+    int carhas[2];
 };
 
 // Stage the tile's positions: indices, flags, scan coordinate and offsets.
 template <class C>
-__device__ __forceinline__ void stage_tile(const SweepArgs &A, Smem<C> &sm, int64_t p0) {
+__device__ __forceinline__ void stage_tile(const SweepArgs &A, const PassDev &ps, Smem<C> &sm,
+                                           int64_t p0) {
     const int64_t n = A.n;
-    const int64_t segmask = (int64_t(1) << A.seg_log2) - 1;
+    const int64_t segmask = (int64_t(1) << ps.seg_log2) - 1;
     for (int j = threadIdx.x; j < C::T; j += WG) {
         const int64_t p = p0 + j;
         const int64_t pc = p < n ? p : n - 1;
@@ -352,8 +363,8 @@ __device__ __forceinline__ void stage_tile(const SweepArgs &A, Smem<C> &sm, int6
             c = pc;
             sm.xs[j] = A.xc[c];
         } else if constexpr (C::D == 2) {
-            c = A.ord[pc];
-            const int l = A.l1;
+            c = ps.ord[pc];
+            const int l = ps.l1;
             flags |= (int)((c >> l) & 1) ? F_SIDE1 : 0;
             int64_t sp = ((c >> (l + 1)) << (l + 1)) + (int64_t(1) << l);
             if (sp > n - 1) sp = n - 1;
@@ -363,9 +374,9 @@ __device__ __forceinline__ void stage_tile(const SweepArgs &A, Smem<C> &sm, int6
             sm.geo[1][j] = t;
             sm.xs[j] = A.xc[n + c];
         } else {
-            const int64_t q = A.ord[pc];
-            c = A.ord2[q];
-            const int l1 = A.l1, l2 = A.l2;
+            const int64_t q = ps.ord[pc];
+            c = ps.ord2[q];
+            const int l1 = ps.l1, l2 = ps.l2;
             flags |= (int)((c >> l1) & 1) ? F_SIDE1 : 0;
             flags |= (int)((q >> l2) & 1) ? F_SIDE2 : 0;
             int64_t sp1 = ((c >> (l1 + 1)) << (l1 + 1)) + (int64_t(1) << l1);
@@ -373,7 +384,7 @@ __device__ __forceinline__ void stage_tile(const SweepArgs &A, Smem<C> &sm, int6
             int64_t sq2 = ((q >> (l2 + 1)) << (l2 + 1)) + (int64_t(1) << l2);
             if (sq2 > n - 1) sq2 = n - 1;
             const double w1 = fabs(A.xc[c] - A.xc[sp1]);
-            const double w2 = fabs(A.xc[n + c] - A.xc[n + A.ord2[sq2]]);
+            const double w2 = fabs(A.xc[n + c] - A.xc[n + ps.ord2[sq2]]);
             const double t1 = A.a * w1, t2 = A.a * w2;
             sm.geo[0][j] = exp(-t1);
             sm.geo[1][j] = t1;
@@ -406,21 +417,27 @@ __device__ __forceinline__ void load_geo(const Smem<C> &sm, int j, double (&geo)
     for (int k = 0; k < C::G; ++k) geo[k] = sm.geo[k][j];
 }
 
+template <class C>
+__device__ __forceinline__ int64_t agg_index(const SweepArgs &A, int dir, int pl, int tile, int rb,
+                                             int nrb, int hh) {
+    return (((((int64_t)dir * A.G + pl) * A.ntile + tile) * nrb + rb) * C::NHALF + hh) * C::NSLOT;
+}
+
 // One scan direction over this thread's run of E positions, with every carry.
 // DIR 0: forward (positions in increasing order, sources at or before the
 //        target in the last coordinate: delta_last = +1);
 // DIR 1: backward (decreasing order, sources strictly after: delta_last = -1).
 // MODE 0 accumulates target values into outv; MODE 1 writes the tile's total.
 template <class C, int MODE, int DIR>
-__device__ __forceinline__ void run_direction(const SweepArgs &A, Smem<C> &sm, int hh, int tile,
-                                              int rb, int nrb, double (&outv)[C::E][C::R]) {
+__device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev &ps, Smem<C> &sm,
+                                              int hh, int tile, int pl, int rb, int nrb,
+                                              double (&outv)[C::E][C::R]) {
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int wave = tid / WAVE;
     const int j0 = tid * C::E;
-    const int seg = 1 << (A.seg_log2 < 30 ? A.seg_log2 : 30);
+    const int seg = 1 << (ps.seg_log2 < 30 ? ps.seg_log2 : 30);
     const int G = seg <= C::E ? 1 : (seg >= C::T ? WG : seg / C::E);
-    const bool cross_tile = seg > C::T;
     const int gw = G < WAVE ? G : WAVE;
     const int lig = lane & (gw - 1);
     const double a = A.a;
@@ -534,31 +551,22 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, Smem<C> &sm, i
                 const double t = a * (DIR == 0 ? xend - xex : xex - xend);
                 tot.shift(exp(-t), t);
                 tot.add_shifted(Frun, 1.0, 0.0);
-                double *dst = (DIR == 0 ? A.aggF : A.aggB) +
-                              ((int64_t)(tile * nrb + rb) * C::NHALF + hh) * C::NSLOT;
+                double *dst = A.agg + agg_index<C>(A, DIR, pl, tile, rb, nrb, hh);
 #pragma unroll
                 for (int i = 0; i < C::NSLOT; ++i) dst[i] = tot.flat()[i];
-                if (rb == 0 && hh == 0) (DIR == 0 ? A.ancF : A.ancB)[tile] = xend;
+                if (rb == 0 && hh == 0) A.anc[((int64_t)DIR * A.G + pl) * A.ntile + tile] = xend;
             }
             return;
         }
-        // ---- carry from the neighbouring tile of the same segment
-        if (cross_tile) {
-            const int64_t ntile = (A.n + C::T - 1) / C::T;
-            const int tps = seg / C::T;
-            const bool has_nb = DIR == 0 ? (tile % tps) != 0
-                                         : (((tile + 1) % tps) != 0 && tile + 1 < ntile);
-            if (has_nb) {
-                State<C> cf;
-                const double *src = (DIR == 0 ? A.carF : A.carB) +
-                                    ((int64_t)(tile * nrb + rb) * C::NHALF + hh) * C::NSLOT;
+        // ---- carry from the other tiles of the same segment (reduced into LDS)
+        if (sm.carhas[DIR]) {
+            State<C> cf;
 #pragma unroll
-                for (int i = 0; i < C::NSLOT; ++i) cf.flat()[i] = src[i];
-                const double anc = DIR == 0 ? A.ancF[tile - 1] : A.ancB[tile + 1];
-                if (tid == (DIR == 0 ? 0 : WG - 1)) xex = anc;
-                const double t = a * (DIR == 0 ? xex - anc : anc - xex);
-                Ex.add_shifted(cf, exp(-t), t);
-            }
+            for (int i = 0; i < C::NSLOT; ++i) cf.flat()[i] = sm.car[DIR][i];
+            const double anc = sm.carx[DIR];
+            if (tid == (DIR == 0 ? 0 : WG - 1)) xex = anc;
+            const double t = a * (DIR == 0 ? xex - anc : anc - xex);
+            Ex.add_shifted(cf, exp(-t), t);
         }
     }
     if constexpr (MODE == 0) {
@@ -593,15 +601,82 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, Smem<C> &sm, i
     }
 }
 
-// MODE 0: full sweep (targets written); MODE 1: tile aggregates only.
+// Sum over the tiles t' of a segment on one side of `tile` of the tile
+// aggregates shifted to the anchor next to `tile`; every term is a product of
+// bounded factors, so the tiles are combined in parallel (fixed order).
+template <class C>
+__device__ __forceinline__ void tile_carries(const SweepArgs &A, const PassDev &ps, Smem<C> &sm,
+                                             int tile, int pl, int rb, int nrb, int hh) {
+    const int seg = 1 << (ps.seg_log2 < 30 ? ps.seg_log2 : 30);
+    if (threadIdx.x < 2) sm.carhas[threadIdx.x] = 0;
+    if (seg <= C::T || A.ntile < 2) {
+        __syncthreads();
+        return;
+    }
+    const int64_t tps = seg / C::T;
+    const int64_t ts0 = (tile / tps) * tps;
+    const int64_t ts1 = ts0 + tps < A.ntile ? ts0 + tps : A.ntile;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x / WAVE;
+#pragma unroll 1
+    for (int dir = 0; dir < 2; ++dir) {
+        const bool has = dir == 0 ? tile > ts0 : tile + 1 < ts1;
+        if (!has) continue;  // uniform over the block
+        const double *ancd = A.anc + (int64_t)dir * A.G * A.ntile + (int64_t)pl * A.ntile;
+        const double xref = dir == 0 ? ancd[tile - 1] : ancd[tile + 1];
+        const int64_t lo = dir == 0 ? ts0 : tile + 1;
+        const int64_t hi = dir == 0 ? tile : ts1;
+        State<C> acc, tmp;
+        acc.zero();
+        for (int64_t t = lo + threadIdx.x; t < hi; t += WG) {
+            const double *src = A.agg + agg_index<C>(A, dir, pl, (int)t, rb, nrb, hh);
+#pragma unroll
+            for (int i = 0; i < C::NSLOT; ++i) tmp.flat()[i] = src[i];
+            const double sh = A.a * (dir == 0 ? xref - ancd[t] : ancd[t] - xref);
+            acc.add_shifted(tmp, exp(-sh), sh);
+        }
+        // block reduction: butterfly inside each wave, then the waves in order
+#pragma unroll
+        for (int i = 0; i < C::NSLOT; ++i) {
+            double v = acc.flat()[i];
+#pragma unroll
+            for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+            if (lane == 0) sm.waveF[wave][i] = v;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < C::NSLOT; i += WG) {
+            double v = 0.0;
+            for (int w = 0; w < NWAVE; ++w) v += sm.waveF[w][i];
+            sm.car[dir][i] = v;
+        }
+        if (threadIdx.x == 0) {
+            sm.carx[dir] = xref;
+            sm.carhas[dir] = 1;
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+}
+
+// MODE 0: one (pass, tile) of the group; the targets' sums go to the pass's slab.
+// MODE 1: tile aggregates of the passes whose segments span tiles.
 template <class C, int MODE>
 __global__ __launch_bounds__(WG) void sweep_kernel(SweepArgs A) {
     __shared__ Smem<C> sm;
-    const int tile = blockIdx.x;
+    int pass, tile;
+    if constexpr (MODE == 0) {
+        pass = A.g0 + (int)(blockIdx.x / A.ntile);
+        tile = (int)(blockIdx.x % A.ntile);
+    } else {
+        pass = A.xt[A.k0 + (int)(blockIdx.x / A.ntile)];
+        tile = (int)(blockIdx.x % A.ntile);
+    }
+    const int pl = pass - A.g0;
+    const PassDev ps = A.passes[pass];
     const int rb = blockIdx.y;
     const int nrb = gridDim.y;
     const int64_t p0 = (int64_t)tile * C::T;
-    stage_tile<C>(A, sm, p0);
+    stage_tile<C>(A, ps, sm, p0);
 
     double outv[C::E][C::R];
 #pragma unroll
@@ -611,134 +686,96 @@ __global__ __launch_bounds__(WG) void sweep_kernel(SweepArgs A) {
 
 #pragma unroll 1
     for (int hh = 0; hh < C::NHALF; ++hh) {
-        run_direction<C, MODE, 0>(A, sm, hh, tile, rb, nrb, outv);
-        run_direction<C, MODE, 1>(A, sm, hh, tile, rb, nrb, outv);
+        if constexpr (MODE == 0) tile_carries<C>(A, ps, sm, tile, pl, rb, nrb, hh);
+        run_direction<C, MODE, 0>(A, ps, sm, hh, tile, pl, rb, nrb, outv);
+        run_direction<C, MODE, 1>(A, ps, sm, hh, tile, pl, rb, nrb, outv);
+        __syncthreads();
     }
 
     if constexpr (MODE == 0) {
         const int j0 = threadIdx.x * C::E;
+        double *slab = A.ypart + (int64_t)pl * A.n * A.W;
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
             const int j = j0 + e;
             if (sm.flags[j] & F_VALID) {
-                double *dst = A.yacc + (int64_t)sm.c[j] * A.W + rb * C::R;
+                double *dst = slab + (int64_t)sm.c[j] * A.W + rb * C::R;
 #pragma unroll
-                for (int r = 0; r < C::R; ++r) dst[r] += outv[e][r];
+                for (int r = 0; r < C::R; ++r) dst[r] = outv[e][r];
             }
         }
     }
 }
 
-// Exclusive scan of tile aggregates inside each segment (one thread per
-// independent slice: half, class, channel row, right-hand side).
-template <class C>
-__global__ __launch_bounds__(WG) void tile_scan_kernel(SweepArgs A, int tps, int64_t ntile,
-                                                       double *carF, double *carB) {
-    const int seg = blockIdx.x;
-    const int rb = blockIdx.y;
-    const int nrb = gridDim.y;
-    constexpr int SLICES = C::NHALF * C::NCLS * C::NTH * C::R;
-    const int64_t t0 = (int64_t)seg * tps;
-    int64_t t1 = t0 + tps;
-    if (t1 > ntile) t1 = ntile;
-    const double a = A.a;
-    for (int sl = threadIdx.x; sl < SLICES; sl += WG) {
-        const int r = sl % C::R;
-        const int rest = sl / C::R;          // (half, class, row)
-        const int hh = rest / (C::NCLS * C::NTH);
-        const int ch = rest % (C::NCLS * C::NTH);
-        auto off = [&](int64_t t, int m) -> int64_t {
-            return ((t * nrb + rb) * C::NHALF + hh) * C::NSLOT + ((int64_t)ch * C::P + m) * C::R + r;
-        };
-        // forward
-        double acc[C::P];
-#pragma unroll
-        for (int m = 0; m < C::P; ++m) acc[m] = 0.0;
-        double ax = A.ancF[t0];
-        for (int64_t t = t0; t < t1; ++t) {
-            const double x = A.ancF[t];
-            if (t > t0) {
-                const double tt = a * (x - ax);
-                const double E = exp(-tt);
-                // carry into tile t is acc anchored at ancF[t-1] (= ax)
-#pragma unroll
-                for (int m = 0; m < C::P; ++m) carF[off(t, m)] = acc[m];
-                if constexpr (C::P == 3) acc[2] = E * (acc[2] + tt * acc[1] + 0.5 * tt * tt * acc[0]);
-                if constexpr (C::P >= 2) acc[1] = E * (acc[1] + tt * acc[0]);
-                acc[0] = E * acc[0];
-            } else {
-#pragma unroll
-                for (int m = 0; m < C::P; ++m) carF[off(t, m)] = 0.0;
-            }
-#pragma unroll
-            for (int m = 0; m < C::P; ++m) acc[m] += A.aggF[off(t, m)];
-            ax = x;
-        }
-        // backward
-#pragma unroll
-        for (int m = 0; m < C::P; ++m) acc[m] = 0.0;
-        ax = A.ancB[t1 - 1];
-        for (int64_t t = t1 - 1; t >= t0; --t) {
-            const double x = A.ancB[t];
-            if (t < t1 - 1) {
-                const double tt = a * (ax - x);
-                const double E = exp(-tt);
-#pragma unroll
-                for (int m = 0; m < C::P; ++m) carB[off(t, m)] = acc[m];
-                if constexpr (C::P == 3) acc[2] = E * (acc[2] + tt * acc[1] + 0.5 * tt * tt * acc[0]);
-                if constexpr (C::P >= 2) acc[1] = E * (acc[1] + tt * acc[0]);
-                acc[0] = E * acc[0];
-            } else {
-#pragma unroll
-                for (int m = 0; m < C::P; ++m) carB[off(t, m)] = 0.0;
-            }
-#pragma unroll
-            for (int m = 0; m < C::P; ++m) acc[m] += A.aggB[off(t, m)];
-            ax = x;
-        }
+// yacc = [yacc +] sum of the group's slabs, in pass order.
+__global__ void accum_kernel(const double *ypart, int G, int64_t len, double *yacc, int first) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double s = first ? 0.0 : yacc[e];
+        for (int g = 0; g < G; ++g) s += ypart[(int64_t)g * len + e];
+        yacc[e] = s;
     }
+}
+
+__global__ void zero_kernel(double *p, int64_t len) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
 // Host-side dispatch.
 // ---------------------------------------------------------------------------
 constexpr int E_RUN = 4;
+constexpr int TILE = WG * E_RUN;
+
+inline unsigned grid_1d(int64_t n) {
+    int64_t g = (n + WG - 1) / WG;
+    if (g > 65535 * 8) g = 65535 * 8;
+    return (unsigned)(g < 1 ? 1 : g);
+}
 
 template <class C>
 mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStream_t s) {
+    static_assert(C::T == TILE, "tile size");
     const KParams kp = kparams(p->kernel, p->d);
     const int64_t n = p->n;
     const int nrb = W / C::R;
     const int64_t ntile = (n + C::T - 1) / C::T;
-    const size_t slab = (size_t)ntile * nrb * C::NHALF * C::NSLOT;
-    double *base = static_cast<double *>(p->agg.ptr);
+    const int npass = (int)p->passes.size();
+    const int64_t len = n * W;
+    if (npass == 0) {
+        hipLaunchKernelGGL(zero_kernel, dim3(grid_1d(len)), dim3(WG), 0, s, yacc, len);
+        MM_HIP_TRY(hipGetLastError());
+        return MM_OK;
+    }
+    const int gmax = group_passes(p, W);
     SweepArgs A{};
     A.xc = static_cast<const double *>(p->xc.ptr);
+    A.passes = static_cast<const PassDev *>(p->pass_dev.ptr);
+    A.xt = static_cast<const int32_t *>(p->pass_xt.ptr);
     A.vin = vin;
-    A.yacc = yacc;
+    A.ypart = static_cast<double *>(p->part.ptr);
     A.n = n;
+    A.ntile = ntile;
     A.W = W;
     A.a = kp.a;
-    A.aggF = base;
-    A.aggB = base + slab;
-    A.carF = base + 2 * slab;
-    A.carB = base + 3 * slab;
-    A.ancF = base + 4 * slab;
-    A.ancB = base + 4 * slab + ntile;
-    for (const Pass &ps : p->passes) {
-        A.ord = ps.ord;
-        A.ord2 = ps.ord2;
-        A.l1 = ps.l1;
-        A.l2 = ps.l2;
-        A.seg_log2 = ps.seg_log2;
-        dim3 grid((unsigned)ntile, (unsigned)nrb);
-        if ((int64_t(1) << ps.seg_log2) > C::T && ntile > 1) {
-            hipLaunchKernelGGL((sweep_kernel<C, 1>), grid, dim3(WG), 0, s, A);
-            const int tps = (int)((int64_t(1) << ps.seg_log2) / C::T);
-            const int64_t nseg = (ntile + tps - 1) / tps;
-            hipLaunchKernelGGL((tile_scan_kernel<C>), dim3((unsigned)nseg, (unsigned)nrb), dim3(WG), 0, s,
-                               A, tps, ntile, const_cast<double *>(A.carF), const_cast<double *>(A.carB));
-        }
+    const size_t aggslab = (size_t)2 * gmax * ntile * nrb * C::NHALF * C::NSLOT;
+    A.agg = static_cast<double *>(p->agg.ptr);
+    A.anc = A.agg + aggslab;
+    for (int g0 = 0; g0 < npass; g0 += gmax) {
+        const int G = npass - g0 < gmax ? npass - g0 : gmax;
+        A.g0 = g0;
+        A.G = G;
+        // passes of the group whose segments span tiles: a contiguous range of xt
+        int k0 = 0, k1 = 0;
+        while (k0 < (int)p->xt_host.size() && p->xt_host[k0] < g0) ++k0;
+        k1 = k0;
+        while (k1 < (int)p->xt_host.size() && p->xt_host[k1] < g0 + G) ++k1;
+        A.k0 = k0;
+        if (k1 > k0 && ntile > 1)
+            hipLaunchKernelGGL((sweep_kernel<C, 1>), dim3((unsigned)((k1 - k0) * ntile), (unsigned)nrb),
+                               dim3(WG), 0, s, A);
         hipEvent_t ev1 = nullptr;
         if (p->profile) {
             // bracket the main sweep launch with events on its stream
@@ -756,9 +793,12 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
             MM_HIP_TRY(hipEventRecord(p->prof_events[p->prof_used].first, s));
             ev1 = p->prof_events[p->prof_used].second;
             p->prof_used++;
+            p->prof_units += (int64_t)G;
         }
-        hipLaunchKernelGGL((sweep_kernel<C, 0>), grid, dim3(WG), 0, s, A);
+        hipLaunchKernelGGL((sweep_kernel<C, 0>), dim3((unsigned)(G * ntile), (unsigned)nrb), dim3(WG), 0, s, A);
         if (ev1) MM_HIP_TRY(hipEventRecord(ev1, s));
+        hipLaunchKernelGGL(accum_kernel, dim3(grid_1d(len)), dim3(WG), 0, s,
+                           static_cast<const double *>(p->part.ptr), G, len, yacc, g0 == 0 ? 1 : 0);
     }
     MM_HIP_TRY(hipGetLastError());
     return MM_OK;
@@ -821,14 +861,55 @@ int rhs_block(const mm_kernel &k, int d, int nrhs) {
     return R;
 }
 
+// Passes per group: the partial slabs of one group stay within 1 GiB.
+constexpr size_t PART_BUDGET = size_t(1) << 30;
+
+static int group_size(int64_t n, int npass, int W) {
+    const size_t slab = (size_t)n * W * sizeof(double);
+    int64_t g = (int64_t)(PART_BUDGET / (slab > 0 ? slab : 1));
+    if (g < 1) g = 1;
+    if (g > npass) g = npass;
+    return (int)(g < 1 ? 1 : g);
+}
+
+int group_passes(mm_plan p, int W) { return group_size(p->n, (int)p->passes.size(), W); }
+
+size_t sweep_part_bytes(int64_t n, int npass, int W) {
+    if (npass == 0) return 0;
+    return (size_t)group_size(n, npass, W) * n * W * sizeof(double);
+}
+
 size_t sweep_agg_bytes(int64_t n, int d, int W, const mm_kernel &k) {
     (void)k;
-    (void)d;
     // per tile and right-hand side at most NHALF*NCLS*NTH*P <= 108 doubles
-    // (d = 3, product form, nu = 5/2), for each of the four arrays
-    const int64_t ntile = (n + WG * E_RUN - 1) / (WG * E_RUN);
+    // (d = 3, product form, nu = 5/2), two directions, per pass of a group
+    int L = 0;
+    while ((int64_t(1) << L) < n) ++L;
+    const int npass = n < 2 ? 0 : (d == 1 ? 1 : (d == 2 ? L : L * (L + 1) / 2));
+    const int64_t G = npass == 0 ? 1 : group_size(n, npass, W);
+    const int64_t ntile = (n + TILE - 1) / TILE;
     const int64_t per_rhs = 128;
-    return (size_t)(4 * ntile * (int64_t)W * per_rhs + 2 * ntile + 16) * sizeof(double);
+    return (size_t)(2 * G * ntile * (int64_t)W * per_rhs + 2 * G * ntile + 16) * sizeof(double);
+}
+
+mm_status upload_pass_tables(mm_plan p) {
+    std::vector<PassDev> tab;
+    p->xt_host.clear();
+    for (size_t i = 0; i < p->passes.size(); ++i) {
+        const Pass &q = p->passes[i];
+        PassDev d{q.ord, q.ord2, q.l1, q.l2, q.seg_log2, 0};
+        tab.push_back(d);
+        if ((int64_t(1) << (q.seg_log2 < 40 ? q.seg_log2 : 40)) > TILE) p->xt_host.push_back((int)i);
+    }
+    if (tab.empty()) return MM_OK;
+    MM_TRY(dev_alloc(p->pass_dev, tab.size() * sizeof(PassDev)));
+    MM_HIP_TRY(hipMemcpy(p->pass_dev.ptr, tab.data(), tab.size() * sizeof(PassDev), hipMemcpyHostToDevice));
+    if (!p->xt_host.empty()) {
+        MM_TRY(dev_alloc(p->pass_xt, p->xt_host.size() * sizeof(int32_t)));
+        MM_HIP_TRY(hipMemcpy(p->pass_xt.ptr, p->xt_host.data(), p->xt_host.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice));
+    }
+    return MM_OK;
 }
 
 mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int R, hipStream_t s) {
