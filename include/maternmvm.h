@@ -192,6 +192,74 @@ mm_status gp_predict(mm_plan plan, const double *alpha, const double *beta, cons
                      int64_t m, int64_t ldz, double *mean, void *stream);
 
 /*
+ * Solver objects: the conjugate-gradient solve of gp_cg_solve (Appendix A,
+ * Algorithm 2, identity preconditioner, null initial guess; with fixed
+ * effects the GLS of Section 3.2) split into steps, so that a caller can
+ * advance many independent GP problems together.  A solver keeps its state on
+ * the device; gp_cg_solve itself is create + iterate until done + finish +
+ * destroy, and every path runs the same kernels, so a problem's iterates do
+ * not depend on which other solvers share its batch (bitwise).
+ * The solver reads the plan's stored orders and the kernel it had at
+ * creation: while solvers of a plan are alive, mm_plan_set_kernel and
+ * mm_plan_destroy on it fail with MM_ERR_ARG.  Several solvers may share one
+ * plan.
+ */
+typedef struct mm_solver_s *mm_solver;
+typedef struct mm_solver_batch_s *mm_solver_batch;
+
+/* Create a solver for (K + sigma2 I) alpha = y - H beta with the arguments of
+ * gp_cg_solve (y: device, n targets in caller order; it is copied) and run
+ * its initialisation on `stream`; *out receives the handle. */
+mm_status mm_solver_create(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects,
+                           double rtol, void *stream, mm_solver *out);
+
+/* Enqueue `iters` further iterations (columns that reached rtol stay frozen;
+ * iterating a solved problem changes nothing). */
+mm_status mm_solver_iterate(mm_solver solver, int32_t iters, void *stream);
+
+/* Columns still above rtol, whether a breakdown (p^T A p <= 0) occurred, and
+ * the convergence summary so far (any output may be NULL).  Synchronises. */
+mm_status mm_solver_poll(mm_solver solver, int32_t *active_cols, int32_t *breakdown,
+                         mm_solve_info *info, void *stream);
+
+/* Write alpha (device, n, caller order) and beta (host, d+1, fixed effects
+ * only) from the current iterate, with the status rules of gp_cg_solve
+ * (MM_ERR_NOCONV / MM_ERR_BREAKDOWN still write the outputs).  Synchronises. */
+mm_status mm_solver_finish(mm_solver solver, double *alpha, double *beta, mm_solve_info *info,
+                           void *stream);
+
+/* Release a solver (synchronises the device).  NULL is accepted. */
+mm_status mm_solver_destroy(mm_solver solver);
+
+/* Group `count` solvers (host array of handles; any mix of n, d, nu, forms and
+ * column counts) for joint iteration: every iteration runs all their products
+ * in one launch per kernel configuration, column width and phase, and all
+ * their vector updates in one launch per step.  With use_graph != 0
+ * the iterations are captured once into a HIP graph and replayed on a
+ * private stream ordered after `stream`.  A solver whose passes exceed one
+ * pass group (very large n, d = 3) cannot join a batch of two or more
+ * (MM_ERR_ARG).  A solver may belong to several batches but must not be
+ * iterated by two at the same time.  The solvers must outlive the batch. */
+mm_status mm_solver_batch_create(mm_solver *solvers, int32_t count, int32_t use_graph,
+                                 mm_solver_batch *out);
+
+/* Launch schedule of a batch: workgroups per compute unit of the persistent
+ * sweep grids (>= 1) and the grid of the vector-update kernels (>= 1).
+ * Results do not depend on it. */
+mm_status mm_solver_batch_set_schedule(mm_solver_batch batch, int32_t sweep_wg_per_cu,
+                                       int32_t cg_grid);
+
+/* Enqueue `iters` iterations of every solver of the batch. */
+mm_status mm_solver_batch_iterate(mm_solver_batch batch, int32_t iters, void *stream);
+
+/* Host array of count entries: columns still active per solver after the
+ * last batch iteration, or -1 after a breakdown.  Synchronises. */
+mm_status mm_solver_batch_poll(mm_solver_batch batch, int32_t *active, void *stream);
+
+/* Release a batch (not its solvers).  NULL is accepted. */
+mm_status mm_solver_batch_destroy(mm_solver_batch batch);
+
+/*
  * Kernel-time accounting for measurement: when enabled, every launch of the
  * divide-and-conquer sweep kernel of this plan (one launch covers a group of
  * passes) is bracketed by HIP events on its stream.  mm_plan_profile_read()

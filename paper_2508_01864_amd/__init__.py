@@ -80,6 +80,20 @@ _SIGS = {
                                          ctypes.POINTER(_MMSolveInfo), _P]),
     "gp_predict": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double), _P, ctypes.c_int64,
                                   ctypes.c_int64, _P, _P]),
+    "mm_solver_create": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_double, _P,
+                                        ctypes.POINTER(_P)]),
+    "mm_solver_iterate": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
+    "mm_solver_poll": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(_MMSolveInfo), _P]),
+    "mm_solver_finish": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(_MMSolveInfo), _P]),
+    "mm_solver_destroy": (ctypes.c_int, [_P]),
+    "mm_solver_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.POINTER(_P)]),
+    "mm_solver_batch_set_schedule": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "mm_solver_batch_iterate": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
+    "mm_solver_batch_poll": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
+    "mm_solver_batch_destroy": (ctypes.c_int, [_P]),
     "mm_plan_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "mm_plan_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_int64),
@@ -186,7 +200,7 @@ class Plan:
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
-            lib().mm_plan_destroy(self._h)
+            _check(lib().mm_plan_destroy(self._h))
             self._h = ctypes.c_void_p()
 
     def __del__(self):
@@ -286,6 +300,104 @@ class Plan:
         _check(lib().mm_plan_profile_read(self._h, ctypes.byref(ms), ctypes.byref(cnt),
                                           ctypes.byref(npass), 1 if reset else 0))
         return ms.value, cnt.value, npass.value
+
+
+def _info_dict(info: _MMSolveInfo, st: int) -> dict:
+    return {"iters": info.iters, "converged_cols": info.converged_cols,
+            "relres_max": info.relres_max, "status": STATUS_NAMES[st]}
+
+
+class Solver:
+    """Conjugate-gradient GP solve split into steps (mm_solver): create, iterate,
+    poll, finish.  gp_cg_solve runs the same kernels, so results agree bitwise."""
+
+    def __init__(self, plan: Plan, y, sigma2: float, fixed_effects: bool = False,
+                 rtol: float = 1e-8, stream=None):
+        self.plan = plan
+        self.fixed_effects = bool(fixed_effects)
+        self._stream = stream
+        self._y = _colmajor(y, plan.n).view(-1)   # read by the creation kernels
+        self._h = ctypes.c_void_p()
+        _check(lib().mm_solver_create(plan.handle, ctypes.c_void_p(self._y.data_ptr()), float(sigma2),
+                                      1 if fixed_effects else 0, float(rtol), _stream_ptr(stream),
+                                      ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def iterate(self, iters: int):
+        _check(lib().mm_solver_iterate(self._h, int(iters), _stream_ptr(self._stream)))
+
+    def poll(self):
+        """(active columns, breakdown flag, info dict)."""
+        act = ctypes.c_int32()
+        brk = ctypes.c_int32()
+        info = _MMSolveInfo()
+        _check(lib().mm_solver_poll(self._h, ctypes.byref(act), ctypes.byref(brk), ctypes.byref(info),
+                                    _stream_ptr(self._stream)))
+        return act.value, brk.value, _info_dict(info, MM_OK)
+
+    def finish(self, raise_on_error: bool = True):
+        """(alpha, beta or None, info) from the current iterate."""
+        torch = _torch()
+        alpha = torch.empty(self.plan.n, dtype=torch.float64, device=self._y.device)
+        beta = (ctypes.c_double * (self.plan.d + 1))()
+        info = _MMSolveInfo()
+        st = lib().mm_solver_finish(self._h, ctypes.c_void_p(alpha.data_ptr()),
+                                    beta if self.fixed_effects else None, ctypes.byref(info),
+                                    _stream_ptr(self._stream))
+        msg = last_error()
+        if st not in (MM_OK, MM_ERR_NOCONV, MM_ERR_BREAKDOWN) or (st != MM_OK and raise_on_error):
+            raise MaternError(st, msg)
+        return alpha, (np.array(beta[:]) if self.fixed_effects else None), _info_dict(info, st)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mm_solver_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SolverBatch:
+    """Joint iteration of several solvers (mm_solver_batch): one launch per kernel
+    configuration and phase per iteration, optionally replayed from a HIP graph."""
+
+    def __init__(self, solvers, use_graph: bool = True, stream=None):
+        self.solvers = list(solvers)
+        self._stream = stream
+        arr = (ctypes.c_void_p * len(self.solvers))(*[s.handle.value for s in self.solvers])
+        self._h = ctypes.c_void_p()
+        _check(lib().mm_solver_batch_create(arr, len(self.solvers), 1 if use_graph else 0,
+                                            ctypes.byref(self._h)))
+
+    def set_schedule(self, sweep_wg_per_cu: int, cg_grid: int):
+        _check(lib().mm_solver_batch_set_schedule(self._h, int(sweep_wg_per_cu), int(cg_grid)))
+
+    def iterate(self, iters: int):
+        _check(lib().mm_solver_batch_iterate(self._h, int(iters), _stream_ptr(self._stream)))
+
+    def poll(self):
+        """Active columns per solver after the last iteration (-1 = breakdown)."""
+        out = (ctypes.c_int32 * len(self.solvers))()
+        _check(lib().mm_solver_batch_poll(self._h, out, _stream_ptr(self._stream)))
+        return list(out)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mm_solver_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def levels(n: int) -> int:

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmaternmvm.so")
-SOURCES = ["plan.hip", "sweep.hip", "api.hip"]
+SOURCES = ["plan.hip", "sweep.hip", "api.hip", "solver.hip"]
 ARCH = "gfx950"
 
 

@@ -17,6 +17,7 @@ namespace mm {
 // ---------------------------------------------------------------------------
 void set_error(const char *fmt, ...);
 void clear_error();
+const char *last_error_str();
 
 #define MM_HIP_TRY(expr)                                                        \
     do {                                                                        \
@@ -91,8 +92,10 @@ struct mm_plan_s {
     mm::DevBuf structure;         // all stored orders (int32)
     std::vector<mm::Pass> passes;
     mm::DevBuf pass_dev;          // device table of the passes
-    mm::DevBuf pass_xt;           // indices of passes whose segments span tiles
-    std::vector<int> xt_host;
+    mm::DevBuf pass_xt[3];        // per tile size (256, 512, 1024 positions): passes whose
+    std::vector<int> xt_host[3];  //   segments span tiles
+    mm::DevBuf seg_tab[3];        // per tile size: (pass, first tile, end tile) of those segments
+    std::vector<int> seg_off[3];  //   offset of each cross-tile pass's first segment
 
     // product work buffers (grow on demand)
     mm::DevBuf vin;               // n x W point-major canonical input
@@ -100,10 +103,7 @@ struct mm_plan_s {
     mm::DevBuf agg;               // tile aggregates and anchors
     mm::DevBuf part;              // per-pass partial results of one pass group
     int64_t work_cols = 0;
-
-    // CG work buffers
-    mm::DevBuf cgbuf;
-    mm::DevBuf redbuf;
+    int nsolvers = 0;             // live solvers reading this plan
 
     // measurement
     bool profile = false;
@@ -118,6 +118,44 @@ namespace mm {
 
 // sweep.hip
 mm_status profile_flush(mm_plan p, double *ms, int64_t *launches);
+
+// Batched sweeps over several problems of one width (one launch per kernel
+// configuration and phase; the work tables are built once per problem set).
+struct BatchEntry {
+    mm_plan p;
+    const double *vin;  // n x W point-major canonical input
+    double *yacc;       // n x W point-major result (sum over passes)
+    double *agg;        // workspaces of sweep_batch_bytes (owned by the caller)
+    double *part;
+};
+// Workspace sizes of a batched product of plan p at width W, where all of the
+// plan's passes run as one group; false if their partial slabs would exceed
+// the group budget (such a problem runs alone through sweep_all).
+bool sweep_batch_bytes(mm_plan p, int W, size_t *agg_bytes, size_t *part_bytes);
+constexpr int ACC_CHUNK = 8192;
+struct AccumDesc {
+    const double *ypart;
+    double *yacc;
+    int64_t len;
+    int G;
+};
+struct SweepBatch {
+    struct Cls {
+        int key = 0, d = 1;
+        KParams kp;
+        std::vector<int> members;
+        DevBuf descs, items_agg, items_carry, items_main;
+        int n_agg = 0, n_carry = 0, n_main = 0;
+    };
+    std::vector<Cls> classes;
+    DevBuf acc_desc, acc_items;
+    int n_acc = 0;
+    int W = 1, WB = 1;
+    int grid_per_cu = 8;  // persistent grid: workgroups per compute unit (tuned)
+};
+mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB, SweepBatch &out);
+mm_status sweep_batch_run(SweepBatch &b, hipStream_t s);
+void sweep_batch_free(SweepBatch &b);
 mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int R, hipStream_t s);
 int rhs_block(const mm_kernel &k, int d, int nrhs);
 size_t sweep_agg_bytes(int64_t n, int d, int W, const mm_kernel &k);

@@ -1,0 +1,956 @@
+// Conjugate gradients as solver objects (Appendix A, Algorithm 2 with the
+// identity preconditioner and a null initial guess), iterated alone or many
+// at once.  A solver keeps its right-hand sides, iterate, residual, direction
+// and scalars on the device in the plan's canonical point order, so
+// iterations need no permutation and no host round trip.  Batched iterations
+// run every solver's product in the batched sweeps (one launch per kernel
+// configuration and phase) and every CG update in one launch per step over a
+// table of (solver, block) items; a single solver runs the very same kernels
+// with a table of one, so a problem's arithmetic does not depend on its
+// batch-mates (results are bitwise identical alone and in a batch).
+#include "mm_internal.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace mm {
+
+namespace {
+
+constexpr int BS = 256;
+constexpr int NRED = 256;  // row blocks of the column dot products (fixed: deterministic sums)
+constexpr int NS = 8;      // scalars per column: [0] r.r [1] p.Ap [2] alpha [3] beta
+                           // [4] |b| [5] active [6] iterations while active [7] |r|
+constexpr int CHUNK = 4096;
+
+struct CgDesc {
+    const double *B;
+    double *X, *R, *P, *Q, *Y;
+    double *part;  // NRED x W partial column sums
+    double *sc;    // W x NS
+    int *flags;    // [0] active columns after the last update, [1] breakdown seen
+    int64_t n;
+    int W;
+    int ncols;
+    double s2, sigma2, rtol;
+};
+
+__device__ __forceinline__ void row_range(int64_t n, int blk, int64_t &lo, int64_t &hi) {
+    const int64_t chunk = (n + NRED - 1) / NRED;
+    lo = blk * chunk;
+    hi = lo + chunk < n ? lo + chunk : n;
+}
+
+// part[blk][r] = sum over the block's rows of acc (one value per thread, W | BS)
+__device__ __forceinline__ void block_col_sum(double acc, int W, double *sm, double *part, int blk) {
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    if ((int)threadIdx.x < W) {
+        double s = 0.0;
+        for (int t = threadIdx.x; t < BS; t += W) s += sm[t];
+        part[(int64_t)blk * W + threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// x0 = 0, r0 = b, p0 = r0, partial |b|^2
+__global__ void cg_init_b(const CgDesc *ds, const int2 *items, int nitems) {
+    __shared__ double sm[BS];
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        const CgDesc d = ds[it.x];
+        int64_t lo, hi;
+        row_range(d.n, it.y, lo, hi);
+        double acc = 0.0;
+        for (int64_t e = lo * d.W + threadIdx.x; e < hi * d.W; e += BS) {
+            const double b = d.B[e];
+            d.X[e] = 0.0;
+            d.R[e] = b;
+            d.P[e] = b;
+            acc += b * b;
+        }
+        block_col_sum(acc, d.W, sm, d.part, it.y);
+    }
+}
+
+__global__ void cg_init_scalars_b(const CgDesc *ds, int nsol) {
+    for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
+        const CgDesc d = ds[k];
+        const int r = threadIdx.x;
+        if (r < d.W) {
+            double s = 0.0;
+            for (int b = 0; b < NRED; ++b) s += d.part[(int64_t)b * d.W + r];
+            double *c = d.sc + r * NS;
+            c[0] = s;
+            c[1] = 0.0;
+            c[2] = 0.0;
+            c[3] = 0.0;
+            c[4] = sqrt(s);
+            c[5] = (r < d.ncols && s > 0.0) ? 1.0 : 0.0;
+            c[6] = 0.0;
+            c[7] = sqrt(s);
+        }
+        if (r == 0) {
+            d.flags[0] = 0;
+            d.flags[1] = 0;
+        }
+    }
+}
+
+// Q = s2 (P + Y) + sigma2 P (Y = off-diagonal kernel sums of P), partial P.Q
+__global__ void cg_apply_b(const CgDesc *ds, const int2 *items, int nitems) {
+    __shared__ double sm[BS];
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        const CgDesc d = ds[it.x];
+        int64_t lo, hi;
+        row_range(d.n, it.y, lo, hi);
+        double acc = 0.0;
+        for (int64_t e = lo * d.W + threadIdx.x; e < hi * d.W; e += BS) {
+            const double p = d.P[e];
+            const double q = d.s2 * (p + d.Y[e]) + d.sigma2 * p;
+            d.Q[e] = q;
+            acc += p * q;
+        }
+        block_col_sum(acc, d.W, sm, d.part, it.y);
+    }
+}
+
+// alpha = r.r / p.Ap per active column; non-positive curvature = breakdown
+__global__ void cg_alpha_b(const CgDesc *ds, int nsol) {
+    for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
+        const CgDesc d = ds[k];
+        const int r = threadIdx.x;
+        if (r >= d.W) continue;
+        double s = 0.0;
+        for (int b = 0; b < NRED; ++b) s += d.part[(int64_t)b * d.W + r];
+        double *c = d.sc + r * NS;
+        c[1] = s;
+        if (c[5] != 0.0) {
+            if (!(s > 0.0)) {
+                d.flags[1] = 1;
+                c[2] = 0.0;
+                c[5] = 0.0;
+            } else {
+                c[2] = c[0] / s;
+                c[6] += 1.0;
+            }
+        } else {
+            c[2] = 0.0;
+        }
+    }
+}
+
+// X += alpha P, R -= alpha Q, partial R.R
+__global__ void cg_update_b(const CgDesc *ds, const int2 *items, int nitems) {
+    __shared__ double sm[BS];
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        const CgDesc d = ds[it.x];
+        int64_t lo, hi;
+        row_range(d.n, it.y, lo, hi);
+        const double al = d.sc[(threadIdx.x % d.W) * NS + 2];
+        double acc = 0.0;
+        for (int64_t e = lo * d.W + threadIdx.x; e < hi * d.W; e += BS) {
+            const double xr = d.X[e] + al * d.P[e];
+            const double rr = d.R[e] - al * d.Q[e];
+            d.X[e] = xr;
+            d.R[e] = rr;
+            acc += rr * rr;
+        }
+        block_col_sum(acc, d.W, sm, d.part, it.y);
+    }
+}
+
+__global__ void cg_reset_active_b(const CgDesc *ds, int nsol) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nsol; k += gridDim.x * blockDim.x)
+        ds[k].flags[0] = 0;
+}
+
+// beta = r.r(new) / r.r(old); columns reaching the tolerance are frozen
+__global__ void cg_beta_b(const CgDesc *ds, int nsol) {
+    for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
+        const CgDesc d = ds[k];
+        const int r = threadIdx.x;
+        if (r >= d.W) continue;
+        double s = 0.0;
+        for (int b = 0; b < NRED; ++b) s += d.part[(int64_t)b * d.W + r];
+        double *c = d.sc + r * NS;
+        if (c[5] != 0.0) {
+            if (sqrt(s) <= d.rtol * c[4]) {
+                c[5] = 0.0;
+                c[3] = 0.0;
+            } else {
+                c[3] = s / c[0];
+                atomicAdd(&d.flags[0], 1);  // integer count of still-active columns
+            }
+            c[7] = sqrt(s);
+            c[0] = s;
+        } else {
+            c[3] = 0.0;
+        }
+    }
+}
+
+// P = R + beta P on active columns
+__global__ void cg_dir_b(const CgDesc *ds, const int2 *items, int nitems) {
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        const CgDesc d = ds[it.x];
+        const int64_t lo = (int64_t)it.y * CHUNK;
+        const int64_t len = d.n * d.W;
+        const int64_t hi = lo + CHUNK < len ? lo + CHUNK : len;
+        for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+            const int r = (int)(e % d.W);
+            if (d.sc[r * NS + 5] != 0.0) d.P[e] = d.R[e] + d.sc[r * NS + 3] * d.P[e];
+        }
+    }
+}
+
+// status[k] = (active columns, breakdown) of every solver, for one host read
+__global__ void cg_collect_b(const CgDesc *ds, int nsol, int2 *status) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nsol; k += gridDim.x * blockDim.x)
+        status[k] = make_int2(ds[k].flags[0], ds[k].flags[1]);
+}
+
+// right-hand sides [y, 1, x_1..x_d] (fixed effects) or [y] in canonical order
+__global__ void fe_rhs_kernel(const double *y, const int32_t *perm, const double *xc, int64_t n, int d,
+                              int fe, int W, double *B) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        double *row = B + c * W;
+        row[0] = y[perm[c]];
+        int col = 1;
+        if (fe) {
+            row[col++] = 1.0;
+            for (int k = 0; k < d; ++k) row[col++] = xc[(int64_t)k * n + c];
+        }
+        for (; col < W; ++col) row[col] = 0.0;
+    }
+}
+
+__global__ void gather_cols_kernel(const double *v, int64_t ldv, int nrhs, const int32_t *perm, int64_t n,
+                                   double *out, int W) {
+    const int64_t total = n * W;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / W;
+        const int r = (int)(e - c * W);
+        out[e] = r < nrhs ? v[(int64_t)r * ldv + perm[c]] : 0.0;
+    }
+}
+
+// partial sums of H^T X for the (d+1) x W block, H = [1, x_1..x_d]
+__global__ void fe_gram_kernel(const double *X, const double *xc, int64_t n, int d, int W, double *part) {
+    __shared__ double sm[BS];
+    int64_t lo, hi;
+    row_range(n, blockIdx.x, lo, hi);
+    for (int i = 0; i <= d; ++i) {
+        double acc = 0.0;
+        for (int64_t e = lo * W + threadIdx.x; e < hi * W; e += BS) {
+            const int64_t c = e / W;
+            const double h = i == 0 ? 1.0 : xc[(int64_t)(i - 1) * n + c];
+            acc += h * X[e];
+        }
+        sm[threadIdx.x] = acc;
+        __syncthreads();
+        if ((int)threadIdx.x < W) {
+            double s = 0.0;
+            for (int t = threadIdx.x; t < BS; t += W) s += sm[t];
+            part[((int64_t)blockIdx.x * (d + 1) + i) * W + threadIdx.x] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// alpha (caller order) = X[:,0] - sum_j X[:,1+j] beta_j
+__global__ void fe_alpha_kernel(const double *X, const int32_t *perm, int64_t n, int W, int nb, double b0, double b1,
+                                double b2, double b3, double *alpha) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        const double *row = X + c * W;
+        double a = row[0];
+        if (nb > 0) a -= row[1] * b0;
+        if (nb > 1) a -= row[2] * b1;
+        if (nb > 2) a -= row[3] * b2;
+        if (nb > 3) a -= row[4] * b3;
+        alpha[perm[c]] = a;
+    }
+}
+
+__global__ void col_out_kernel(const double *X, const int32_t *perm, int64_t n, int W, int nrhs, double *out,
+                               int64_t ldo) {
+    const int64_t total = n * nrhs;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / n);
+        const int64_t c = e - (int64_t)r * n;
+        out[(int64_t)r * ldo + perm[c]] = X[c * W + r];
+    }
+}
+
+inline unsigned grid1(int64_t n) {
+    int64_t g = (n + BS - 1) / BS;
+    if (g > 65535 * 8) g = 65535 * 8;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+inline unsigned pgrid(int nitems, int cap) {
+    return (unsigned)(nitems < cap ? (nitems < 1 ? 1 : nitems) : cap);
+}
+
+int pow2ceil(int v) {
+    int w = 1;
+    while (w < v) w <<= 1;
+    return w;
+}
+
+template <class T>
+mm_status upload_vec(DevBuf &b, const std::vector<T> &v) {
+    if (v.empty()) return MM_OK;
+    MM_TRY(dev_alloc(b, v.size() * sizeof(T)));
+    MM_HIP_TRY(hipMemcpy(b.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return MM_OK;
+}
+
+}  // namespace
+}  // namespace mm
+
+using namespace mm;
+
+struct mm_solver_s {
+    mm_plan plan = nullptr;
+    int W = 1, ncols = 1, fe = 0, d = 1;
+    double sigma2 = 0.0, rtol = 0.0;
+    DevBuf buf;
+    CgDesc desc{};
+    DevBuf ws;                       // sweep workspaces (aggregates, partial slabs)
+    double *agg = nullptr, *part = nullptr;
+    bool batchable = true;           // all passes fit one group: may join batches
+    int64_t iters = 0;
+    mm_solver_batch self = nullptr;  // batch of one for solitary iterations
+};
+
+struct mm_solver_batch_s {
+    std::vector<mm_solver> members;
+    std::vector<SweepBatch> sweeps;      // one per distinct width among the members
+    DevBuf cg_desc, items_blk, items_chunk, status;
+    int n_blk = 0, n_chunk = 0;
+    bool plain = false;                  // lone solver too large for one pass group
+    hipStream_t bs = nullptr;            // private stream for graph capture and replay
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int graph_iters = 0;
+    int use_graph = 1;
+    int grid_cap = 2048;                 // persistent grid of the CG step kernels
+    int wg_per_cu = 8;                   // persistent sweep grids: workgroups per compute unit
+};
+
+namespace mm {
+namespace {
+
+// Enqueue `iters` CG iterations of every member of the batch on stream s.
+mm_status batch_enqueue(mm_solver_batch b, int iters, hipStream_t s) {
+    const CgDesc *ds = static_cast<const CgDesc *>(b->cg_desc.ptr);
+    const int2 *ib = static_cast<const int2 *>(b->items_blk.ptr);
+    const int2 *ic = static_cast<const int2 *>(b->items_chunk.ptr);
+    const int nsol = (int)b->members.size();
+    for (int it = 0; it < iters; ++it) {
+        if (b->plain) {
+            mm_solver m = b->members[0];
+            MM_TRY(sweep_all(m->plan, m->desc.P, m->desc.Y, m->W, rhs_block(m->plan->kernel, m->d, m->W), s));
+        } else {
+            for (SweepBatch &sb : b->sweeps) MM_TRY(sweep_batch_run(sb, s));
+        }
+        hipLaunchKernelGGL(cg_apply_b, dim3(pgrid(b->n_blk, b->grid_cap)), dim3(BS), 0, s, ds, ib, b->n_blk);
+        hipLaunchKernelGGL(cg_alpha_b, dim3(pgrid(nsol, 1024)), dim3(BS), 0, s, ds, nsol);
+        hipLaunchKernelGGL(cg_update_b, dim3(pgrid(b->n_blk, b->grid_cap)), dim3(BS), 0, s, ds, ib, b->n_blk);
+        if (it == iters - 1)  // count the columns still active after the last iteration
+            hipLaunchKernelGGL(cg_reset_active_b, dim3(pgrid((nsol + BS - 1) / BS, 64)), dim3(BS), 0, s, ds, nsol);
+        hipLaunchKernelGGL(cg_beta_b, dim3(pgrid(nsol, 1024)), dim3(BS), 0, s, ds, nsol);
+        hipLaunchKernelGGL(cg_dir_b, dim3(pgrid(b->n_chunk, b->grid_cap)), dim3(BS), 0, s, ds, ic, b->n_chunk);
+    }
+    hipLaunchKernelGGL(cg_collect_b, dim3(pgrid((nsol + BS - 1) / BS, 64)), dim3(BS), 0, s, ds, nsol,
+                       static_cast<int2 *>(b->status.ptr));
+    MM_HIP_TRY(hipGetLastError());
+    return MM_OK;
+}
+
+mm_status batch_build(mm_solver_batch b) {
+    std::vector<CgDesc> descs;
+    std::vector<int2> ib, ic;
+    std::vector<int> widths;
+    for (size_t k = 0; k < b->members.size(); ++k) {
+        mm_solver s = b->members[k];
+        if (!s->batchable) {
+            if (b->members.size() > 1) {
+                set_error("solver %zu is too large to share a batch (its passes exceed one group)", k);
+                return MM_ERR_ARG;
+            }
+            b->plain = true;
+        }
+        size_t w = 0;
+        while (w < widths.size() && widths[w] != s->W) ++w;
+        if (w == widths.size()) widths.push_back(s->W);
+        descs.push_back(s->desc);
+        for (int blk = 0; blk < NRED; ++blk) ib.push_back(make_int2((int)k, blk));
+        const int64_t nch = (s->desc.n * s->W + CHUNK - 1) / CHUNK;
+        for (int64_t c = 0; c < nch; ++c) ic.push_back(make_int2((int)k, (int)c));
+    }
+    if (descs.empty()) return MM_OK;
+    if (!b->plain) {
+        b->sweeps.resize(widths.size());
+        for (size_t w = 0; w < widths.size(); ++w) {
+            std::vector<BatchEntry> ent;
+            const mm_solver *first = nullptr;
+            for (const mm_solver &s : b->members)
+                if (s->W == widths[w]) {
+                    if (!first) first = &s;
+                    ent.push_back(BatchEntry{s->plan, s->desc.P, s->desc.Y, s->agg, s->part});
+                }
+            const int WB = rhs_block((*first)->plan->kernel, (*first)->d, widths[w]);
+            MM_TRY(sweep_batch_build(ent, widths[w], WB, b->sweeps[w]));
+            b->sweeps[w].grid_per_cu = b->wg_per_cu;
+        }
+    }
+    MM_TRY(upload_vec(b->cg_desc, descs));
+    MM_TRY(upload_vec(b->items_blk, ib));
+    MM_TRY(upload_vec(b->items_chunk, ic));
+    b->n_blk = (int)ib.size();
+    b->n_chunk = (int)ic.size();
+    MM_TRY(dev_alloc(b->status, b->members.size() * sizeof(int2)));
+    return MM_OK;
+}
+
+void batch_free(mm_solver_batch b) {
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    for (SweepBatch &sb : b->sweeps) sweep_batch_free(sb);
+    b->sweeps.clear();
+    dev_free(b->cg_desc);
+    dev_free(b->items_blk);
+    dev_free(b->items_chunk);
+    dev_free(b->status);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->bs) (void)hipStreamDestroy(b->bs);
+}
+
+}  // namespace
+
+mm_status solver_batch_iterate(mm_solver_batch b, int iters, hipStream_t user) {
+    if (b->members.empty() || iters < 1) return MM_OK;
+    if (!b->use_graph) {
+        MM_TRY(batch_enqueue(b, iters, user));
+    } else {
+        if (!b->bs) {
+            MM_HIP_TRY(hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking));
+            MM_HIP_TRY(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+            MM_HIP_TRY(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+        }
+        if (!b->graph || b->graph_iters != iters) {
+            if (b->graph) (void)hipGraphExecDestroy(b->graph);
+            b->graph = nullptr;
+            hipGraph_t g = nullptr;
+            MM_HIP_TRY(hipStreamBeginCapture(b->bs, hipStreamCaptureModeThreadLocal));
+            mm_status st = batch_enqueue(b, iters, b->bs);
+            hipError_t e = hipStreamEndCapture(b->bs, &g);
+            if (st != MM_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess) {
+                set_error("graph capture failed: %s", hipGetErrorString(e));
+                return MM_ERR_HIP;
+            }
+            e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                set_error("graph instantiation failed: %s", hipGetErrorString(e));
+                b->graph = nullptr;
+                return MM_ERR_HIP;
+            }
+            b->graph_iters = iters;
+        }
+        MM_HIP_TRY(hipEventRecord(b->ev_in, user));
+        MM_HIP_TRY(hipStreamWaitEvent(b->bs, b->ev_in, 0));
+        MM_HIP_TRY(hipGraphLaunch(b->graph, b->bs));
+        MM_HIP_TRY(hipEventRecord(b->ev_out, b->bs));
+        MM_HIP_TRY(hipStreamWaitEvent(user, b->ev_out, 0));
+    }
+    for (mm_solver s : b->members) s->iters += iters;
+    return MM_OK;
+}
+
+}  // namespace mm
+
+// ---------------------------------------------------------------------------
+// helpers shared by the C entry points
+// ---------------------------------------------------------------------------
+namespace {
+
+mm_status check_solve_args(mm_plan plan, double sigma2, double rtol) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return MM_ERR_ARG;
+    }
+    if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) {
+        set_error("sigma2 must be positive and finite");
+        return MM_ERR_ARG;
+    }
+    if (!(rtol > 0.0) || !std::isfinite(rtol)) {
+        set_error("rtol must be positive and finite");
+        return MM_ERR_ARG;
+    }
+    const KParams kp = kparams(plan->kernel, plan->d);
+    if (!kp.prod && plan->d >= 2 && kp.P >= 2) {
+        set_error("the L1 Matern form with nu >= 3/2 in d >= 2 is not positive definite; use the product form");
+        return MM_ERR_NOTPD;
+    }
+    return MM_OK;
+}
+
+// Solver with W columns whose right-hand sides are filled by `fill` into B.
+template <class F>
+mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol, hipStream_t s, F &&fill,
+                     mm_solver *out) {
+    const int64_t n = plan->n;
+    const int R = rhs_block(plan->kernel, plan->d, ncols);
+    const int W = pow2ceil(ncols > R ? ncols : R);
+    mm_solver sv = new (std::nothrow) mm_solver_s();
+    if (!sv) {
+        set_error("host allocation failed");
+        return MM_ERR_NOMEM;
+    }
+    sv->plan = plan;
+    sv->W = W;
+    sv->ncols = ncols;
+    sv->fe = fe;
+    sv->d = plan->d;
+    sv->sigma2 = sigma2;
+    sv->rtol = rtol;
+    const size_t vec = (size_t)n * W;
+    size_t agg_b = 0, part_b = 0;
+    sv->batchable = sweep_batch_bytes(plan, W, &agg_b, &part_b);
+    mm_status st = dev_alloc(sv->buf, (6 * vec + (size_t)NRED * W * 8 + (size_t)W * NS + 8) * sizeof(double));
+    if (st == MM_OK) {
+        if (sv->batchable) {
+            st = dev_alloc(sv->ws, agg_b + part_b);
+            if (st == MM_OK) {
+                sv->agg = static_cast<double *>(sv->ws.ptr);
+                sv->part = reinterpret_cast<double *>(static_cast<char *>(sv->ws.ptr) + agg_b);
+            }
+        } else {
+            st = ensure_work(plan, W);  // a lone solver sweeps in the plan's own work buffers
+        }
+    }
+    if (st != MM_OK) {
+        dev_free(sv->ws);
+        dev_free(sv->buf);
+        delete sv;
+        return st;
+    }
+    double *base = static_cast<double *>(sv->buf.ptr);
+    CgDesc &d = sv->desc;
+    double *Bm = base;
+    d.B = Bm;
+    d.X = base + vec;
+    d.R = base + 2 * vec;
+    d.P = base + 3 * vec;
+    d.Q = base + 4 * vec;
+    d.Y = base + 5 * vec;
+    d.part = base + 6 * vec;
+    d.sc = d.part + (size_t)NRED * W * 8;
+    d.flags = reinterpret_cast<int *>(d.sc + (size_t)W * NS);
+    d.n = n;
+    d.W = W;
+    d.ncols = ncols;
+    d.s2 = plan->kernel.outputscale2;
+    d.sigma2 = sigma2;
+    d.rtol = rtol;
+    fill(Bm, W);
+    // a batch of one for solitary iterations; the init runs through the batched kernels too
+    mm_solver_batch b = new (std::nothrow) mm_solver_batch_s();
+    if (!b) {
+        dev_free(sv->ws);
+        dev_free(sv->buf);
+        delete sv;
+        set_error("host allocation failed");
+        return MM_ERR_NOMEM;
+    }
+    b->members.push_back(sv);
+    b->use_graph = 0;
+    st = batch_build(b);
+    if (st == MM_OK) {
+        const CgDesc *ds = static_cast<const CgDesc *>(b->cg_desc.ptr);
+        hipLaunchKernelGGL(cg_init_b, dim3(pgrid(b->n_blk, 2048)), dim3(BS), 0, s, ds,
+                           static_cast<const int2 *>(b->items_blk.ptr), b->n_blk);
+        hipLaunchKernelGGL(cg_init_scalars_b, dim3(1), dim3(BS), 0, s, ds, 1);
+        if (hipGetLastError() != hipSuccess) {
+            set_error("solver initialisation launch failed");
+            st = MM_ERR_HIP;
+        }
+    }
+    if (st != MM_OK) {
+        batch_free(b);
+        delete b;
+        dev_free(sv->ws);
+        dev_free(sv->buf);
+        delete sv;
+        return st;
+    }
+    sv->self = b;
+    plan->nsolvers++;
+    plan->last_stream = s;
+    *out = sv;
+    return MM_OK;
+}
+
+// Host-side convergence summary from the device scalars (synchronises s).
+mm_status solver_summary(mm_solver sv, hipStream_t s, int *conv, int *brk, double *relmax, mm_solve_info *info) {
+    std::vector<double> hsc((size_t)sv->W * NS);
+    int fl[2] = {0, 0};
+    MM_HIP_TRY(hipMemcpyAsync(hsc.data(), sv->desc.sc, hsc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    MM_HIP_TRY(hipMemcpyAsync(fl, sv->desc.flags, sizeof fl, hipMemcpyDeviceToHost, s));
+    MM_HIP_TRY(hipStreamSynchronize(s));
+    int c = 0;
+    double rel = 0.0, itmax = 0.0;
+    for (int r = 0; r < sv->ncols; ++r) {
+        const double bn = hsc[r * NS + 4];
+        const double rn = hsc[r * NS + 7];
+        const double rr = bn > 0.0 ? rn / bn : 0.0;
+        if (rr > rel) rel = rr;
+        if (hsc[r * NS + 6] > itmax) itmax = hsc[r * NS + 6];
+        if (bn == 0.0 || rr <= sv->rtol) ++c;
+    }
+    *conv = c;
+    *brk = fl[1];
+    *relmax = rel;
+    if (info) {
+        info->iters = (int32_t)itmax;
+        info->converged_cols = c;
+        info->relres_max = rel;
+    }
+    return MM_OK;
+}
+
+// Iterate a single solver until convergence, breakdown or maxit.
+mm_status solver_run(mm_solver sv, int maxit, hipStream_t s) {
+    const int check_every = 8;
+    int2 st{1, 0};
+    while (sv->iters < maxit) {
+        const int k = (int)(maxit - sv->iters < check_every ? maxit - sv->iters : check_every);
+        MM_TRY(solver_batch_iterate(sv->self, k, s));
+        MM_HIP_TRY(hipMemcpyAsync(&st, sv->self->status.ptr, sizeof st, hipMemcpyDeviceToHost, s));
+        MM_HIP_TRY(hipStreamSynchronize(s));
+        if (st.y || st.x == 0) break;
+    }
+    return MM_OK;
+}
+
+// GLS from the solved columns [A^-1 y, A^-1 H] (Section 3.2) and alpha in caller order.
+mm_status solver_output(mm_solver sv, double *alpha, double *beta, hipStream_t s) {
+    mm_plan plan = sv->plan;
+    const int64_t n = plan->n;
+    const int d = plan->d;
+    const int W = sv->W;
+    const int32_t *perm = static_cast<const int32_t *>(plan->perm.ptr);
+    const double *xc = static_cast<const double *>(plan->xc.ptr);
+    if (!sv->fe) {
+        hipLaunchKernelGGL(col_out_kernel, dim3(grid1(n)), dim3(BS), 0, s, sv->desc.X, perm, n, W, 1, alpha, n);
+        MM_HIP_TRY(hipGetLastError());
+        return MM_OK;
+    }
+    const int nb = d + 1;
+    double *part = sv->desc.part;
+    hipLaunchKernelGGL(fe_gram_kernel, dim3(NRED), dim3(BS), 0, s, sv->desc.X, xc, n, d, W, part);
+    std::vector<double> hp((size_t)NRED * nb * W);
+    MM_HIP_TRY(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    MM_HIP_TRY(hipStreamSynchronize(s));
+    std::vector<double> HX((size_t)nb * W, 0.0);  // HX[i*W + j] = h_i^T X_j
+    for (int b = 0; b < NRED; ++b)
+        for (int i = 0; i < nb; ++i)
+            for (int j = 0; j < W; ++j) HX[i * W + j] += hp[((size_t)b * nb + i) * W + j];
+    double G[4][4], g[4], Lm[4][4] = {{0}}, w[4], hb[4] = {0, 0, 0, 0};
+    for (int i = 0; i < nb; ++i) {
+        g[i] = HX[i * W + 0];
+        for (int j = 0; j < nb; ++j) G[i][j] = 0.5 * (HX[i * W + 1 + j] + HX[j * W + 1 + i]);
+    }
+    for (int j = 0; j < nb; ++j) {
+        double dsum = G[j][j];
+        for (int k = 0; k < j; ++k) dsum -= Lm[j][k] * Lm[j][k];
+        if (!(dsum > 0.0)) {
+            set_error("GLS Gram matrix H^T A^-1 H is not positive definite (collinear features?)");
+            return MM_ERR_NOTPD;
+        }
+        Lm[j][j] = sqrt(dsum);
+        for (int i = j + 1; i < nb; ++i) {
+            double t = G[i][j];
+            for (int k = 0; k < j; ++k) t -= Lm[i][k] * Lm[j][k];
+            Lm[i][j] = t / Lm[j][j];
+        }
+    }
+    for (int i = 0; i < nb; ++i) {
+        double t = g[i];
+        for (int k = 0; k < i; ++k) t -= Lm[i][k] * w[k];
+        w[i] = t / Lm[i][i];
+    }
+    for (int i = nb - 1; i >= 0; --i) {
+        double t = w[i];
+        for (int k = i + 1; k < nb; ++k) t -= Lm[k][i] * hb[k];
+        hb[i] = t / Lm[i][i];
+    }
+    for (int i = 0; i < nb; ++i) beta[i] = hb[i];
+    hipLaunchKernelGGL(fe_alpha_kernel, dim3(grid1(n)), dim3(BS), 0, s, sv->desc.X, perm, n, W, nb, hb[0], hb[1],
+                       hb[2], hb[3], alpha);
+    MM_HIP_TRY(hipGetLastError());
+    return MM_OK;
+}
+
+mm_status status_of(int conv, int ncols, int brk, int iters, double rel) {
+    if (brk) {
+        set_error("conjugate gradients broke down (p^T A p <= 0)");
+        return MM_ERR_BREAKDOWN;
+    }
+    if (conv < ncols) {
+        set_error("conjugate gradients did not reach rtol in %d iterations (relres %.3e)", iters, rel);
+        return MM_ERR_NOCONV;
+    }
+    return MM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mm_status mm_solver_create(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects, double rtol,
+                           void *stream, mm_solver *out) {
+    clear_error();
+    if (!out) {
+        set_error("out is NULL");
+        return MM_ERR_ARG;
+    }
+    *out = nullptr;
+    MM_TRY(check_solve_args(plan, sigma2, rtol));
+    if (!y) {
+        set_error("y is NULL");
+        return MM_ERR_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int ncols = fixed_effects ? plan->d + 2 : 1;
+    return solver_new(plan, ncols, fixed_effects ? 1 : 0, sigma2, rtol, s,
+                      [&](double *B, int W) {
+                          hipLaunchKernelGGL(fe_rhs_kernel, dim3(grid1(plan->n)), dim3(BS), 0, s, y,
+                                             static_cast<const int32_t *>(plan->perm.ptr),
+                                             static_cast<const double *>(plan->xc.ptr), plan->n, plan->d,
+                                             fixed_effects ? 1 : 0, W, B);
+                      },
+                      out);
+}
+
+mm_status mm_solver_iterate(mm_solver solver, int32_t iters, void *stream) {
+    clear_error();
+    if (!solver || iters < 0) {
+        set_error("solver is NULL or iters < 0");
+        return MM_ERR_ARG;
+    }
+    return solver_batch_iterate(solver->self, iters, static_cast<hipStream_t>(stream));
+}
+
+mm_status mm_solver_poll(mm_solver solver, int32_t *active_cols, int32_t *breakdown, mm_solve_info *info,
+                         void *stream) {
+    clear_error();
+    if (!solver) {
+        set_error("solver is NULL");
+        return MM_ERR_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int conv = 0, brk = 0;
+    double rel = 0.0;
+    MM_TRY(solver_summary(solver, s, &conv, &brk, &rel, info));
+    if (active_cols) *active_cols = solver->ncols - conv;
+    if (breakdown) *breakdown = brk;
+    return MM_OK;
+}
+
+mm_status mm_solver_finish(mm_solver solver, double *alpha, double *beta, mm_solve_info *info, void *stream) {
+    clear_error();
+    if (!solver || !alpha || (solver->fe && !beta)) {
+        set_error("solver and alpha (and beta with fixed effects) must be non-NULL");
+        return MM_ERR_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int conv = 0, brk = 0;
+    double rel = 0.0;
+    mm_solve_info inf{};
+    MM_TRY(solver_summary(solver, s, &conv, &brk, &rel, &inf));
+    if (info) *info = inf;
+    MM_TRY(solver_output(solver, alpha, beta, s));
+    MM_HIP_TRY(hipStreamSynchronize(s));
+    return status_of(conv, solver->ncols, brk, inf.iters, rel);
+}
+
+mm_status mm_solver_destroy(mm_solver solver) {
+    if (!solver) return MM_OK;
+    (void)hipDeviceSynchronize();
+    if (solver->self) {
+        batch_free(solver->self);
+        delete solver->self;
+    }
+    solver->plan->nsolvers--;
+    dev_free(solver->ws);
+    dev_free(solver->buf);
+    delete solver;
+    return MM_OK;
+}
+
+mm_status mm_solver_batch_create(mm_solver *solvers, int32_t count, int32_t use_graph, mm_solver_batch *out) {
+    clear_error();
+    if (!out || !solvers || count < 1) {
+        set_error("solvers, count >= 1 and out are required");
+        return MM_ERR_ARG;
+    }
+    *out = nullptr;
+    mm_solver_batch b = new (std::nothrow) mm_solver_batch_s();
+    if (!b) {
+        set_error("host allocation failed");
+        return MM_ERR_NOMEM;
+    }
+    for (int i = 0; i < count; ++i) {
+        if (!solvers[i]) {
+            delete b;
+            set_error("solver %d is NULL", i);
+            return MM_ERR_ARG;
+        }
+        b->members.push_back(solvers[i]);
+    }
+    b->use_graph = use_graph ? 1 : 0;
+    mm_status st = batch_build(b);
+    if (st != MM_OK) {
+        batch_free(b);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return MM_OK;
+}
+
+mm_status mm_solver_batch_set_schedule(mm_solver_batch batch, int32_t sweep_wg_per_cu, int32_t cg_grid) {
+    clear_error();
+    if (!batch || sweep_wg_per_cu < 1 || cg_grid < 1) {
+        set_error("batch is NULL or schedule out of range");
+        return MM_ERR_ARG;
+    }
+    batch->wg_per_cu = sweep_wg_per_cu;
+    for (SweepBatch &sb : batch->sweeps) sb.grid_per_cu = sweep_wg_per_cu;
+    batch->grid_cap = cg_grid;
+    if (batch->graph) (void)hipGraphExecDestroy(batch->graph);
+    batch->graph = nullptr;
+    return MM_OK;
+}
+
+mm_status mm_solver_batch_iterate(mm_solver_batch batch, int32_t iters, void *stream) {
+    clear_error();
+    if (!batch || iters < 0) {
+        set_error("batch is NULL or iters < 0");
+        return MM_ERR_ARG;
+    }
+    return solver_batch_iterate(batch, iters, static_cast<hipStream_t>(stream));
+}
+
+mm_status mm_solver_batch_poll(mm_solver_batch batch, int32_t *active, void *stream) {
+    clear_error();
+    if (!batch || !active) {
+        set_error("batch and active are required");
+        return MM_ERR_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<int2> st(batch->members.size());
+    MM_HIP_TRY(hipMemcpyAsync(st.data(), batch->status.ptr, st.size() * sizeof(int2), hipMemcpyDeviceToHost, s));
+    MM_HIP_TRY(hipStreamSynchronize(s));
+    for (size_t k = 0; k < st.size(); ++k) active[k] = st[k].y ? -1 : st[k].x;
+    return MM_OK;
+}
+
+mm_status mm_solver_batch_destroy(mm_solver_batch batch) {
+    if (!batch) return MM_OK;
+    (void)hipDeviceSynchronize();
+    batch_free(batch);
+    delete batch;
+    return MM_OK;
+}
+
+mm_status gp_cg_solve(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects, double rtol,
+                      int32_t maxit, double *alpha, double *beta, mm_solve_info *info, void *stream) {
+    clear_error();
+    MM_TRY(check_solve_args(plan, sigma2, rtol));
+    if (!y || !alpha) {
+        set_error("y and alpha must be non-NULL");
+        return MM_ERR_ARG;
+    }
+    if (fixed_effects && !beta) {
+        set_error("beta must be non-NULL when fixed_effects is set");
+        return MM_ERR_ARG;
+    }
+    if (maxit < 1) {
+        set_error("maxit must be >= 1");
+        return MM_ERR_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    mm_solver sv = nullptr;
+    MM_TRY(mm_solver_create(plan, y, sigma2, fixed_effects, rtol, stream, &sv));
+    mm_status st = solver_run(sv, maxit, s);
+    if (st == MM_OK) st = mm_solver_finish(sv, alpha, beta, info, stream);
+    if (st != MM_OK && st != MM_ERR_NOCONV && st != MM_ERR_BREAKDOWN) {
+        mm_solver_destroy(sv);
+        return st;
+    }
+    std::string msg = last_error_str();
+    mm_solver_destroy(sv);
+    if (st != MM_OK) set_error("%s", msg.c_str());
+    return st;
+}
+
+mm_status gp_cg_solve_multi(mm_plan plan, const double *Bc, int64_t ldb, int32_t nrhs, double sigma2, double rtol,
+                            int32_t maxit, double *Xc, int64_t ldx, mm_solve_info *info, void *stream) {
+    clear_error();
+    MM_TRY(check_solve_args(plan, sigma2, rtol));
+    if (!Bc || !Xc) {
+        set_error("B and X must be non-NULL");
+        return MM_ERR_ARG;
+    }
+    if (nrhs < 1 || nrhs > 64 || maxit < 1) {
+        set_error("nrhs must be in [1, 64] and maxit >= 1");
+        return MM_ERR_ARG;
+    }
+    if (ldb < plan->n || ldx < plan->n) {
+        set_error("ldb and ldx must be >= n");
+        return MM_ERR_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    mm_solver sv = nullptr;
+    MM_TRY(solver_new(plan, nrhs, 0, sigma2, rtol, s,
+                      [&](double *B, int W) {
+                          hipLaunchKernelGGL(gather_cols_kernel, dim3(grid1(plan->n * W)), dim3(BS), 0, s, Bc, ldb,
+                                             nrhs, static_cast<const int32_t *>(plan->perm.ptr), plan->n, B, W);
+                      },
+                      &sv));
+    mm_status st = solver_run(sv, maxit, s);
+    int conv = 0, brk = 0;
+    double rel = 0.0;
+    mm_solve_info inf{};
+    if (st == MM_OK) st = solver_summary(sv, s, &conv, &brk, &rel, &inf);
+    if (st == MM_OK) {
+        if (info) *info = inf;
+        hipLaunchKernelGGL(col_out_kernel, dim3(grid1(plan->n * nrhs)), dim3(BS), 0, s, sv->desc.X,
+                           static_cast<const int32_t *>(plan->perm.ptr), plan->n, sv->W, nrhs, Xc, ldx);
+        if (hipStreamSynchronize(s) != hipSuccess) {
+            set_error("HIP error after the solve");
+            st = MM_ERR_HIP;
+        } else {
+            st = status_of(conv, nrhs, brk, inf.iters, rel);
+        }
+    }
+    std::string msg = last_error_str();
+    mm_solver_destroy(sv);
+    if (st != MM_OK) set_error("%s", msg.c_str());
+    return st;
+}
+
+}  // extern "C"

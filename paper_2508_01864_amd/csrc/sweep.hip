@@ -32,6 +32,8 @@
 
 #include "mm_internal.h"
 
+#include <cstdlib>
+
 namespace mm {
 namespace {
 
@@ -98,7 +100,8 @@ struct SweepArgs {
     const int32_t *xt;     // indices of the passes whose segments span several tiles
     const double *vin;     // n x W point-major canonical input
     double *ypart;         // G slabs of n x W: one partial result per pass of the group
-    double *agg;           // tile aggregates [2 dirs][G][ntile][nrb][NHALF][NSLOT]
+    double *agg;           // tile aggregates [2 dirs][G][ntile][W][NHALF][NSLOT]
+    double *car;           // tile carries, same layout as agg
     double *anc;           // tile anchors [2 dirs][G][ntile]
     int64_t n;
     int64_t ntile;
@@ -106,18 +109,27 @@ struct SweepArgs {
     int g0;                // first pass of the group
     int k0;                // first entry of xt inside the group
     int G;                 // passes in the group
+    int nslice;            // carry-scan slices (sub-sweep x class x row x column)
+    const int4 *segs;      // the plan's cross-tile segments (pass, first tile, end tile)
     double a;
 };
 
-// Static configuration of a sweep instance.
-template <int D_, int P_, bool PROD_, int R_, int E_>
+// Static configuration of a sweep instance.  A workgroup is one wave.  Its 64
+// lanes are WCOL right-hand-side columns times RUNS runs: lane (run, col)
+// scans the E consecutive positions run*E .. run*E+E-1 of a tile of
+// T = RUNS*E positions for one column.  The runs of a column are joined by a
+// lane scan of log2(RUNS) steps; tiles of a segment are joined through the
+// tile aggregates and the tile carry scan.  The tile's geometry is staged once
+// in LDS and read by every column (broadcast).
+template <int D_, int P_, bool PROD_, int WCOL_, int E_>
 struct Cfg {
     static constexpr int D = D_;
     static constexpr int P = P_;
     static constexpr bool PROD = PROD_;
-    static constexpr int R = R_;
+    static constexpr int WCOL = WCOL_;
+    static constexpr int RUNS = WAVE / WCOL;
     static constexpr int E = E_;
-    static constexpr int T = WG * E;                       // tile positions
+    static constexpr int T = RUNS * E;                       // tile positions
     static constexpr int NTH = PROD ? IPow<P, D - 1>::v : 1; // non-scan channel rows
     // source classes (orthants of the non-scan coordinates) and how many
     // sub-sweeps they are split over so that one state fits the register file
@@ -125,13 +137,15 @@ struct Cfg {
     static constexpr int FULLSLOT = NCLS_ALL * NTH * P;
     static constexpr int NHALF = (D == 3) ? (FULLSLOT <= 16 ? 1 : (FULLSLOT <= 32 ? 2 : 4)) : 1;
     static constexpr int NCLS = NCLS_ALL / NHALF;
-    static constexpr int NSLOT = NCLS * NTH * P * R;       // doubles per state
-    static constexpr int G = 2 * (D - 1);                  // staged geometry doubles
+    static constexpr int NSLOT = NCLS * NTH * P;             // doubles per state
+    static constexpr int G = 2 * (D - 1);                    // staged geometry doubles
+    static constexpr bool REGOUT = E * NSLOT <= 64;          // keep targets in registers
+    static constexpr int BLK = E < 8 ? E : 8;                // prefetch block of long runs
 };
 
 template <class C>
 struct State {
-    double s[C::NCLS][C::NTH][C::P][C::R];
+    double s[C::NCLS][C::NTH][C::P];
 
     __device__ __forceinline__ void zero() {
 #pragma unroll
@@ -139,9 +153,7 @@ struct State {
 #pragma unroll
             for (int h = 0; h < C::NTH; ++h)
 #pragma unroll
-                for (int m = 0; m < C::P; ++m)
-#pragma unroll
-                    for (int r = 0; r < C::R; ++r) s[c][h][m][r] = 0.0;
+                for (int m = 0; m < C::P; ++m) s[c][h][m] = 0.0;
     }
 
     // this <- M(E, t) this
@@ -150,13 +162,11 @@ struct State {
 #pragma unroll
         for (int c = 0; c < C::NCLS; ++c)
 #pragma unroll
-            for (int h = 0; h < C::NTH; ++h)
-#pragma unroll
-                for (int r = 0; r < C::R; ++r) {
-                    if constexpr (C::P == 3) s[c][h][2][r] = E * (s[c][h][2][r] + t * s[c][h][1][r] + t2 * s[c][h][0][r]);
-                    if constexpr (C::P >= 2) s[c][h][1][r] = E * (s[c][h][1][r] + t * s[c][h][0][r]);
-                    s[c][h][0][r] = E * s[c][h][0][r];
-                }
+            for (int h = 0; h < C::NTH; ++h) {
+                if constexpr (C::P == 3) s[c][h][2] = E * (s[c][h][2] + t * s[c][h][1] + t2 * s[c][h][0]);
+                if constexpr (C::P >= 2) s[c][h][1] = E * (s[c][h][1] + t * s[c][h][0]);
+                s[c][h][0] = E * s[c][h][0];
+            }
     }
 
     // this <- this + M(E, t) o
@@ -165,17 +175,15 @@ struct State {
 #pragma unroll
         for (int c = 0; c < C::NCLS; ++c)
 #pragma unroll
-            for (int h = 0; h < C::NTH; ++h)
-#pragma unroll
-                for (int r = 0; r < C::R; ++r) {
-                    if constexpr (C::P == 3) s[c][h][2][r] += E * (o.s[c][h][2][r] + t * o.s[c][h][1][r] + t2 * o.s[c][h][0][r]);
-                    if constexpr (C::P >= 2) s[c][h][1][r] += E * (o.s[c][h][1][r] + t * o.s[c][h][0][r]);
-                    s[c][h][0][r] += E * o.s[c][h][0][r];
-                }
+            for (int h = 0; h < C::NTH; ++h) {
+                if constexpr (C::P == 3) s[c][h][2] += E * (o.s[c][h][2] + t * o.s[c][h][1] + t2 * o.s[c][h][0]);
+                if constexpr (C::P >= 2) s[c][h][1] += E * (o.s[c][h][1] + t * o.s[c][h][0]);
+                s[c][h][0] += E * o.s[c][h][0];
+            }
     }
 
-    __device__ __forceinline__ double *flat() { return &s[0][0][0][0]; }
-    __device__ __forceinline__ const double *flat() const { return &s[0][0][0][0]; }
+    __device__ __forceinline__ double *flat() { return &s[0][0][0]; }
+    __device__ __forceinline__ const double *flat() const { return &s[0][0][0]; }
 };
 
 // Geometry of one element (source and target vectors) derived from its staged offsets.
@@ -184,7 +192,7 @@ struct State {
 //   L1 form:      f[m] = s_m(W), g[m] = g_m(W) with W the summed offset.
 template <class C>
 struct ElemVec {
-    double f[C::NTH][C::PROD ? 1 : C::P];
+    double f[C::PROD ? C::NTH : C::P];
     double g[C::PROD ? C::NTH : C::P];
 };
 
@@ -193,7 +201,7 @@ __device__ __forceinline__ void elem_vectors(const double *geo, ElemVec<C> &ev) 
     constexpr int P = C::P;
     if constexpr (C::D == 1) {  // no other coordinate: unit source and target
         static_assert(C::D != 1 || C::PROD, "d = 1 uses the product path");
-        ev.f[0][0] = 1.0;
+        ev.f[0] = 1.0;
         ev.g[0] = 1.0;
         return;
     } else if constexpr (C::PROD) {
@@ -215,7 +223,7 @@ __device__ __forceinline__ void elem_vectors(const double *geo, ElemVec<C> &ev) 
                 fs *= sv[k][idx];
                 gs *= gv[k][idx];
             }
-            ev.f[th][0] = fs;
+            ev.f[th] = fs;
             ev.g[th] = gs;
         }
     } else {
@@ -226,64 +234,52 @@ __device__ __forceinline__ void elem_vectors(const double *geo, ElemVec<C> &ev) 
             E *= geo[2 * k];
             t += geo[2 * k + 1];
         }
-        double sv[P], gv[P];
-        src_vec<P>(E, t, sv);
-        tgt_vec<P>(E, t, gv);
-#pragma unroll
-        for (int m = 0; m < P; ++m) {
-            ev.f[0][m] = sv[m];
-            ev.g[m] = gv[m];
-        }
+        src_vec<P>(E, t, ev.f);
+        tgt_vec<P>(E, t, ev.g);
     }
 }
 
 // S[cls] += v * source vector.  The class is selected through the value
 // (v or 0) rather than a branch so the state stays in registers.
 template <class C>
-__device__ __forceinline__ void add_source(State<C> &S, int cls, const ElemVec<C> &ev,
-                                           const double (&v)[C::R]) {
+__device__ __forceinline__ void add_source(State<C> &S, int cls, const ElemVec<C> &ev, double v) {
 #pragma unroll
     for (int c = 0; c < C::NCLS; ++c) {
+        const double vc = (c == cls) ? v : 0.0;
 #pragma unroll
-        for (int r = 0; r < C::R; ++r) {
-            const double vc = (c == cls) ? v[r] : 0.0;
+        for (int h = 0; h < C::NTH; ++h) {
+            if constexpr (C::PROD) {
+                S.s[c][h][0] += ev.f[h] * vc;
+            } else {
 #pragma unroll
-            for (int h = 0; h < C::NTH; ++h) {
-                if constexpr (C::PROD) {
-                    S.s[c][h][0][r] += ev.f[h][0] * vc;
-                } else {
-#pragma unroll
-                    for (int m = 0; m < C::P; ++m) S.s[c][h][m][r] += ev.f[h][m] * vc;
-                }
+                for (int m = 0; m < C::P; ++m) S.s[c][h][m] += ev.f[m] * vc;
             }
         }
     }
 }
 
-// out += target vector . S[cls]
+// target vector . S[cls]
 template <class C>
-__device__ __forceinline__ void read_target(const State<C> &S, int cls, const ElemVec<C> &ev,
-                                            double (&out)[C::R]) {
+__device__ __forceinline__ double read_target(const State<C> &S, int cls, const ElemVec<C> &ev) {
+    double out = 0.0;
 #pragma unroll
     for (int c = 0; c < C::NCLS; ++c) {
+        double acc = 0.0;
 #pragma unroll
-        for (int r = 0; r < C::R; ++r) {
-            double acc = 0.0;
+        for (int h = 0; h < C::NTH; ++h) {
+            if constexpr (C::PROD) {
+                double row = S.s[c][h][0];
 #pragma unroll
-            for (int h = 0; h < C::NTH; ++h) {
-                if constexpr (C::PROD) {
-                    double row = S.s[c][h][0][r];
+                for (int m = 1; m < C::P; ++m) row += coef<C::P>(m) * S.s[c][h][m];
+                acc += ev.g[h] * row;
+            } else {
 #pragma unroll
-                    for (int m = 1; m < C::P; ++m) row += coef<C::P>(m) * S.s[c][h][m][r];
-                    acc += ev.g[h] * row;
-                } else {
-#pragma unroll
-                    for (int m = 0; m < C::P; ++m) acc += ev.g[m] * S.s[c][h][m][r];
-                }
+                for (int m = 0; m < C::P; ++m) acc += ev.g[m] * S.s[c][h][m];
             }
-            out[r] += (c == cls) ? acc : 0.0;
         }
+        out += (c == cls) ? acc : 0.0;
     }
+    return out;
 }
 
 // Source / target class of an element in sub-sweep `hh`.  d = 2: the x1 half
@@ -320,18 +316,9 @@ __device__ __forceinline__ void classes(int flags, int hh, int &scls, int &tcls)
     }
 }
 
-// Exchange a state with another lane (DS permute of the 64-bit halves).
-template <class C>
-__device__ __forceinline__ void shfl_up_state(const State<C> &in, State<C> &out, int delta) {
-#pragma unroll
-    for (int i = 0; i < C::NSLOT; ++i) out.flat()[i] = __shfl_up(in.flat()[i], delta, WAVE);
-}
-template <class C>
-__device__ __forceinline__ void shfl_down_state(const State<C> &in, State<C> &out, int delta) {
-#pragma unroll
-    for (int i = 0; i < C::NSLOT; ++i) out.flat()[i] = __shfl_down(in.flat()[i], delta, WAVE);
-}
-
+// Staged tile in LDS, stored [element of the run][run]: lanes of different
+// runs read different banks, lanes of the same run (different columns) read
+// the same address (broadcast).  Local position j lives at slot(j).
 template <class C>
 struct Smem {
     int32_t c[C::T];
@@ -339,29 +326,31 @@ struct Smem {
     double xs[C::T];
     double est[C::T];
     double geo[C::G > 0 ? C::G : 1][C::T];
-    double waveF[NWAVE][C::NSLOT];
-    double waveFx[NWAVE];
-    double car[2][C::NSLOT];   // carry from the other tiles of the segment, per direction
-    double carx[2];            // its anchor
-    int carhas[2];
 };
 
-// Stage the tile's positions: indices, flags, scan coordinate and offsets.
+template <class C>
+__device__ __forceinline__ int slot(int j) {
+    return (j % C::E) * C::RUNS + j / C::E;
+}
+
+// Stage the tile's positions: indices, flags, scan coordinate, offsets and
+// the decay between consecutive positions.
 template <class C>
 __device__ __forceinline__ void stage_tile(const SweepArgs &A, const PassDev &ps, Smem<C> &sm,
                                            int64_t p0) {
     const int64_t n = A.n;
     const int64_t segmask = (int64_t(1) << ps.seg_log2) - 1;
-    for (int j = threadIdx.x; j < C::T; j += WG) {
+    for (int j = threadIdx.x; j < C::T; j += WAVE) {
         const int64_t p = p0 + j;
         const int64_t pc = p < n ? p : n - 1;
         int flags = p < n ? F_VALID : 0;
         if (p < n && (p & segmask) == 0) flags |= F_SEGSTART;
         if (p >= n - 1 || ((p + 1) & segmask) == 0) flags |= F_SEGEND;
+        const int sj = slot<C>(j);
         int64_t c;
         if constexpr (C::D == 1) {
             c = pc;
-            sm.xs[j] = A.xc[c];
+            sm.xs[sj] = A.xc[c];
         } else if constexpr (C::D == 2) {
             c = ps.ord[pc];
             const int l = ps.l1;
@@ -370,9 +359,9 @@ __device__ __forceinline__ void stage_tile(const SweepArgs &A, const PassDev &ps
             if (sp > n - 1) sp = n - 1;
             const double w = fabs(A.xc[c] - A.xc[sp]);
             const double t = A.a * w;
-            sm.geo[0][j] = exp(-t);
-            sm.geo[1][j] = t;
-            sm.xs[j] = A.xc[n + c];
+            sm.geo[0][sj] = exp(-t);
+            sm.geo[1][sj] = t;
+            sm.xs[sj] = A.xc[n + c];
         } else {
             const int64_t q = ps.ord[pc];
             c = ps.ord2[q];
@@ -386,324 +375,453 @@ __device__ __forceinline__ void stage_tile(const SweepArgs &A, const PassDev &ps
             const double w1 = fabs(A.xc[c] - A.xc[sp1]);
             const double w2 = fabs(A.xc[n + c] - A.xc[n + ps.ord2[sq2]]);
             const double t1 = A.a * w1, t2 = A.a * w2;
-            sm.geo[0][j] = exp(-t1);
-            sm.geo[1][j] = t1;
-            sm.geo[2][j] = exp(-t2);
-            sm.geo[3][j] = t2;
-            sm.xs[j] = A.xc[2 * n + c];
+            sm.geo[0][sj] = exp(-t1);
+            sm.geo[1][sj] = t1;
+            sm.geo[2][sj] = exp(-t2);
+            sm.geo[3][sj] = t2;
+            sm.xs[sj] = A.xc[2 * n + c];
         }
-        sm.c[j] = (int32_t)c;
-        sm.flags[j] = flags;
+        sm.c[sj] = (int32_t)c;
+        sm.flags[sj] = flags;
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < C::T; j += WG) {
+    for (int j = threadIdx.x; j < C::T; j += WAVE) {
+        const int sj = slot<C>(j);
         double e = 1.0;
-        if (j > 0 && !(sm.flags[j] & F_SEGSTART)) e = exp(-A.a * (sm.xs[j] - sm.xs[j - 1]));
-        sm.est[j] = e;
+        if (j > 0 && !(sm.flags[sj] & F_SEGSTART)) e = exp(-A.a * (sm.xs[sj] - sm.xs[slot<C>(j - 1)]));
+        sm.est[sj] = e;
     }
     __syncthreads();
 }
 
 template <class C>
-__device__ __forceinline__ void load_v(const SweepArgs &A, int c, int rb, double (&v)[C::R]) {
-    const double *src = A.vin + (int64_t)c * A.W + rb * C::R;
+__device__ __forceinline__ void load_geo(const Smem<C> &sm, int sj, double (&geo)[C::G > 0 ? C::G : 1]) {
 #pragma unroll
-    for (int r = 0; r < C::R; ++r) v[r] = src[r];
+    for (int k = 0; k < C::G; ++k) geo[k] = sm.geo[k][sj];
 }
 
 template <class C>
-__device__ __forceinline__ void load_geo(const Smem<C> &sm, int j, double (&geo)[C::G > 0 ? C::G : 1]) {
+__device__ __forceinline__ int64_t agg_index(const SweepArgs &A, int dir, int pl, int64_t tile, int col,
+                                             int hh) {
+    return (((((int64_t)dir * A.G + pl) * A.ntile + tile) * A.W + col) * C::NHALF + hh) * C::NSLOT;
+}
+
+// F <- F + M(|xto - x of the partner|) F(partner), partner o runs away in the
+// scan direction (the same column's lane o*WCOL lanes up or down).
+template <class C, bool UP>
+__device__ __forceinline__ void scan_step(State<C> &F, int o, double xto, bool ok, double a) {
+    const int dl = o * C::WCOL;
+    const double xp = UP ? __shfl_up(xto, dl, WAVE) : __shfl_down(xto, dl, WAVE);
+    const double t = a * (UP ? xto - xp : xp - xto);
+    const double E = exp(-t);
+    const double t2 = 0.5 * t * t;
 #pragma unroll
-    for (int k = 0; k < C::G; ++k) geo[k] = sm.geo[k][j];
+    for (int c = 0; c < C::NCLS; ++c)
+#pragma unroll
+        for (int h = 0; h < C::NTH; ++h) {
+            double q[C::P];
+#pragma unroll
+            for (int m = 0; m < C::P; ++m)
+                q[m] = UP ? __shfl_up(F.s[c][h][m], dl, WAVE) : __shfl_down(F.s[c][h][m], dl, WAVE);
+            if (ok) {
+                if constexpr (C::P == 3) F.s[c][h][2] += E * (q[2] + t * q[1] + t2 * q[0]);
+                if constexpr (C::P >= 2) F.s[c][h][1] += E * (q[1] + t * q[0]);
+                F.s[c][h][0] += E * q[0];
+            }
+        }
 }
 
-template <class C>
-__device__ __forceinline__ int64_t agg_index(const SweepArgs &A, int dir, int pl, int tile, int rb,
-                                             int nrb, int hh) {
-    return (((((int64_t)dir * A.G + pl) * A.ntile + tile) * nrb + rb) * C::NHALF + hh) * C::NSLOT;
-}
-
-// One scan direction over this thread's run of E positions, with every carry.
-// DIR 0: forward (positions in increasing order, sources at or before the
-//        target in the last coordinate: delta_last = +1);
-// DIR 1: backward (decreasing order, sources strictly after: delta_last = -1).
-// MODE 0 accumulates target values into outv; MODE 1 writes the tile's total.
-template <class C, int MODE, int DIR>
-__device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev &ps, Smem<C> &sm,
-                                              int hh, int tile, int pl, int rb, int nrb,
-                                              double (&outv)[C::E][C::R]) {
-    const int tid = threadIdx.x;
-    const int lane = tid & (WAVE - 1);
-    const int wave = tid / WAVE;
-    const int j0 = tid * C::E;
-    const int seg = 1 << (ps.seg_log2 < 30 ? ps.seg_log2 : 30);
-    const int G = seg <= C::E ? 1 : (seg >= C::T ? WG : seg / C::E);
-    const int gw = G < WAVE ? G : WAVE;
-    const int lig = lane & (gw - 1);
-    const double a = A.a;
+// Process element e of the lane's run in a scan step: move the state to the
+// element (or reset at a segment boundary), read the target value, add the
+// source.  Returns the target value.
+template <class C, int DIR, bool TARGET>
+__device__ __forceinline__ double scan_elem(const Smem<C> &sm, State<C> &S, int e, int i, int run, int hh,
+                                            double &prevx, double v, double a) {
     constexpr int BOUND = DIR == 0 ? F_SEGSTART : F_SEGEND;
-    // first / last processed element of the run
-    const int jbeg = DIR == 0 ? j0 : j0 + C::E - 1;
-    const int jend = DIR == 0 ? j0 + C::E - 1 : j0;
-    const double xbeg = sm.xs[jbeg];
-    const double xend = sm.xs[jend];
+    const int sj = e * C::RUNS + run;
+    const int fl = sm.flags[sj];
+    int sc, tc;
+    classes<C>(fl, hh, sc, tc);
+    const double xj = sm.xs[sj];
+    if (fl & BOUND) {
+        if constexpr (TARGET) S.zero();
+    } else {
+        const double t = a * (DIR == 0 ? xj - prevx : prevx - xj);
+        const double Ed = (i == 0) ? exp(-t) : sm.est[DIR == 0 ? sj : sj + C::RUNS];
+        S.shift(Ed, t);
+    }
+    prevx = xj;
+    double geo[C::G > 0 ? C::G : 1];
+    load_geo<C>(sm, sj, geo);
+    ElemVec<C> ev;
+    elem_vectors<C>(geo, ev);
+    double out = 0.0;
+    if constexpr (TARGET) out = read_target<C>(S, tc, ev);
+    add_source<C>(S, sc, ev, v);
+    return out;
+}
+
+// One scan direction over this lane's run, with every carry.
+// DIR 0: forward (increasing positions; sources at or before the target in
+//        the last coordinate: delta_last = +1);
+// DIR 1: backward (decreasing positions; sources strictly after: delta_last = -1).
+// MODE 0: target values go to outv (short runs) or to the pass's slab (long
+//         runs: the backward direction, run first, stores; the forward adds);
+// MODE 1: the tile's total is written to the aggregates.
+template <class C, int MODE, int DIR>
+__device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev &ps, const Smem<C> &sm,
+                                              int hh, int64_t tile, int pl, int col, int run,
+                                              const double (&vr)[C::REGOUT ? C::E : 1],
+                                              double (&outv)[C::REGOUT ? C::E : 1], double *slab) {
+    const int seg = 1 << (ps.seg_log2 < 30 ? ps.seg_log2 : 30);
+    // runs per segment group (1 when segments fit in a run)
+    const int Gr = seg <= C::E ? 1 : (seg >= C::T ? C::RUNS : seg / C::E);
+    const int lig = run & (Gr - 1);
+    const double a = A.a;
+    const int ebeg = DIR == 0 ? 0 : C::E - 1;
+    const int eend = DIR == 0 ? C::E - 1 : 0;
+    const double xbeg = sm.xs[ebeg * C::RUNS + run];
+    const double xend = sm.xs[eend * C::RUNS + run];
+    const double *vcol = A.vin + col;
 
     State<C> Ex;  // carry entering the run, anchored at xex
     Ex.zero();
     double xex = xbeg;
 
-    if (G > 1) {
+    if (Gr > 1) {
         // ---- run aggregate (anchored at xend)
         State<C> F;
         F.zero();
+        double px = xbeg;
+        if constexpr (C::REGOUT) {
 #pragma unroll
-        for (int i = 0; i < C::E; ++i) {
-            const int e = DIR == 0 ? i : C::E - 1 - i;
-            const int j = j0 + e;
-            int sc, tc;
-            classes<C>(sm.flags[j], hh, sc, tc);
-            double geo[C::G > 0 ? C::G : 1];
-            load_geo<C>(sm, j, geo);
-            ElemVec<C> ev;
-            elem_vectors<C>(geo, ev);
-            double v[C::R];
-            load_v<C>(A, sm.c[j], rb, v);
-            if (i > 0) {
-                const int js = DIR == 0 ? j : j + 1;  // decay between j and its predecessor
-                const double t = a * (DIR == 0 ? sm.xs[j] - sm.xs[j - 1] : sm.xs[j + 1] - sm.xs[j]);
-                F.shift(sm.est[js], t);
+            for (int i = 0; i < C::E; ++i) {
+                const int e = DIR == 0 ? i : C::E - 1 - i;
+                scan_elem<C, DIR, false>(sm, F, e, i, run, hh, px, vr[e], a);
             }
-            add_source<C>(F, sc, ev, v);
-        }
-        State<C> Frun = F;
-        // ---- wave-level inclusive scan toward this direction
+        } else {
 #pragma unroll 1
-        for (int o = 1; o < gw; o <<= 1) {
-            State<C> T2;
-            double xp;
-            if constexpr (DIR == 0) {
-                xp = __shfl_up(xend, o, WAVE);
-                shfl_up_state<C>(F, T2, o);
-            } else {
-                xp = __shfl_down(xend, o, WAVE);
-                shfl_down_state<C>(F, T2, o);
-            }
-            const bool ok = DIR == 0 ? (lig >= o) : (lig + o < gw);
-            if (ok) {
-                const double t = a * (DIR == 0 ? xend - xp : xp - xend);
-                F.add_shifted(T2, exp(-t), t);
-            }
-        }
-        // exclusive value inside the wave group
-        {
-            double xp;
-            if constexpr (DIR == 0) {
-                xp = __shfl_up(xend, 1, WAVE);
-                shfl_up_state<C>(F, Ex, 1);
-            } else {
-                xp = __shfl_down(xend, 1, WAVE);
-                shfl_down_state<C>(F, Ex, 1);
-            }
-            const bool has = DIR == 0 ? (lig > 0) : (lig < gw - 1);
-            if (has) {
-                xex = xp;
-            } else {
-                Ex.zero();
-            }
-        }
-        // ---- across the waves of a group (128 or 256 threads)
-        if (G > WAVE) {
-            const int edge = DIR == 0 ? WAVE - 1 : 0;
-            if (lane == edge) {
+            for (int b = 0; b < C::E; b += C::BLK) {
+                double vb[C::BLK];
 #pragma unroll
-                for (int i = 0; i < C::NSLOT; ++i) sm.waveF[wave][i] = F.flat()[i];
-                sm.waveFx[wave] = xend;
-            }
-            __syncthreads();
-            const int wpg = G / WAVE;
-            const int gfirst = (wave / wpg) * wpg;
-            const int glast = gfirst + wpg - 1;
-            const bool has_prev_waves = DIR == 0 ? (wave > gfirst) : (wave < glast);
-            if (has_prev_waves) {
-                State<C> acc, tmp;
-                acc.zero();
-                const int wstart = DIR == 0 ? gfirst : glast;
-                double ax = sm.waveFx[wstart];
-                for (int w = wstart; w != wave; w += (DIR == 0 ? 1 : -1)) {
-#pragma unroll
-                    for (int i = 0; i < C::NSLOT; ++i) tmp.flat()[i] = sm.waveF[w][i];
-                    const double t = a * (DIR == 0 ? sm.waveFx[w] - ax : ax - sm.waveFx[w]);
-                    acc.shift(exp(-t), t);
-                    acc.add_shifted(tmp, 1.0, 0.0);
-                    ax = sm.waveFx[w];
+                for (int k = 0; k < C::BLK; ++k) {
+                    const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
+                    const int sj = e * C::RUNS + run;
+                    vb[k] = (sm.flags[sj] & F_VALID) ? vcol[(int64_t)sm.c[sj] * A.W] : 0.0;
                 }
-                if (lane == (DIR == 0 ? 0 : WAVE - 1)) xex = ax;
-                const double t = a * (DIR == 0 ? xex - ax : ax - xex);
-                Ex.add_shifted(acc, exp(-t), t);
+#pragma unroll
+                for (int k = 0; k < C::BLK; ++k) {
+                    const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
+                    scan_elem<C, DIR, false>(sm, F, e, b + k, run, hh, px, vb[k], a);
+                }
             }
-            __syncthreads();
+        }
+        State<C> Frun;
+        if constexpr (MODE == 1) Frun = F;
+        // ---- inclusive scan over the runs of this column
+#pragma unroll 1
+        for (int o = 1; o < Gr; o <<= 1) {
+            const bool ok = DIR == 0 ? (lig >= o) : (lig + o < Gr);
+            scan_step<C, DIR == 0>(F, o, xend, ok, a);
+        }
+        // exclusive value
+        {
+            const int dl = C::WCOL;
+            const double xp = DIR == 0 ? __shfl_up(xend, dl, WAVE) : __shfl_down(xend, dl, WAVE);
+            const bool has = DIR == 0 ? (lig > 0) : (lig < Gr - 1);
+#pragma unroll
+            for (int k = 0; k < C::NSLOT; ++k) {
+                const double q = DIR == 0 ? __shfl_up(F.flat()[k], dl, WAVE) : __shfl_down(F.flat()[k], dl, WAVE);
+                Ex.flat()[k] = has ? q : 0.0;
+            }
+            if (has) xex = xp;
         }
         if constexpr (MODE == 1) {
             // tile total: inclusive value of the run that ends the tile in this direction
-            const int owner = DIR == 0 ? WG - 1 : 0;
-            if (tid == owner) {
+            if (run == (DIR == 0 ? C::RUNS - 1 : 0)) {
                 State<C> tot = Ex;
                 const double t = a * (DIR == 0 ? xend - xex : xex - xend);
                 tot.shift(exp(-t), t);
                 tot.add_shifted(Frun, 1.0, 0.0);
-                double *dst = A.agg + agg_index<C>(A, DIR, pl, tile, rb, nrb, hh);
+                double *dst = A.agg + agg_index<C>(A, DIR, pl, tile, col, hh);
 #pragma unroll
-                for (int i = 0; i < C::NSLOT; ++i) dst[i] = tot.flat()[i];
-                if (rb == 0 && hh == 0) A.anc[((int64_t)DIR * A.G + pl) * A.ntile + tile] = xend;
+                for (int k = 0; k < C::NSLOT; ++k) dst[k] = tot.flat()[k];
+                if (col == 0 && hh == 0) A.anc[((int64_t)DIR * A.G + pl) * A.ntile + tile] = xend;
             }
             return;
         }
-        // ---- carry from the other tiles of the same segment (reduced into LDS)
-        if (sm.carhas[DIR]) {
-            State<C> cf;
+        // ---- carry from the other tiles of the segment (tile carry scan)
+        if (seg > C::T && A.ntile > 1) {
+            const int64_t tps = seg / C::T;
+            const bool has_nb = DIR == 0 ? (tile % tps) != 0 : (((tile + 1) % tps) != 0 && tile + 1 < A.ntile);
+            if (has_nb) {
+                State<C> cf;
+                const double *src = A.car + agg_index<C>(A, DIR, pl, tile, col, hh);
 #pragma unroll
-            for (int i = 0; i < C::NSLOT; ++i) cf.flat()[i] = sm.car[DIR][i];
-            const double anc = sm.carx[DIR];
-            if (tid == (DIR == 0 ? 0 : WG - 1)) xex = anc;
-            const double t = a * (DIR == 0 ? xex - anc : anc - xex);
-            Ex.add_shifted(cf, exp(-t), t);
+                for (int k = 0; k < C::NSLOT; ++k) cf.flat()[k] = src[k];
+                const double anc = A.anc[((int64_t)DIR * A.G + pl) * A.ntile + (DIR == 0 ? tile - 1 : tile + 1)];
+                if (run == (DIR == 0 ? 0 : C::RUNS - 1)) xex = anc;
+                const double t = a * (DIR == 0 ? xex - anc : anc - xex);
+                Ex.add_shifted(cf, exp(-t), t);
+            }
         }
     }
     if constexpr (MODE == 0) {
         // ---- the scan proper: targets read the state, then sources enter it
         State<C> S = Ex;
-        double prevx = xex;
+        double px = xex;
+        if constexpr (C::REGOUT) {
 #pragma unroll
-        for (int i = 0; i < C::E; ++i) {
-            const int e = DIR == 0 ? i : C::E - 1 - i;
-            const int j = j0 + e;
-            const int fl = sm.flags[j];
-            int sc, tc;
-            classes<C>(fl, hh, sc, tc);
-            const double xj = sm.xs[j];
-            if (fl & BOUND) {
-                S.zero();
-            } else {
-                const double t = a * (DIR == 0 ? xj - prevx : prevx - xj);
-                const double E = (i == 0) ? exp(-t) : sm.est[DIR == 0 ? j : j + 1];
-                S.shift(E, t);
+            for (int i = 0; i < C::E; ++i) {
+                const int e = DIR == 0 ? i : C::E - 1 - i;
+                outv[e] += scan_elem<C, DIR, true>(sm, S, e, i, run, hh, px, vr[e], a);
             }
-            prevx = xj;
-            double geo[C::G > 0 ? C::G : 1];
-            load_geo<C>(sm, j, geo);
-            ElemVec<C> ev;
-            elem_vectors<C>(geo, ev);
-            double v[C::R];
-            load_v<C>(A, sm.c[j], rb, v);
-            read_target<C>(S, tc, ev, outv[e]);
-            add_source<C>(S, sc, ev, v);
-        }
-    }
-}
-
-// Sum over the tiles t' of a segment on one side of `tile` of the tile
-// aggregates shifted to the anchor next to `tile`; every term is a product of
-// bounded factors, so the tiles are combined in parallel (fixed order).
-template <class C>
-__device__ __forceinline__ void tile_carries(const SweepArgs &A, const PassDev &ps, Smem<C> &sm,
-                                             int tile, int pl, int rb, int nrb, int hh) {
-    const int seg = 1 << (ps.seg_log2 < 30 ? ps.seg_log2 : 30);
-    if (threadIdx.x < 2) sm.carhas[threadIdx.x] = 0;
-    if (seg <= C::T || A.ntile < 2) {
-        __syncthreads();
-        return;
-    }
-    const int64_t tps = seg / C::T;
-    const int64_t ts0 = (tile / tps) * tps;
-    const int64_t ts1 = ts0 + tps < A.ntile ? ts0 + tps : A.ntile;
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int wave = threadIdx.x / WAVE;
+        } else {
 #pragma unroll 1
-    for (int dir = 0; dir < 2; ++dir) {
-        const bool has = dir == 0 ? tile > ts0 : tile + 1 < ts1;
-        if (!has) continue;  // uniform over the block
-        const double *ancd = A.anc + (int64_t)dir * A.G * A.ntile + (int64_t)pl * A.ntile;
-        const double xref = dir == 0 ? ancd[tile - 1] : ancd[tile + 1];
-        const int64_t lo = dir == 0 ? ts0 : tile + 1;
-        const int64_t hi = dir == 0 ? tile : ts1;
-        State<C> acc, tmp;
-        acc.zero();
-        for (int64_t t = lo + threadIdx.x; t < hi; t += WG) {
-            const double *src = A.agg + agg_index<C>(A, dir, pl, (int)t, rb, nrb, hh);
+            for (int b = 0; b < C::E; b += C::BLK) {
+                double vb[C::BLK], ob[C::BLK];
+                int64_t addr[C::BLK];
 #pragma unroll
-            for (int i = 0; i < C::NSLOT; ++i) tmp.flat()[i] = src[i];
-            const double sh = A.a * (dir == 0 ? xref - ancd[t] : ancd[t] - xref);
-            acc.add_shifted(tmp, exp(-sh), sh);
-        }
-        // block reduction: butterfly inside each wave, then the waves in order
+                for (int k = 0; k < C::BLK; ++k) {
+                    const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
+                    const int sj = e * C::RUNS + run;
+                    const bool valid = sm.flags[sj] & F_VALID;
+                    addr[k] = valid ? (int64_t)sm.c[sj] * A.W + col : -1;
+                    vb[k] = valid ? A.vin[addr[k]] : 0.0;
+                    // the slab already holds this element's earlier values unless this is
+                    // the first write of the pass (backward direction of sub-sweep 0)
+                    ob[k] = (valid && (DIR == 0 || hh > 0)) ? slab[addr[k]] : 0.0;
+                }
 #pragma unroll
-        for (int i = 0; i < C::NSLOT; ++i) {
-            double v = acc.flat()[i];
-#pragma unroll
-            for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-            if (lane == 0) sm.waveF[wave][i] = v;
+                for (int k = 0; k < C::BLK; ++k) {
+                    const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
+                    const double val = scan_elem<C, DIR, true>(sm, S, e, b + k, run, hh, px, vb[k], a);
+                    if (addr[k] >= 0) slab[addr[k]] = ob[k] + val;
+                }
+            }
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < C::NSLOT; i += WG) {
-            double v = 0.0;
-            for (int w = 0; w < NWAVE; ++w) v += sm.waveF[w][i];
-            sm.car[dir][i] = v;
-        }
-        if (threadIdx.x == 0) {
-            sm.carx[dir] = xref;
-            sm.carhas[dir] = 1;
-        }
-        __syncthreads();
     }
-    __syncthreads();
 }
 
-// MODE 0: one (pass, tile) of the group; the targets' sums go to the pass's slab.
-// MODE 1: tile aggregates of the passes whose segments span tiles.
+// MODE 0: one (pass, tile, column block) of the group; targets' sums go to
+// the pass's slab.  MODE 1: tile aggregates of the passes whose segments span
+// several tiles.
 template <class C, int MODE>
-__global__ __launch_bounds__(WG) void sweep_kernel(SweepArgs A) {
-    __shared__ Smem<C> sm;
-    int pass, tile;
+__device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, int64_t bx, int by) {
+    int pass;
+    int64_t tile;
     if constexpr (MODE == 0) {
-        pass = A.g0 + (int)(blockIdx.x / A.ntile);
-        tile = (int)(blockIdx.x % A.ntile);
+        pass = A.g0 + (int)(bx / A.ntile);
+        tile = bx % A.ntile;
     } else {
-        pass = A.xt[A.k0 + (int)(blockIdx.x / A.ntile)];
-        tile = (int)(blockIdx.x % A.ntile);
+        pass = A.xt[A.k0 + (int)(bx / A.ntile)];
+        tile = bx % A.ntile;
     }
     const int pl = pass - A.g0;
     const PassDev ps = A.passes[pass];
-    const int rb = blockIdx.y;
-    const int nrb = gridDim.y;
-    const int64_t p0 = (int64_t)tile * C::T;
+    const int lane = threadIdx.x;
+    const int col = by * C::WCOL + lane % C::WCOL;
+    const int run = lane / C::WCOL;
+    const int64_t p0 = tile * C::T;
     stage_tile<C>(A, ps, sm, p0);
+    double *slab = A.ypart + (int64_t)pl * A.n * A.W;
 
-    double outv[C::E][C::R];
+    double vr[C::REGOUT ? C::E : 1], outv[C::REGOUT ? C::E : 1];
+    if constexpr (C::REGOUT) {
 #pragma unroll
-    for (int e = 0; e < C::E; ++e)
-#pragma unroll
-        for (int r = 0; r < C::R; ++r) outv[e][r] = 0.0;
+        for (int e = 0; e < C::E; ++e) {
+            const int sj = e * C::RUNS + run;
+            vr[e] = (sm.flags[sj] & F_VALID) ? A.vin[(int64_t)sm.c[sj] * A.W + col] : 0.0;
+            outv[e] = 0.0;
+        }
+    }
 
 #pragma unroll 1
     for (int hh = 0; hh < C::NHALF; ++hh) {
-        if constexpr (MODE == 0) tile_carries<C>(A, ps, sm, tile, pl, rb, nrb, hh);
-        run_direction<C, MODE, 0>(A, ps, sm, hh, tile, pl, rb, nrb, outv);
-        run_direction<C, MODE, 1>(A, ps, sm, hh, tile, pl, rb, nrb, outv);
-        __syncthreads();
+        run_direction<C, MODE, 1>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab);
+        run_direction<C, MODE, 0>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab);
     }
 
-    if constexpr (MODE == 0) {
-        const int j0 = threadIdx.x * C::E;
-        double *slab = A.ypart + (int64_t)pl * A.n * A.W;
+    if constexpr (MODE == 0 && C::REGOUT) {
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
-            const int j = j0 + e;
-            if (sm.flags[j] & F_VALID) {
-                double *dst = slab + (int64_t)sm.c[j] * A.W + rb * C::R;
+            const int sj = e * C::RUNS + run;
+            if (sm.flags[sj] & F_VALID) slab[(int64_t)sm.c[sj] * A.W + col] = outv[e];
+        }
+    }
+}
+
+template <class C, int MODE>
+__global__ __launch_bounds__(WAVE) void sweep_kernel(SweepArgs A) {
+    __shared__ Smem<C> sm;
+    sweep_body<C, MODE>(A, sm, blockIdx.x, blockIdx.y);
+}
+
+// Batched: every item (problem, block x, block y) of a table runs the same body
+// with its problem's arguments; a fixed grid walks the table (persistent).
+template <class C, int MODE>
+__global__ __launch_bounds__(WAVE) void sweep_batch_kernel(const SweepArgs *descs, const int4 *items, int nitems) {
+    __shared__ Smem<C> sm;
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int4 it = items[i];
+        const SweepArgs A = descs[it.x];
+        sweep_body<C, MODE>(A, sm, it.y, it.z);
+        __syncthreads();
+    }
+}
+
+// Exclusive scans of the tile aggregates over the tiles of each segment, in
+// both directions: car[t] = the sum over the segment's tiles before t
+// (forward) or after t (backward) of their aggregates, moved to the anchor
+// next to t.  One wave per (segment, slice): a slice is one (sub-sweep,
+// class, channel row, column) P-vector.  Lanes take chunks of consecutive
+// tiles, scan them serially, join the chunks with a lane scan and write the
+// tiles' exclusive values.  `segs` lists (pass, first tile, end tile) of the
+// segments that span several tiles; blockIdx.x indexes them.
+template <class C>
+__device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int by) {
+    const int4 sg = A.segs[bx];
+    const int nslice = A.nslice;
+    const int pass = sg.x;
+    const int64_t t0 = sg.y, t1 = sg.z;
+    const int pl = pass - A.g0;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int sl = by * 4 + threadIdx.x / WAVE;
+    if (sl >= nslice) return;
+    const int colw = sl % C::WCOL;
+    const int rowcb = sl / C::WCOL;  // (column block, row)
+    constexpr int ROWS = C::NHALF * C::NCLS * C::NTH;
+    const int row = rowcb % ROWS;
+    const int cb = rowcb / ROWS;
+    const int hh = row / (C::NCLS * C::NTH);
+    const int ch = row % (C::NCLS * C::NTH);
+    const int col = cb * C::WCOL + colw;
+    const double a = A.a;
+    const int64_t nt = t1 - t0;
+    const int64_t chunk = (nt + WAVE - 1) / WAVE;
+    const int64_t lo = t0 + lane * chunk;
+    const int64_t hi = lo + chunk < t1 ? lo + chunk : t1;
+    const int nact = (int)((nt + chunk - 1) / chunk);  // lanes holding tiles
+#pragma unroll 1
+    for (int dir = 0; dir < 2; ++dir) {
+        const double *anc = A.anc + ((int64_t)dir * A.G + pl) * A.ntile;
+        auto off = [&](int64_t t) -> int64_t { return agg_index<C>(A, dir, pl, t, col, hh) + (int64_t)ch * C::P; };
+        // chunk aggregate in the scan direction, anchored at the chunk's last tile
+        const int64_t cb0 = dir == 0 ? lo : hi - 1;
+        const int64_t cb1 = dir == 0 ? hi - 1 : lo;   // last processed tile
+        const int64_t step = dir == 0 ? 1 : -1;
+        const bool active = lane < nact;
+        double acc[C::P];
 #pragma unroll
-                for (int r = 0; r < C::R; ++r) dst[r] = outv[e][r];
+        for (int m = 0; m < C::P; ++m) acc[m] = 0.0;
+        // inactive lanes (no tiles) hold a zero state at the segment's largest anchor,
+        // so every shift they take part in is by a non-negative distance
+        double xa = active ? anc[cb1] : anc[t1 - 1];
+        if (active) {
+            double xprev = anc[cb0];
+            const int64_t cnt = hi - lo;
+            // blocks of 8 tiles: issue the loads first, then the dependent updates
+            for (int64_t b = 0; b < cnt; b += 8) {
+                double xs8[8], g8[8][C::P];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int64_t t = cb0 + step * (b + k);
+                    const bool in = b + k < cnt;
+                    xs8[k] = in ? anc[t] : 0.0;
+#pragma unroll
+                    for (int m = 0; m < C::P; ++m) g8[k][m] = in ? A.agg[off(t) + m] : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (b + k >= cnt) break;
+                    const double x = xs8[k];
+                    const double tt = a * (dir == 0 ? x - xprev : xprev - x);
+                    const double E = exp(-tt);
+                    if constexpr (C::P == 3) acc[2] = E * (acc[2] + tt * acc[1] + 0.5 * tt * tt * acc[0]);
+                    if constexpr (C::P >= 2) acc[1] = E * (acc[1] + tt * acc[0]);
+                    acc[0] = E * acc[0];
+#pragma unroll
+                    for (int m = 0; m < C::P; ++m) acc[m] += g8[k][m];
+                    xprev = x;
+                }
             }
         }
+        // inclusive lane scan toward the direction
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const double xp = dir == 0 ? __shfl_up(xa, o, WAVE) : __shfl_down(xa, o, WAVE);
+            double q[C::P];
+#pragma unroll
+            for (int m = 0; m < C::P; ++m) q[m] = dir == 0 ? __shfl_up(acc[m], o, WAVE) : __shfl_down(acc[m], o, WAVE);
+            const bool ok = dir == 0 ? (lane >= o) : (lane + o < WAVE);
+            if (ok) {
+                const double tt = a * (dir == 0 ? xa - xp : xp - xa);
+                const double E = exp(-tt);
+                if constexpr (C::P == 3) acc[2] += E * (q[2] + tt * q[1] + 0.5 * tt * tt * q[0]);
+                if constexpr (C::P >= 2) acc[1] += E * (q[1] + tt * q[0]);
+                acc[0] += E * q[0];
+            }
+        }
+        // exclusive value entering the chunk
+        double ex[C::P];
+        double xe;
+        {
+            const double xp = dir == 0 ? __shfl_up(xa, 1, WAVE) : __shfl_down(xa, 1, WAVE);
+            const bool has = dir == 0 ? (lane > 0) : (lane < WAVE - 1);
+#pragma unroll
+            for (int m = 0; m < C::P; ++m) {
+                const double q = dir == 0 ? __shfl_up(acc[m], 1, WAVE) : __shfl_down(acc[m], 1, WAVE);
+                ex[m] = has ? q : 0.0;
+            }
+            xe = xp;
+        }
+        // walk the chunk again, writing each tile's exclusive carry
+        if (active) {
+            for (int64_t t = cb0;; t += step) {
+                const double x = anc[t];
+                const bool first = (dir == 0 ? t == t0 : t == t1 - 1);
+                if (!first) {
+                    // move the carry to the anchor next to t (previous tile in the direction)
+                    const double xn = anc[t - step];
+                    const double tt = a * (dir == 0 ? xn - xe : xe - xn);
+                    const double E = exp(-tt);
+                    if constexpr (C::P == 3) ex[2] = E * (ex[2] + tt * ex[1] + 0.5 * tt * tt * ex[0]);
+                    if constexpr (C::P >= 2) ex[1] = E * (ex[1] + tt * ex[0]);
+                    ex[0] = E * ex[0];
+                    xe = xn;
+#pragma unroll
+                    for (int m = 0; m < C::P; ++m) A.car[off(t) + m] = ex[m];
+                }
+                // include tile t
+                {
+                    const double tt = a * (dir == 0 ? x - xe : xe - x);
+                    const double E = first ? 1.0 : exp(-tt);
+                    if (!first) {
+                        if constexpr (C::P == 3) ex[2] = E * (ex[2] + tt * ex[1] + 0.5 * tt * tt * ex[0]);
+                        if constexpr (C::P >= 2) ex[1] = E * (ex[1] + tt * ex[0]);
+                        ex[0] = E * ex[0];
+                    }
+#pragma unroll
+                    for (int m = 0; m < C::P; ++m) ex[m] += A.agg[off(t) + m];
+                    xe = x;
+                }
+                if (t == cb1) break;
+            }
+        }
+    }
+}
+
+template <class C>
+__global__ __launch_bounds__(256) void carry_kernel(SweepArgs A) {
+    carry_body<C>(A, blockIdx.x, blockIdx.y);
+}
+
+// Batched carry scans: items (problem, segment, slice group).
+template <class C>
+__global__ __launch_bounds__(256) void carry_batch_kernel(const SweepArgs *descs, const int4 *items, int nitems) {
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int4 it = items[i];
+        const SweepArgs A = descs[it.x];
+        carry_body<C>(A, it.y, it.z);
     }
 }
 
@@ -726,56 +844,70 @@ __global__ void zero_kernel(double *p, int64_t len) {
 // ---------------------------------------------------------------------------
 // Host-side dispatch.
 // ---------------------------------------------------------------------------
-constexpr int E_RUN = 4;
-constexpr int TILE = WG * E_RUN;
+constexpr int BS1 = 256;
 
 inline unsigned grid_1d(int64_t n) {
-    int64_t g = (n + WG - 1) / WG;
+    int64_t g = (n + BS1 - 1) / BS1;
     if (g > 65535 * 8) g = 65535 * 8;
     return (unsigned)(g < 1 ? 1 : g);
 }
 
+inline int tile_index(int T) { return T >= 1024 ? 2 : (T >= 512 ? 1 : 0); }
+
 template <class C>
 mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStream_t s) {
-    static_assert(C::T == TILE, "tile size");
+    static_assert(C::T == 256 || C::T == 512 || C::T == 1024, "tile sizes with a cross-tile pass list");
     const KParams kp = kparams(p->kernel, p->d);
     const int64_t n = p->n;
-    const int nrb = W / C::R;
+    const int ncb = W / C::WCOL;
     const int64_t ntile = (n + C::T - 1) / C::T;
     const int npass = (int)p->passes.size();
     const int64_t len = n * W;
     if (npass == 0) {
-        hipLaunchKernelGGL(zero_kernel, dim3(grid_1d(len)), dim3(WG), 0, s, yacc, len);
+        hipLaunchKernelGGL(zero_kernel, dim3(grid_1d(len)), dim3(BS1), 0, s, yacc, len);
         MM_HIP_TRY(hipGetLastError());
         return MM_OK;
     }
+    const int ti = tile_index(C::T);
+    const std::vector<int> &xt = p->xt_host[ti];
     const int gmax = group_passes(p, W);
     SweepArgs A{};
     A.xc = static_cast<const double *>(p->xc.ptr);
     A.passes = static_cast<const PassDev *>(p->pass_dev.ptr);
-    A.xt = static_cast<const int32_t *>(p->pass_xt.ptr);
+    A.xt = static_cast<const int32_t *>(p->pass_xt[ti].ptr);
     A.vin = vin;
     A.ypart = static_cast<double *>(p->part.ptr);
     A.n = n;
     A.ntile = ntile;
     A.W = W;
     A.a = kp.a;
-    const size_t aggslab = (size_t)2 * gmax * ntile * nrb * C::NHALF * C::NSLOT;
+    const size_t aggslab = (size_t)2 * gmax * ntile * W * C::NHALF * C::NSLOT;
     A.agg = static_cast<double *>(p->agg.ptr);
-    A.anc = A.agg + aggslab;
+    A.car = A.agg + aggslab;
+    A.anc = A.car + aggslab;
     for (int g0 = 0; g0 < npass; g0 += gmax) {
         const int G = npass - g0 < gmax ? npass - g0 : gmax;
         A.g0 = g0;
         A.G = G;
         // passes of the group whose segments span tiles: a contiguous range of xt
-        int k0 = 0, k1 = 0;
-        while (k0 < (int)p->xt_host.size() && p->xt_host[k0] < g0) ++k0;
-        k1 = k0;
-        while (k1 < (int)p->xt_host.size() && p->xt_host[k1] < g0 + G) ++k1;
+        int k0 = 0;
+        while (k0 < (int)xt.size() && xt[k0] < g0) ++k0;
+        int k1 = k0;
+        while (k1 < (int)xt.size() && xt[k1] < g0 + G) ++k1;
         A.k0 = k0;
-        if (k1 > k0 && ntile > 1)
-            hipLaunchKernelGGL((sweep_kernel<C, 1>), dim3((unsigned)((k1 - k0) * ntile), (unsigned)nrb),
-                               dim3(WG), 0, s, A);
+        if (k1 > k0 && ntile > 1) {
+            const dim3 gx((unsigned)((k1 - k0) * ntile), (unsigned)ncb);
+            hipLaunchKernelGGL((sweep_kernel<C, 1>), gx, dim3(WAVE), 0, s, A);
+            // segments of the group's cross-tile passes: a contiguous range of the plan's table
+            const std::vector<int> &so = p->seg_off[ti];
+            const int s0 = so[k0], s1 = so[k1];
+            const int nslice = C::NHALF * C::NCLS * C::NTH * W;
+            A.nslice = nslice;
+            A.segs = static_cast<const int4 *>(p->seg_tab[ti].ptr) + s0;
+            if (s1 > s0)
+                hipLaunchKernelGGL((carry_kernel<C>), dim3((unsigned)(s1 - s0), (unsigned)((nslice + 3) / 4)),
+                                   dim3(256), 0, s, A);
+        }
         hipEvent_t ev1 = nullptr;
         if (p->profile) {
             // bracket the main sweep launch with events on its stream
@@ -795,78 +927,96 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
             p->prof_used++;
             p->prof_units += (int64_t)G;
         }
-        hipLaunchKernelGGL((sweep_kernel<C, 0>), dim3((unsigned)(G * ntile), (unsigned)nrb), dim3(WG), 0, s, A);
+        hipLaunchKernelGGL((sweep_kernel<C, 0>), dim3((unsigned)(G * ntile), (unsigned)ncb), dim3(WAVE), 0, s, A);
         if (ev1) MM_HIP_TRY(hipEventRecord(ev1, s));
-        hipLaunchKernelGGL(accum_kernel, dim3(grid_1d(len)), dim3(WG), 0, s,
+        hipLaunchKernelGGL(accum_kernel, dim3(grid_1d(len)), dim3(BS1), 0, s,
                            static_cast<const double *>(p->part.ptr), G, len, yacc, g0 == 0 ? 1 : 0);
     }
     MM_HIP_TRY(hipGetLastError());
     return MM_OK;
 }
 
-template <int D, int P, bool PROD>
-mm_status dispatch_r(mm_plan p, const double *vin, double *yacc, int W, int R, hipStream_t s) {
-    // only the blocks that max_r() can select are instantiated
-    if constexpr (Cfg<D, P, PROD, 4, E_RUN>::NSLOT <= 16) {
-        if (R == 4) return run_passes<Cfg<D, P, PROD, 4, E_RUN>>(p, vin, yacc, W, s);
-    }
-    if constexpr (Cfg<D, P, PROD, 2, E_RUN>::NSLOT <= 16) {
-        if (R == 2) return run_passes<Cfg<D, P, PROD, 2, E_RUN>>(p, vin, yacc, W, s);
-    }
-    return run_passes<Cfg<D, P, PROD, 1, E_RUN>>(p, vin, yacc, W, s);
+// Lane layout by the padded width W (a multiple of the block WB returned by
+// rhs_block): WCOL = WB columns per wave and runs of E = 256*WCOL/64
+// positions (tiles of 256 positions).  with_cfg calls f(Tag<Cfg<...>>) for the
+// configuration of (d, nu, form, WB).
+template <class C>
+struct Tag {
+    using type = C;
+};
+
+template <int D, int P, bool PROD, class F>
+mm_status with_wb(int WB, F &&f) {
+    if (WB == 32) return f(Tag<Cfg<D, P, PROD, 32, 128>>{});
+    if (WB == 4) return f(Tag<Cfg<D, P, PROD, 4, 16>>{});
+    if (WB == 2) return f(Tag<Cfg<D, P, PROD, 2, 8>>{});
+    return f(Tag<Cfg<D, P, PROD, 1, 4>>{});
 }
 
-template <int D, int P, bool PROD>
-int max_r() {
-    // right-hand sides per thread such that a scan state stays within the register budget
-    if (Cfg<D, P, PROD, 4, E_RUN>::NSLOT <= 16) return 4;
-    if (Cfg<D, P, PROD, 2, E_RUN>::NSLOT <= 16) return 2;
-    return 1;
-}
-
-template <int D>
-int max_r_d(const KParams &kp) {
-    if (kp.P == 1) return max_r<D, 1, true>();
+template <int D, class F>
+mm_status with_p(const KParams &kp, int WB, F &&f) {
+    if (kp.P == 1) return with_wb<D, 1, true>(WB, f);
     if constexpr (D == 1) {
-        return kp.P == 2 ? max_r<D, 2, true>() : max_r<D, 3, true>();
+        if (kp.P == 2) return with_wb<D, 2, true>(WB, f);
+        return with_wb<D, 3, true>(WB, f);
     } else {
-        if (kp.P == 2) return kp.prod ? max_r<D, 2, true>() : max_r<D, 2, false>();
-        return kp.prod ? max_r<D, 3, true>() : max_r<D, 3, false>();
+        if (kp.P == 2) return kp.prod ? with_wb<D, 2, true>(WB, f) : with_wb<D, 2, false>(WB, f);
+        return kp.prod ? with_wb<D, 3, true>(WB, f) : with_wb<D, 3, false>(WB, f);
     }
 }
 
-template <int D>
-mm_status dispatch_p(mm_plan p, const KParams &kp, const double *vin, double *yacc, int W, int R,
-                     hipStream_t s) {
-    if (kp.P == 1) return dispatch_r<D, 1, true>(p, vin, yacc, W, R, s);
-    if constexpr (D == 1) {
-        if (kp.P == 2) return dispatch_r<D, 2, true>(p, vin, yacc, W, R, s);
-        return dispatch_r<D, 3, true>(p, vin, yacc, W, R, s);
-    } else {
-        if (kp.P == 2)
-            return kp.prod ? dispatch_r<D, 2, true>(p, vin, yacc, W, R, s)
-                           : dispatch_r<D, 2, false>(p, vin, yacc, W, R, s);
-        return kp.prod ? dispatch_r<D, 3, true>(p, vin, yacc, W, R, s)
-                       : dispatch_r<D, 3, false>(p, vin, yacc, W, R, s);
-    }
+template <class F>
+mm_status with_cfg(int d, const KParams &kp, int WB, F &&f) {
+    if (d == 1) return with_p<1>(kp, WB, f);
+    if (d == 2) return with_p<2>(kp, WB, f);
+    return with_p<3>(kp, WB, f);
+}
+
+// Arguments of a problem's single pass group (all passes) for configuration C,
+// with caller-owned aggregate and partial-slab workspaces.
+template <class C>
+SweepArgs make_args(mm_plan p, const double *vin, double *agg, double *part, int W, int gmax) {
+    const KParams kp = kparams(p->kernel, p->d);
+    const int ti = tile_index(C::T);
+    const int64_t ntile = (p->n + C::T - 1) / C::T;
+    SweepArgs A{};
+    A.xc = static_cast<const double *>(p->xc.ptr);
+    A.passes = static_cast<const PassDev *>(p->pass_dev.ptr);
+    A.xt = static_cast<const int32_t *>(p->pass_xt[ti].ptr);
+    A.vin = vin;
+    A.ypart = part;
+    A.n = p->n;
+    A.ntile = ntile;
+    A.W = W;
+    A.a = kp.a;
+    const size_t aggslab = (size_t)2 * gmax * ntile * W * C::NHALF * C::NSLOT;
+    A.agg = agg;
+    A.car = A.agg + aggslab;
+    A.anc = A.car + aggslab;
+    A.nslice = C::NHALF * C::NCLS * C::NTH * W;
+    A.segs = static_cast<const int4 *>(p->seg_tab[ti].ptr);
+    A.g0 = 0;
+    A.k0 = 0;
+    A.G = (int)p->passes.size();
+    return A;
 }
 
 }  // namespace
 
+// Columns per wave (the padding unit of the number of right-hand sides):
+// 32 from 32 columns up, 4 from 4, else 2 or 1.
 int rhs_block(const mm_kernel &k, int d, int nrhs) {
-    const KParams kp = kparams(k, d);
-    int rmax = d == 1 ? max_r_d<1>(kp) : (d == 2 ? max_r_d<2>(kp) : max_r_d<3>(kp));
-    int R = 1;
-    while (R * 2 <= rmax && R * 2 <= nrhs) R *= 2;
-    return R;
+    (void)k;
+    (void)d;
+    return nrhs >= 32 ? 32 : (nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1));
 }
 
 // Passes per group: the partial slabs of one group stay within 1 GiB.
 constexpr size_t PART_BUDGET = size_t(1) << 30;
 
 static int group_size(int64_t n, int npass, int W) {
-    const size_t slab = (size_t)n * W * sizeof(double);
-    int64_t g = (int64_t)(PART_BUDGET / (slab > 0 ? slab : 1));
+    const size_t slabb = (size_t)n * W * sizeof(double);
+    int64_t g = (int64_t)(PART_BUDGET / (slabb > 0 ? slabb : 1));
     if (g < 1) g = 1;
     if (g > npass) g = npass;
     return (int)(g < 1 ? 1 : g);
@@ -879,50 +1029,236 @@ size_t sweep_part_bytes(int64_t n, int npass, int W) {
     return (size_t)group_size(n, npass, W) * n * W * sizeof(double);
 }
 
+// Aggregates and carries: per tile and right-hand side at most
+// NHALF*NCLS*NTH*P <= 108 doubles (d = 3, product form, nu = 5/2), two
+// directions, per pass of a group; anchors 2 per tile and pass.  The smallest
+// tile (256 positions) gives the most tiles.
+static size_t agg_bytes_for(int64_t n, int W, int64_t G) {
+    const int64_t ntile = (n + 255) / 256;
+    const int64_t per_rhs = 108;
+    return (size_t)(2 * (2 * G * ntile * (int64_t)W * per_rhs) + 2 * G * ntile + 16) * sizeof(double);
+}
+
 size_t sweep_agg_bytes(int64_t n, int d, int W, const mm_kernel &k) {
     (void)k;
-    // per tile and right-hand side at most NHALF*NCLS*NTH*P <= 108 doubles
-    // (d = 3, product form, nu = 5/2), two directions, per pass of a group
     int L = 0;
     while ((int64_t(1) << L) < n) ++L;
     const int npass = n < 2 ? 0 : (d == 1 ? 1 : (d == 2 ? L : L * (L + 1) / 2));
     const int64_t G = npass == 0 ? 1 : group_size(n, npass, W);
-    const int64_t ntile = (n + TILE - 1) / TILE;
-    const int64_t per_rhs = 128;
-    return (size_t)(2 * G * ntile * (int64_t)W * per_rhs + 2 * G * ntile + 16) * sizeof(double);
+    return agg_bytes_for(n, W, G);
+}
+
+bool sweep_batch_bytes(mm_plan p, int W, size_t *agg_bytes, size_t *part_bytes) {
+    const int npass = (int)p->passes.size();
+    const size_t slab = (size_t)p->n * W * sizeof(double);
+    if (npass > 0 && (size_t)npass * slab > PART_BUDGET) return false;
+    const int64_t G = npass > 0 ? npass : 1;
+    *part_bytes = (size_t)G * slab;
+    *agg_bytes = agg_bytes_for(p->n, W, G);
+    return true;
 }
 
 mm_status upload_pass_tables(mm_plan p) {
     std::vector<PassDev> tab;
-    p->xt_host.clear();
+    for (int ti = 0; ti < 3; ++ti) p->xt_host[ti].clear();
     for (size_t i = 0; i < p->passes.size(); ++i) {
         const Pass &q = p->passes[i];
-        PassDev d{q.ord, q.ord2, q.l1, q.l2, q.seg_log2, 0};
-        tab.push_back(d);
-        if ((int64_t(1) << (q.seg_log2 < 40 ? q.seg_log2 : 40)) > TILE) p->xt_host.push_back((int)i);
+        PassDev dv{q.ord, q.ord2, q.l1, q.l2, q.seg_log2, 0};
+        tab.push_back(dv);
+        for (int ti = 0; ti < 3; ++ti)
+            if (q.seg_log2 > 8 + ti) p->xt_host[ti].push_back((int)i);
     }
     if (tab.empty()) return MM_OK;
     MM_TRY(dev_alloc(p->pass_dev, tab.size() * sizeof(PassDev)));
     MM_HIP_TRY(hipMemcpy(p->pass_dev.ptr, tab.data(), tab.size() * sizeof(PassDev), hipMemcpyHostToDevice));
-    if (!p->xt_host.empty()) {
-        MM_TRY(dev_alloc(p->pass_xt, p->xt_host.size() * sizeof(int32_t)));
-        MM_HIP_TRY(hipMemcpy(p->pass_xt.ptr, p->xt_host.data(), p->xt_host.size() * sizeof(int32_t),
+    for (int ti = 0; ti < 3; ++ti) {
+        if (p->xt_host[ti].empty()) continue;
+        MM_TRY(dev_alloc(p->pass_xt[ti], p->xt_host[ti].size() * sizeof(int32_t)));
+        MM_HIP_TRY(hipMemcpy(p->pass_xt[ti].ptr, p->xt_host[ti].data(), p->xt_host[ti].size() * sizeof(int32_t),
                              hipMemcpyHostToDevice));
+        // segments (pass, first tile, end tile) of the cross-tile passes, and the
+        // offset of each pass's first segment (seg_off[k] for xt entry k)
+        const int64_t T = int64_t(256) << ti;
+        const int64_t ntile = (p->n + T - 1) / T;
+        std::vector<int4> tab4;
+        p->seg_off[ti].clear();
+        for (int pi : p->xt_host[ti]) {
+            p->seg_off[ti].push_back((int)tab4.size());
+            const int64_t tps = (int64_t(1) << p->passes[pi].seg_log2) / T;
+            for (int64_t t0 = 0; t0 < ntile; t0 += tps) {
+                const int64_t t1 = t0 + tps < ntile ? t0 + tps : ntile;
+                if (t1 - t0 >= 2) tab4.push_back(make_int4(pi, (int)t0, (int)t1, 0));
+            }
+        }
+        p->seg_off[ti].push_back((int)tab4.size());
+        if (!tab4.empty()) {
+            MM_TRY(dev_alloc(p->seg_tab[ti], tab4.size() * sizeof(int4)));
+            MM_HIP_TRY(hipMemcpy(p->seg_tab[ti].ptr, tab4.data(), tab4.size() * sizeof(int4), hipMemcpyHostToDevice));
+        }
     }
     return MM_OK;
 }
 
-mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int R, hipStream_t s) {
+// WB: columns per wave (1, 2, 4 or 32); W a multiple of WB.
+mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int WB, hipStream_t s) {
     const KParams kp = kparams(p->kernel, p->d);
-    if (W % R != 0) {
-        set_error("internal: width %d is not a multiple of the block %d", W, R);
+    if ((WB != 1 && WB != 2 && WB != 4 && WB != 32) || W % WB != 0) {
+        set_error("internal: width %d does not match the block %d", W, WB);
         return MM_ERR_ARG;
     }
-    switch (p->d) {
-        case 1: return dispatch_p<1>(p, kp, vin, yacc, W, R, s);
-        case 2: return dispatch_p<2>(p, kp, vin, yacc, W, R, s);
-        default: return dispatch_p<3>(p, kp, vin, yacc, W, R, s);
+    return with_cfg(p->d, kp, WB, [&](auto t) {
+        using C = typename decltype(t)::type;
+        return run_passes<C>(p, vin, yacc, W, s);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Batched sweeps: several problems (each with its own plan) of the same width
+// W in one launch per kernel configuration and phase.  The tables list work
+// items (problem, block x, block y); a fixed grid walks them.
+// ---------------------------------------------------------------------------
+namespace {
+__global__ void accum_batch_kernel(const AccumDesc *descs, const int2 *items, int nitems) {
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        const AccumDesc d = descs[it.x];
+        const int64_t lo = (int64_t)it.y * ACC_CHUNK;
+        const int64_t hi = lo + ACC_CHUNK < d.len ? lo + ACC_CHUNK : d.len;
+        for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+            double sum = 0.0;
+            for (int g = 0; g < d.G; ++g) sum += d.ypart[(int64_t)g * d.len + e];
+            d.yacc[e] = sum;
+        }
     }
+}
+
+template <class T>
+mm_status upload(DevBuf &b, const std::vector<T> &v) {
+    if (v.empty()) return MM_OK;
+    MM_TRY(dev_alloc(b, v.size() * sizeof(T)));
+    MM_HIP_TRY(hipMemcpy(b.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return MM_OK;
+}
+
+inline unsigned persist_grid(int nitems, int per_cu) {
+    int64_t g = (int64_t)256 * per_cu;
+    if (g > nitems) g = nitems;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+}  // namespace
+
+mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB, SweepBatch &out) {
+    sweep_batch_free(out);
+    out.W = W;
+    out.WB = WB;
+    // group the problems by kernel configuration
+    std::vector<int> keys;
+    for (size_t k = 0; k < probs.size(); ++k) {
+        mm_plan p = probs[k].p;
+        const KParams kp = kparams(p->kernel, p->d);
+        const int key = (p->d * 4 + kp.P) * 2 + (kp.prod ? 1 : 0);
+        size_t c = 0;
+        while (c < keys.size() && keys[c] != key) ++c;
+        if (c == keys.size()) {
+            keys.push_back(key);
+            out.classes.emplace_back();
+            out.classes.back().key = key;
+            out.classes.back().d = p->d;
+            out.classes.back().kp = kp;
+        }
+        out.classes[c].members.push_back((int)k);
+        size_t ab = 0, pb = 0;
+        if (!sweep_batch_bytes(p, W, &ab, &pb)) {
+            set_error("batched product: problem %zu needs several pass groups at width %d", k, W);
+            return MM_ERR_ARG;
+        }
+    }
+    std::vector<AccumDesc> ad;
+    std::vector<int2> ai;
+    for (size_t k = 0; k < probs.size(); ++k) {
+        mm_plan p = probs[k].p;
+        AccumDesc d{probs[k].part, probs[k].yacc, (int64_t)p->n * W, (int)p->passes.size()};
+        ad.push_back(d);
+        const int64_t nch = (d.len + ACC_CHUNK - 1) / ACC_CHUNK;
+        for (int64_t c = 0; c < nch; ++c) ai.push_back(make_int2((int)k, (int)c));
+    }
+    MM_TRY(upload(out.acc_desc, ad));
+    MM_TRY(upload(out.acc_items, ai));
+    out.n_acc = (int)ai.size();
+    for (auto &cl : out.classes) {
+        MM_TRY(with_cfg(cl.d, cl.kp, WB, [&](auto t) {
+            using C = typename decltype(t)::type;
+            const int ti = tile_index(C::T);
+            std::vector<SweepArgs> descs;
+            std::vector<int4> ia, ic, im;
+            for (size_t m = 0; m < cl.members.size(); ++m) {
+                const BatchEntry &e = probs[cl.members[m]];
+                mm_plan p = e.p;
+                const int npass = (int)p->passes.size();
+                SweepArgs A = make_args<C>(p, e.vin, e.agg, e.part, W, npass > 0 ? npass : 1);
+                descs.push_back(A);
+                if (npass == 0) continue;
+                const int ncb = W / C::WCOL;
+                const int64_t nxt = (int64_t)p->xt_host[ti].size();
+                if (A.ntile > 1)
+                    for (int64_t bx = 0; bx < nxt * A.ntile; ++bx)
+                        for (int by = 0; by < ncb; ++by) ia.push_back(make_int4((int)m, (int)bx, by, 0));
+                const int nseg = p->seg_off[ti].empty() ? 0 : p->seg_off[ti].back();
+                if (A.ntile > 1)
+                    for (int sg = 0; sg < nseg; ++sg)
+                        for (int by = 0; by < (A.nslice + 3) / 4; ++by) ic.push_back(make_int4((int)m, sg, by, 0));
+                for (int64_t bx = 0; bx < (int64_t)npass * A.ntile; ++bx)
+                    for (int by = 0; by < ncb; ++by) im.push_back(make_int4((int)m, (int)bx, by, 0));
+            }
+            MM_TRY(upload(cl.descs, descs));
+            MM_TRY(upload(cl.items_agg, ia));
+            MM_TRY(upload(cl.items_carry, ic));
+            MM_TRY(upload(cl.items_main, im));
+            cl.n_agg = (int)ia.size();
+            cl.n_carry = (int)ic.size();
+            cl.n_main = (int)im.size();
+            return MM_OK;
+        }));
+    }
+    return MM_OK;
+}
+
+mm_status sweep_batch_run(SweepBatch &b, hipStream_t s) {
+    for (auto &cl : b.classes) {
+        MM_TRY(with_cfg(cl.d, cl.kp, b.WB, [&](auto t) {
+            using C = typename decltype(t)::type;
+            const SweepArgs *descs = static_cast<const SweepArgs *>(cl.descs.ptr);
+            if (cl.n_agg > 0)
+                hipLaunchKernelGGL((sweep_batch_kernel<C, 1>), dim3(persist_grid(cl.n_agg, b.grid_per_cu)), dim3(WAVE), 0,
+                                   s, descs, static_cast<const int4 *>(cl.items_agg.ptr), cl.n_agg);
+            if (cl.n_carry > 0)
+                hipLaunchKernelGGL((carry_batch_kernel<C>), dim3(persist_grid(cl.n_carry, b.grid_per_cu)), dim3(256),
+                                   0, s, descs, static_cast<const int4 *>(cl.items_carry.ptr), cl.n_carry);
+            if (cl.n_main > 0)
+                hipLaunchKernelGGL((sweep_batch_kernel<C, 0>), dim3(persist_grid(cl.n_main, b.grid_per_cu)), dim3(WAVE),
+                                   0, s, descs, static_cast<const int4 *>(cl.items_main.ptr), cl.n_main);
+            return MM_OK;
+        }));
+    }
+    if (b.n_acc > 0)
+        hipLaunchKernelGGL(accum_batch_kernel, dim3(persist_grid(b.n_acc, 4)), dim3(256), 0, s,
+                           static_cast<const AccumDesc *>(b.acc_desc.ptr), static_cast<const int2 *>(b.acc_items.ptr),
+                           b.n_acc);
+    MM_HIP_TRY(hipGetLastError());
+    return MM_OK;
+}
+
+void sweep_batch_free(SweepBatch &b) {
+    for (auto &cl : b.classes) {
+        dev_free(cl.descs);
+        dev_free(cl.items_agg);
+        dev_free(cl.items_carry);
+        dev_free(cl.items_main);
+    }
+    b.classes.clear();
+    dev_free(b.acc_desc);
+    dev_free(b.acc_items);
+    b.n_acc = 0;
 }
 
 }  // namespace mm

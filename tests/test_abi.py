@@ -87,3 +87,19 @@ def test_null_pointers_rejected_on_host():
     assert L.gp_predict(None, None, None, None, 1, 1, None, None) == mm.MM_ERR_ARG
     assert L.mm_plan_destroy(None) == mm.MM_OK
     assert L.mm_plan_profile_enable(None, 1) == mm.MM_ERR_ARG
+
+
+def test_solver_entry_points_reject_null_handles_on_host():
+    L = mm.lib()
+    h = ctypes.c_void_p()
+    assert L.mm_solver_create(None, None, 0.1, 0, 1e-8, None, ctypes.byref(h)) == mm.MM_ERR_ARG
+    assert not h.value
+    assert L.mm_solver_iterate(None, 1, None) == mm.MM_ERR_ARG
+    assert L.mm_solver_poll(None, None, None, None, None) == mm.MM_ERR_ARG
+    assert L.mm_solver_finish(None, None, None, None, None) == mm.MM_ERR_ARG
+    assert L.mm_solver_destroy(None) == mm.MM_OK
+    assert L.mm_solver_batch_create(None, 0, 1, ctypes.byref(h)) == mm.MM_ERR_ARG
+    assert L.mm_solver_batch_iterate(None, 1, None) == mm.MM_ERR_ARG
+    assert L.mm_solver_batch_set_schedule(None, 1, 1) == mm.MM_ERR_ARG
+    assert L.mm_solver_batch_poll(None, None, None) == mm.MM_ERR_ARG
+    assert L.mm_solver_batch_destroy(None) == mm.MM_OK
