@@ -20,6 +20,16 @@ Also printed in the same JSON line:
                 measured with HIP events on its stream during the timed
                 steps, against the 8 TB/s HBM peak;
   mvm           the plain product alone at 1, 8 and 32 right-hand sides;
+  batched       256 independent problems of uneven N, d, nu and lengthscale
+                (N log-uniform in [1e3, 2e5], d in {1,2,3}, nu in {1/2,3/2,5/2}):
+                one product each and a fixed number of CG iterations each, run
+                batched (shared launches, HIP-graph replay, autotuned grids)
+                and one problem at a time through the plain entry points, on
+                the same inputs; results are checked bitwise equal;
+  served        a bounded sample of the served GP-regression stream (fixed
+                effects, Poisson arrivals at 0.9x the plain path's measured
+                capacity): p50/p99 latency and solves/s of the continuous-
+                batching server against first-come-first-served plain solves;
   cpu_baseline  the dense FP64 CPU oracle timed on a bounded sample of target
                 rows of the same product (all host cores).
 """
@@ -74,6 +84,130 @@ def cpu_baseline(x, v, seconds: float):
                       "points/s = rows / time" % (rows, N, dt)}
 
 
+def _events_ms(fn, reps):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_batched(dev, count, iters):
+    """256 uneven problems: batched vs one-at-a-time, products and CG iterations."""
+    import torch
+    import paper_2508_01864_amd as mm
+    from paper_2508_01864_amd import autotune, batched
+    import workloads
+    probs = workloads.config4(count=count)
+    ntot = int(sum(p.n for p in probs))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plans = [mm.Plan(torch.as_tensor(p.x, device=dev), mm.Kernel(p.two_nu, p.form, p.ell)) for p in probs]
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    vcs = [torch.as_tensor(p.v, device=dev).view(1, -1) for p in probs]
+    y_plain = [torch.empty_like(v) for v in vcs]
+    y_batch = [torch.empty_like(v) for v in vcs]
+
+    def plain_mvm():
+        for pl, v, y in zip(plans, vcs, y_plain):
+            pl.mvm_raw(v, y, 1)
+    mb = mm.MvmBatch(plans, nrhs=1, use_graph=True)
+    key = autotune.signature("mvm", [(p.n, p.d, p.kernel.two_nu, p.kernel.form, 1) for p in plans])
+    sched = autotune.tune(mb, key, lambda: mb.run_raw(vcs, y_batch), reps=2)
+
+    def batch_mvm():
+        mb.run_raw(vcs, y_batch)
+    plain_mvm()
+    batch_mvm()
+    ms_plain = _events_ms(plain_mvm, 3)
+    ms_batch = _events_ms(batch_mvm, 5)
+    torch.cuda.synchronize()
+    same_mvm = all(torch.equal(a, b) for a, b in zip(y_plain, y_batch))
+    mb.close()
+
+    # CG: `iters` iterations of every problem (no convergence test counted)
+    ys = [torch.as_tensor(p.y, device=dev) for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    alphas_plain = [pl.cg_solve(y, p.sigma2, rtol=1e-8, maxit=iters, raise_on_error=False)[0]
+                    for pl, y, p in zip(plans, ys, probs)]
+    torch.cuda.synchronize()
+    cg_plain_s = time.perf_counter() - t0
+    # tune once on a throwaway batch of the same shape (its iterations are not timed)
+    warm = batched.solve_many(plans, ys, [p.sigma2 for p in probs], rtol=1e-8, maxit=40, chunk=8, tune=True)
+    del warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = batched.solve_many(plans, ys, [p.sigma2 for p in probs], rtol=1e-8, maxit=iters,
+                             chunk=min(16, iters), tune=True, rebuild_frac=1.0)   # cached schedule
+    torch.cuda.synchronize()
+    cg_batch_s = time.perf_counter() - t0
+    same_cg = all(torch.equal(a, r.alpha) for a, r in zip(alphas_plain, res))
+    for pl in plans:
+        pl.close()
+    by_d = {str(d): int(sum(1 for p in probs if p.d == d)) for d in (1, 2, 3)}
+    return {
+        "workload": "%d problems, N log-uniform [1e3, 2e5] (total %d points), d/nu uniform, "
+                    "ell log-uniform [0.05, 0.5], sigma2 0.01, product form for nu >= 3/2 in d >= 2" % (count, ntot),
+        "dims": by_d, "total_points": ntot, "plan_build_s": build_s,
+        "mvm_plain_ms": ms_plain, "mvm_batched_ms": ms_batch,
+        "mvm_points_per_s_plain": ntot / (ms_plain * 1e-3),
+        "mvm_points_per_s_batched": ntot / (ms_batch * 1e-3),
+        "mvm_speedup": ms_plain / ms_batch, "mvm_bitwise_equal": bool(same_mvm),
+        "mvm_schedule": list(sched),
+        "cg_iters": iters, "cg_plain_s": cg_plain_s, "cg_batched_s": cg_batch_s,
+        "cg_point_iters_per_s_plain": ntot * iters / cg_plain_s,
+        "cg_point_iters_per_s_batched": ntot * iters / cg_batch_s,
+        "cg_speedup": cg_plain_s / cg_batch_s, "cg_bitwise_equal": bool(same_cg),
+    }
+
+
+def bench_served(dev, count):
+    """The served stream against plain first-come-first-served solves."""
+    import torch
+    import paper_2508_01864_amd as mm
+    from paper_2508_01864_amd import serve
+    import workloads
+    probs = workloads.config5(count=count, rate=1.0)
+    base = [p.arrival for p in probs]          # unit-rate Poisson arrival times
+    reqs = [serve.Request(k, 0.0, p.x, p.y, mm.Kernel(p.two_nu, p.form, p.ell), p.sigma2, p.z,
+                          rtol=1e-8, maxit=20000) for k, p in enumerate(probs)]
+    # plain service times (all requests back to back) give the plain capacity
+    plain0 = serve.run_plain(reqs)
+    service = [r.done - r.admitted for r in plain0]
+    cap = len(reqs) / sum(service)
+    rate = 0.9 * cap
+    for r, a in zip(reqs, base):
+        r.arrival = a / rate
+    # plain FIFO latencies for these arrivals from the measured service times
+    free_at = 0.0
+    plain = []
+    for r, sv in zip(reqs, service):
+        start = max(free_at, r.arrival)
+        free_at = start + sv
+        plain.append(serve.Response(r.rid, r.arrival, start, free_at, None, None, None, {}))
+    srv = serve.Server(chunk=16)
+    served = srv.run(reqs)
+    same = all(torch.equal(a.alpha, b.alpha) and torch.equal(a.mean, b.mean) for a, b in zip(served, plain0))
+    sp, ss = serve.summary(plain), serve.summary(served)
+    return {
+        "workload": "first %d requests of the served stream: N log-uniform [5e3, 3e5], d/nu uniform, "
+                    "sigma2 log-uniform [1e-3, 1e-1], affine trend + sin/cos field, fixed effects, "
+                    "1000 predict points, rtol 1e-8; Poisson arrivals at 0.9x plain capacity" % count,
+        "n": [len(r.y) for r in reqs], "d": [int(r.x.shape[1]) for r in reqs],
+        "rate_per_s": rate, "plain_capacity_per_s": cap,
+        "plain": sp, "served": ss, "served_bitwise_equal_alone": bool(same),
+        "iters": [r.info["iters"] for r in served],
+        "server": {"ticks": srv.ticks, "rebuilds": srv.rebuilds, "peak_slots": srv.peak_slots,
+                   "peak_bytes": srv.peak_bytes, "budget_bytes": srv.budget},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +217,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mvm", action="store_true")
+    ap.add_argument("--batched-count", type=int, default=256)
+    ap.add_argument("--batched-iters", type=int, default=32)
+    ap.add_argument("--served-count", type=int, default=8)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -185,6 +324,15 @@ def main():
             log("mvm nrhs=%d: %.3f ms (%.3e points/s)" % (nrhs, ms, N * nrhs / (ms * 1e-3)))
     plan.close()
 
+    batched_out = None
+    if not args.no_batched:
+        log("batched: %d problems" % args.batched_count)
+        batched_out = bench_batched(dev, args.batched_count, args.batched_iters)
+    served_out = None
+    if not args.no_served and args.served_count > 0:
+        log("served: %d requests" % args.served_count)
+        served_out = bench_served(dev, args.served_count)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -215,6 +363,8 @@ def main():
         "cg_iters": iters,
         "true_relres": true_res,
         "mvm": mvm_rows,
+        "batched": batched_out,
+        "served": served_out,
     }
     print(json.dumps(out), flush=True)
 

@@ -207,6 +207,11 @@ mm_status gp_predict(mm_plan plan, const double *alpha, const double *beta, cons
 typedef struct mm_solver_s *mm_solver;
 typedef struct mm_solver_batch_s *mm_solver_batch;
 
+/* Upper bound of the device memory of one solver (its CG state, sweep
+ * workspaces and the work tables of a batch it joins), excluding the plan;
+ * host only, for admission control.  0 for invalid arguments. */
+size_t mm_solver_footprint_bytes(int64_t n, int32_t d, int32_t fixed_effects, const mm_kernel *kernel);
+
 /* Create a solver for (K + sigma2 I) alpha = y - H beta with the arguments of
  * gp_cg_solve (y: device, n targets in caller order; it is copied) and run
  * its initialisation on `stream`; *out receives the handle. */
@@ -236,9 +241,9 @@ mm_status mm_solver_destroy(mm_solver solver);
  * in one launch per kernel configuration, column width and phase, and all
  * their vector updates in one launch per step.  With use_graph != 0
  * the iterations are captured once into a HIP graph and replayed on a
- * private stream ordered after `stream`.  A solver whose passes exceed one
- * pass group (very large n, d = 3) cannot join a batch of two or more
- * (MM_ERR_ARG).  A solver may belong to several batches but must not be
+ * private stream ordered after `stream`.  A solver whose per-pass partial
+ * sums (passes x n x columns doubles) exceed 16 GiB cannot join a batch of
+ * two or more (MM_ERR_ARG).  A solver may belong to several batches but must not be
  * iterated by two at the same time.  The solvers must outlive the batch. */
 mm_status mm_solver_batch_create(mm_solver *solvers, int32_t count, int32_t use_graph,
                                  mm_solver_batch *out);
@@ -258,6 +263,40 @@ mm_status mm_solver_batch_poll(mm_solver_batch batch, int32_t *active, void *str
 
 /* Release a batch (not its solvers).  NULL is accepted. */
 mm_status mm_solver_batch_destroy(mm_solver_batch batch);
+
+/*
+ * Batched products over independent point sets: y_k = (K_k + diag_shift I) v_k
+ * for every plan k of the batch (Section 2, eq. Ky, per problem), with one
+ * gather launch, one launch per kernel configuration and sweep phase, and one
+ * scatter launch for the whole batch.  Each problem's result is bitwise the
+ * result of matern_mvm on its plan alone.  The batch owns its work buffers
+ * and pins its plans (mm_plan_set_kernel / mm_plan_destroy fail while it
+ * lives).  A problem whose per-pass partial sums (passes x n x columns
+ * doubles) exceed 16 GiB cannot be batched (MM_ERR_ARG).
+ *   plans     host array of count plan handles (count >= 1; any mix of n, d, nu, form)
+ *   nrhs      right-hand sides of every problem, 1..256
+ *   use_graph != 0: the launches are captured once into a HIP graph and
+ *             replayed on a private stream ordered after the caller's stream
+ */
+typedef struct mm_mvm_batch_s *mm_mvm_batch;
+
+mm_status mm_mvm_batch_create(const mm_plan *plans, int32_t count, int32_t nrhs, int32_t use_graph,
+                              mm_mvm_batch *out);
+
+/* Launch schedule: workgroups per compute unit of the persistent sweep grids
+ * and the grid of the gather/scatter kernels (both >= 1; results do not
+ * depend on them). */
+mm_status mm_mvm_batch_set_schedule(mm_mvm_batch batch, int32_t sweep_wg_per_cu, int32_t grid);
+
+/* Run the batch.  v, y: host arrays of count device pointers (n_k x nrhs
+ * column-major, caller order); ldv, ldy: host arrays of leading dimensions
+ * (>= n_k).  The pointer tables are copied before the call returns (it waits
+ * for the previous call's copy only). */
+mm_status mm_mvm_batch_run(mm_mvm_batch batch, const double *const *v, const int64_t *ldv,
+                           double *const *y, const int64_t *ldy, double diag_shift, void *stream);
+
+/* Release a batch and its work buffers (synchronises the device); NULL is accepted. */
+mm_status mm_mvm_batch_destroy(mm_mvm_batch batch);
 
 /*
  * Kernel-time accounting for measurement: when enabled, every launch of the

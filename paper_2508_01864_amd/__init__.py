@@ -80,6 +80,8 @@ _SIGS = {
                                          ctypes.POINTER(_MMSolveInfo), _P]),
     "gp_predict": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double), _P, ctypes.c_int64,
                                   ctypes.c_int64, _P, _P]),
+    "mm_solver_footprint_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                                    ctypes.POINTER(_MMKernel)]),
     "mm_solver_create": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_double, _P,
                                         ctypes.POINTER(_P)]),
     "mm_solver_iterate": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
@@ -94,6 +96,12 @@ _SIGS = {
     "mm_solver_batch_iterate": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "mm_solver_batch_poll": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
     "mm_solver_batch_destroy": (ctypes.c_int, [_P]),
+    "mm_mvm_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(_P)]),
+    "mm_mvm_batch_set_schedule": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "mm_mvm_batch_run": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int64), ctypes.c_double, _P]),
+    "mm_mvm_batch_destroy": (ctypes.c_int, [_P]),
     "mm_plan_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "mm_plan_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_int64),
@@ -103,14 +111,33 @@ _SIGS = {
 _lib = None
 
 
+def _hip_runtimes():
+    """Paths of the HIP runtime libraries mapped into this process."""
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted(set(line.split()[-1] for line in f if "libamdhip64" in line))
+    except OSError:
+        return []
+
+
 def lib():
-    """The loaded library; raises if it has not been built (no fallback exists)."""
+    """The loaded library; raises if it has not been built (no fallback exists).
+
+    PyTorch is imported first so that the library binds to the HIP runtime
+    PyTorch already uses: device memory and stream handles then belong to one
+    runtime (a second copy of the runtime in the process would not see
+    PyTorch's streams and may fail to open the device)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libmaternmvm.so is not built (run __graft_entry__.build() or "
                                "python -m paper_2508_01864_amd.build); there is no fallback path")
+        import torch  # noqa: F401  (loads PyTorch's HIP runtime before the library)
         L = ctypes.CDLL(LIB_PATH)
+        rts = _hip_runtimes()
+        if len(rts) > 1:
+            raise RuntimeError("two HIP runtimes are loaded (%s); load libmaternmvm through this "
+                               "module after importing torch" % ", ".join(rts))
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
             fn.restype = res
@@ -149,6 +176,12 @@ def footprint_bytes(n: int, d: int, nrhs: int, kernel: Kernel) -> int:
     """Upper bound of a plan's device memory (host-only; 0 for invalid arguments)."""
     k = kernel.c()
     return int(lib().mm_plan_footprint_bytes(int(n), int(d), int(nrhs), ctypes.byref(k)))
+
+
+def solver_footprint_bytes(n: int, d: int, fixed_effects: bool, kernel: Kernel) -> int:
+    """Upper bound of one solver's device memory, plan excluded (host-only)."""
+    k = kernel.c()
+    return int(lib().mm_solver_footprint_bytes(int(n), int(d), 1 if fixed_effects else 0, ctypes.byref(k)))
 
 
 def _torch():
@@ -391,6 +424,48 @@ class SolverBatch:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().mm_solver_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MvmBatch:
+    """Batched products y_k = (K_k + shift I) v_k over many plans (mm_mvm_batch)."""
+
+    def __init__(self, plans, nrhs: int = 1, use_graph: bool = True, stream=None):
+        self.plans = list(plans)
+        self.nrhs = int(nrhs)
+        self._stream = stream
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        self._h = ctypes.c_void_p()
+        _check(lib().mm_mvm_batch_create(arr, len(self.plans), self.nrhs, 1 if use_graph else 0,
+                                         ctypes.byref(self._h)))
+
+    def set_schedule(self, sweep_wg_per_cu: int, grid: int):
+        _check(lib().mm_mvm_batch_set_schedule(self._h, int(sweep_wg_per_cu), int(grid)))
+
+    def run_raw(self, vcs, ycs, shift: float = 0.0):
+        """vcs, ycs: lists of contiguous (nrhs, n_k) float64 CUDA tensors (column-major n_k x nrhs)."""
+        k = len(self.plans)
+        vp = (ctypes.c_void_p * k)(*[t.data_ptr() for t in vcs])
+        yp = (ctypes.c_void_p * k)(*[t.data_ptr() for t in ycs])
+        ld = (ctypes.c_int64 * k)(*[p.n for p in self.plans])
+        _check(lib().mm_mvm_batch_run(self._h, vp, ld, yp, ld, float(shift), _stream_ptr(self._stream)))
+
+    def run(self, vs, shift: float = 0.0):
+        """vs: list of (n_k,) or (n_k, nrhs) tensors; returns the list of products."""
+        vcs = [_colmajor(v, p.n) for v, p in zip(vs, self.plans)]
+        ycs = [_torch().empty_like(vc) for vc in vcs]
+        self.run_raw(vcs, ycs, shift)
+        return [yc.view(-1) if v.dim() == 1 else yc.t() for v, yc in zip(vs, ycs)]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mm_mvm_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

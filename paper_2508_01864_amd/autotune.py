@@ -1,0 +1,116 @@
+"""Launch-schedule autotuner for batched products and solver batches.
+
+A batch runs persistent grids whose size is a free parameter: the workgroups
+per compute unit of the sweep launches and the grid of the vector-update (or
+gather/scatter) launches.  Results never depend on them (every work item runs
+the same arithmetic), so tuning only changes speed.  The tuner times each
+candidate with HIP events on the caller's stream, keeps the fastest, and
+caches the choice in a JSON file keyed by the batch's shape (its kernel
+classes, column widths and size buckets).
+
+The cache file is ``$MM_TUNE_CACHE`` if set, else ``_tune_cache.json`` next to
+this module.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Callable, Dict, Iterable, List, Sequence, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SWEEP_WG_PER_CU = (1, 2, 4, 8, 16)
+SIDE_GRID = (512, 2048, 8192)
+DEFAULT = (8, 2048)
+
+
+def cache_path() -> str:
+    return os.environ.get("MM_TUNE_CACHE", os.path.join(_HERE, "_tune_cache.json"))
+
+
+def _load() -> Dict[str, list]:
+    try:
+        with open(cache_path()) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(key: str, value: Tuple[int, int], timings: Dict[str, float]):
+    data = _load()
+    data[key] = {"schedule": list(value), "ms": timings}
+    tmp = cache_path() + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, cache_path())
+
+
+def signature(kind: str, members: Iterable[Tuple[int, int, int, str, int]]) -> str:
+    """Cache key of a batch: kind ('solver' or 'mvm'), the sorted set of
+    (d, two_nu, form, width) classes, and log2 buckets of the problem count
+    and of the total number of points."""
+    members = list(members)
+    classes = sorted(set((d, t, f, w) for (_, d, t, f, w) in members))
+    ntot = sum(m[0] for m in members)
+    return "%s|k%d|N%d|%s" % (kind, int(round(math.log2(max(len(members), 1)))),
+                              int(round(math.log2(max(ntot, 1)))),
+                              ";".join("d%d.nu%d.%s.w%d" % c for c in classes))
+
+
+def cached(key: str):
+    """The cached schedule of a batch shape, or None."""
+    hit = _load().get(key)
+    return tuple(int(v) for v in hit["schedule"]) if hit else None
+
+
+def _time(step: Callable[[], None], reps: int) -> float:
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        step()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(batch, key: str, step: Callable[[], None], reps: int = 2,
+         sweep_candidates: Sequence[int] = SWEEP_WG_PER_CU,
+         side_candidates: Sequence[int] = SIDE_GRID, use_cache: bool = True) -> Tuple[int, int]:
+    """Pick (sweep workgroups per CU, side grid) for ``batch`` (an MvmBatch or
+    SolverBatch: anything with ``set_schedule``) by timing ``step`` (one or a
+    few batch launches).  The sweep parameter is tuned first with the default
+    side grid, then the side grid with the chosen sweep parameter."""
+    if use_cache:
+        hit = _load().get(key)
+        if hit:
+            sched = tuple(int(v) for v in hit["schedule"])
+            batch.set_schedule(*sched)
+            return sched
+    timings: Dict[str, float] = {}
+    best_wg, best_t = DEFAULT[0], float("inf")
+    batch.set_schedule(DEFAULT[0], DEFAULT[1])
+    step()  # graph capture and first touch outside the timings
+    for wg in sweep_candidates:
+        batch.set_schedule(wg, DEFAULT[1])
+        step()
+        t = _time(step, reps)
+        timings["wg%d/g%d" % (wg, DEFAULT[1])] = t
+        if t < best_t:
+            best_wg, best_t = wg, t
+    best_g = DEFAULT[1]
+    for g in side_candidates:
+        if g == DEFAULT[1]:
+            continue
+        batch.set_schedule(best_wg, g)
+        step()
+        t = _time(step, reps)
+        timings["wg%d/g%d" % (best_wg, g)] = t
+        if t < best_t:
+            best_g, best_t = g, t
+    batch.set_schedule(best_wg, best_g)
+    if use_cache:
+        _store(key, (best_wg, best_g), timings)
+    return best_wg, best_g

@@ -2,7 +2,10 @@
 
 Each source in ``csrc/`` is compiled to an object in ``_build/`` (in parallel),
 then linked into ``libmaternmvm.so`` next to this file.  Every HIP object is
-built for gfx950 only, with packed-FP32 instruction selection switched off.
+built for gfx950 only, with packed-FP32 instruction selection switched off
+and without implicit multiply-add contraction: the sources write every fused
+multiply-add they want as fma(), so a computation rounds the same way in every
+kernel it is inlined into (batched and single-problem paths agree bitwise).
 """
 from __future__ import annotations
 
@@ -16,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmaternmvm.so")
-SOURCES = ["plan.hip", "sweep.hip", "api.hip", "solver.hip"]
+SOURCES = ["plan.hip", "sweep.hip", "api.hip", "solver.hip", "batch.hip"]
 ARCH = "gfx950"
 
 
@@ -29,7 +32,7 @@ def hipcc() -> str:
 
 def compile_flags():
     return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
-            "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wno-unused-result", "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I" + os.path.join(HERE, "..", "include")]
 
 

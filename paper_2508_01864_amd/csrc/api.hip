@@ -45,7 +45,7 @@ __global__ void scatter_out_kernel(const double *vin, const double *yacc, int W,
         const int r = (int)(e / n);
         const int64_t c = e - (int64_t)r * n;
         const double vv = vin[c * W + r];
-        y[(int64_t)r * ldy + perm[c]] = s2 * (vv + yacc[c * W + r]) + shift * vv;
+        y[(int64_t)r * ldy + perm[c]] = fma(shift, vv, s2 * (vv + yacc[c * W + r]));
     }
 }
 
@@ -140,6 +140,28 @@ using namespace mm;
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+namespace {
+// Release every buffer of a plan (no error state is touched).
+void plan_free(mm_plan plan) {
+    (void)hipDeviceSynchronize();
+    dev_free(plan->xc);
+    dev_free(plan->perm);
+    dev_free(plan->structure);
+    dev_free(plan->vin);
+    dev_free(plan->yacc);
+    dev_free(plan->agg);
+    dev_free(plan->part);
+    dev_free(plan->pass_dev);
+    for (auto &b : plan->pass_xt) dev_free(b);
+    for (auto &b : plan->seg_tab) dev_free(b);
+    for (auto &e : plan->prof_events) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    delete plan;
+}
+}  // namespace
+
 extern "C" {
 
 const char *mm_version(void) { return "maternmvm 0.1 (gfx950)"; }
@@ -203,7 +225,7 @@ mm_status mm_plan_create(const double *x, int64_t n, int32_t d, int64_t ldx, con
     p->last_stream = s;
     mm_status st = plan_build(p, x, ldx, s);
     if (st != MM_OK) {
-        mm_plan_destroy(p);
+        plan_free(p);
         return st;
     }
     *out = p;
@@ -217,8 +239,8 @@ mm_status mm_plan_set_kernel(mm_plan plan, const mm_kernel *kernel) {
         return MM_ERR_ARG;
     }
     MM_TRY(validate_kernel(kernel));
-    if (plan->nsolvers > 0) {
-        set_error("the plan has %d live solver(s); destroy them before changing its kernel", plan->nsolvers);
+    if (plan->npins > 0) {
+        set_error("the plan is in use by %d solver(s) or batch(es); release them before changing its kernel", plan->npins);
         return MM_ERR_ARG;
     }
     plan->kernel = *kernel;
@@ -240,26 +262,11 @@ mm_status mm_plan_info(mm_plan plan, int64_t *n, int32_t *d, mm_kernel *kernel) 
 mm_status mm_plan_destroy(mm_plan plan) {
     clear_error();
     if (!plan) return MM_OK;
-    if (plan->nsolvers > 0) {
-        set_error("the plan has %d live solver(s); destroy them first", plan->nsolvers);
+    if (plan->npins > 0) {
+        set_error("the plan is in use by %d solver(s) or batch(es); release them first", plan->npins);
         return MM_ERR_ARG;
     }
-    (void)hipDeviceSynchronize();
-    dev_free(plan->xc);
-    dev_free(plan->perm);
-    dev_free(plan->structure);
-    dev_free(plan->vin);
-    dev_free(plan->yacc);
-    dev_free(plan->agg);
-    dev_free(plan->part);
-    dev_free(plan->pass_dev);
-    for (auto &b : plan->pass_xt) dev_free(b);
-    for (auto &b : plan->seg_tab) dev_free(b);
-    for (auto &e : plan->prof_events) {
-        (void)hipEventDestroy(e.first);
-        (void)hipEventDestroy(e.second);
-    }
-    delete plan;
+    plan_free(plan);
     return MM_OK;
 }
 

@@ -103,7 +103,7 @@ struct mm_plan_s {
     mm::DevBuf agg;               // tile aggregates and anchors
     mm::DevBuf part;              // per-pass partial results of one pass group
     int64_t work_cols = 0;
-    int nsolvers = 0;             // live solvers reading this plan
+    int npins = 0;                // live solvers and product batches reading this plan
 
     // measurement
     bool profile = false;
@@ -132,6 +132,7 @@ struct BatchEntry {
 // plan's passes run as one group; false if their partial slabs would exceed
 // the group budget (such a problem runs alone through sweep_all).
 bool sweep_batch_bytes(mm_plan p, int W, size_t *agg_bytes, size_t *part_bytes);
+bool sweep_batch_bytes_n(int64_t n, int npass, int W, size_t *agg_bytes, size_t *part_bytes);
 constexpr int ACC_CHUNK = 8192;
 struct AccumDesc {
     const double *ypart;

@@ -67,7 +67,7 @@ __global__ void cg_init_b(const CgDesc *ds, const int2 *items, int nitems) {
             d.X[e] = 0.0;
             d.R[e] = b;
             d.P[e] = b;
-            acc += b * b;
+            acc = fma(b, b, acc);
         }
         block_col_sum(acc, d.W, sm, d.part, it.y);
     }
@@ -108,9 +108,9 @@ __global__ void cg_apply_b(const CgDesc *ds, const int2 *items, int nitems) {
         double acc = 0.0;
         for (int64_t e = lo * d.W + threadIdx.x; e < hi * d.W; e += BS) {
             const double p = d.P[e];
-            const double q = d.s2 * (p + d.Y[e]) + d.sigma2 * p;
+            const double q = fma(d.sigma2, p, d.s2 * (p + d.Y[e]));
             d.Q[e] = q;
-            acc += p * q;
+            acc = fma(p, q, acc);
         }
         block_col_sum(acc, d.W, sm, d.part, it.y);
     }
@@ -152,11 +152,11 @@ __global__ void cg_update_b(const CgDesc *ds, const int2 *items, int nitems) {
         const double al = d.sc[(threadIdx.x % d.W) * NS + 2];
         double acc = 0.0;
         for (int64_t e = lo * d.W + threadIdx.x; e < hi * d.W; e += BS) {
-            const double xr = d.X[e] + al * d.P[e];
-            const double rr = d.R[e] - al * d.Q[e];
+            const double xr = fma(al, d.P[e], d.X[e]);
+            const double rr = fma(-al, d.Q[e], d.R[e]);
             d.X[e] = xr;
             d.R[e] = rr;
-            acc += rr * rr;
+            acc = fma(rr, rr, acc);
         }
         block_col_sum(acc, d.W, sm, d.part, it.y);
     }
@@ -202,7 +202,7 @@ __global__ void cg_dir_b(const CgDesc *ds, const int2 *items, int nitems) {
         const int64_t hi = lo + CHUNK < len ? lo + CHUNK : len;
         for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
             const int r = (int)(e % d.W);
-            if (d.sc[r * NS + 5] != 0.0) d.P[e] = d.R[e] + d.sc[r * NS + 3] * d.P[e];
+            if (d.sc[r * NS + 5] != 0.0) d.P[e] = fma(d.sc[r * NS + 3], d.P[e], d.R[e]);
         }
     }
 }
@@ -248,7 +248,7 @@ __global__ void fe_gram_kernel(const double *X, const double *xc, int64_t n, int
         for (int64_t e = lo * W + threadIdx.x; e < hi * W; e += BS) {
             const int64_t c = e / W;
             const double h = i == 0 ? 1.0 : xc[(int64_t)(i - 1) * n + c];
-            acc += h * X[e];
+            acc = fma(h, X[e], acc);
         }
         sm[threadIdx.x] = acc;
         __syncthreads();
@@ -332,7 +332,7 @@ struct mm_solver_batch_s {
     std::vector<SweepBatch> sweeps;      // one per distinct width among the members
     DevBuf cg_desc, items_blk, items_chunk, status;
     int n_blk = 0, n_chunk = 0;
-    bool plain = false;                  // lone solver too large for one pass group
+    bool plain = false;                  // lone solver too large for a batch workspace
     hipStream_t bs = nullptr;            // private stream for graph capture and replay
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraphExec_t graph = nullptr;
@@ -380,7 +380,7 @@ mm_status batch_build(mm_solver_batch b) {
         mm_solver s = b->members[k];
         if (!s->batchable) {
             if (b->members.size() > 1) {
-                set_error("solver %zu is too large to share a batch (its passes exceed one group)", k);
+                set_error("solver %zu is too large to share a batch (its partial sums exceed 16 GiB)", k);
                 return MM_ERR_ARG;
             }
             b->plain = true;
@@ -528,6 +528,7 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
     const size_t vec = (size_t)n * W;
     size_t agg_b = 0, part_b = 0;
     sv->batchable = sweep_batch_bytes(plan, W, &agg_b, &part_b);
+    agg_b = (agg_b + 255) & ~size_t(255);
     mm_status st = dev_alloc(sv->buf, (6 * vec + (size_t)NRED * W * 8 + (size_t)W * NS + 8) * sizeof(double));
     if (st == MM_OK) {
         if (sv->batchable) {
@@ -596,7 +597,7 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
         return st;
     }
     sv->self = b;
-    plan->nsolvers++;
+    plan->npins++;
     plan->last_stream = s;
     *out = sv;
     return MM_OK;
@@ -719,6 +720,29 @@ mm_status status_of(int conv, int ncols, int brk, int iters, double rel) {
 
 extern "C" {
 
+size_t mm_solver_footprint_bytes(int64_t n, int32_t d, int32_t fixed_effects, const mm_kernel *kernel) {
+    if (n < 1 || d < 1 || d > 3 || !kernel) return 0;
+    if (kernel->two_nu != 1 && kernel->two_nu != 3 && kernel->two_nu != 5) return 0;
+    const int ncols = fixed_effects ? d + 2 : 1;
+    const int R = rhs_block(*kernel, d, ncols);
+    const int W = pow2ceil(ncols > R ? ncols : R);
+    int L = 0;
+    while ((int64_t(1) << L) < n) ++L;
+    const int npass = n < 2 ? 0 : (d == 1 ? 1 : (d == 2 ? L : L * (L + 1) / 2));
+    size_t b = ((size_t)6 * n * W + (size_t)NRED * W * 8 + (size_t)W * NS + 8) * sizeof(double);
+    size_t agg_b = 0, part_b = 0;
+    if (sweep_batch_bytes_n(n, npass, W, &agg_b, &part_b)) {
+        b += ((agg_b + 255) & ~size_t(255)) + part_b;
+    } else {  // a lone solver sweeps in the plan's work buffers
+        b += 2 * (size_t)n * W * sizeof(double) + sweep_agg_bytes(n, d, W, *kernel) + sweep_part_bytes(n, npass, W);
+    }
+    // work tables of a batch: sweep items (at most three per pass, tile of 256 and
+    // column block) and the vector-update items
+    const int64_t ntile = (n + 255) / 256;
+    b += (size_t)3 * (npass + 1) * (ntile + 1) * W * 16 + (size_t)NRED * 8 + (size_t)(n * W / CHUNK + 1) * 8;
+    return b;
+}
+
 mm_status mm_solver_create(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects, double rtol,
                            void *stream, mm_solver *out) {
     clear_error();
@@ -793,7 +817,7 @@ mm_status mm_solver_destroy(mm_solver solver) {
         batch_free(solver->self);
         delete solver->self;
     }
-    solver->plan->nsolvers--;
+    solver->plan->npins--;
     dev_free(solver->ws);
     dev_free(solver->buf);
     delete solver;

@@ -71,8 +71,8 @@ __device__ __forceinline__ void tgt_vec(double E, double t, double (&gv)[P]) {
         gv[0] = E * (1.0 + t);
         gv[1] = E;
     } else {
-        gv[0] = E * (1.0 + t + t * t * (1.0 / 3.0));
-        gv[1] = E * (1.0 + t * (2.0 / 3.0));
+        gv[0] = E * fma(t * (1.0 / 3.0), t, 1.0 + t);
+        gv[1] = E * fma(t, 2.0 / 3.0, 1.0);
         gv[2] = E * (2.0 / 3.0);
     }
 }
@@ -163,8 +163,8 @@ struct State {
         for (int c = 0; c < C::NCLS; ++c)
 #pragma unroll
             for (int h = 0; h < C::NTH; ++h) {
-                if constexpr (C::P == 3) s[c][h][2] = E * (s[c][h][2] + t * s[c][h][1] + t2 * s[c][h][0]);
-                if constexpr (C::P >= 2) s[c][h][1] = E * (s[c][h][1] + t * s[c][h][0]);
+                if constexpr (C::P == 3) s[c][h][2] = E * fma(t2, s[c][h][0], fma(t, s[c][h][1], s[c][h][2]));
+                if constexpr (C::P >= 2) s[c][h][1] = E * fma(t, s[c][h][0], s[c][h][1]);
                 s[c][h][0] = E * s[c][h][0];
             }
     }
@@ -176,9 +176,10 @@ struct State {
         for (int c = 0; c < C::NCLS; ++c)
 #pragma unroll
             for (int h = 0; h < C::NTH; ++h) {
-                if constexpr (C::P == 3) s[c][h][2] += E * (o.s[c][h][2] + t * o.s[c][h][1] + t2 * o.s[c][h][0]);
-                if constexpr (C::P >= 2) s[c][h][1] += E * (o.s[c][h][1] + t * o.s[c][h][0]);
-                s[c][h][0] += E * o.s[c][h][0];
+                if constexpr (C::P == 3)
+                    s[c][h][2] = fma(E, fma(t2, o.s[c][h][0], fma(t, o.s[c][h][1], o.s[c][h][2])), s[c][h][2]);
+                if constexpr (C::P >= 2) s[c][h][1] = fma(E, fma(t, o.s[c][h][0], o.s[c][h][1]), s[c][h][1]);
+                s[c][h][0] = fma(E, o.s[c][h][0], s[c][h][0]);
             }
     }
 
@@ -249,10 +250,10 @@ __device__ __forceinline__ void add_source(State<C> &S, int cls, const ElemVec<C
 #pragma unroll
         for (int h = 0; h < C::NTH; ++h) {
             if constexpr (C::PROD) {
-                S.s[c][h][0] += ev.f[h] * vc;
+                S.s[c][h][0] = fma(ev.f[h], vc, S.s[c][h][0]);
             } else {
 #pragma unroll
-                for (int m = 0; m < C::P; ++m) S.s[c][h][m] += ev.f[m] * vc;
+                for (int m = 0; m < C::P; ++m) S.s[c][h][m] = fma(ev.f[m], vc, S.s[c][h][m]);
             }
         }
     }
@@ -270,11 +271,11 @@ __device__ __forceinline__ double read_target(const State<C> &S, int cls, const 
             if constexpr (C::PROD) {
                 double row = S.s[c][h][0];
 #pragma unroll
-                for (int m = 1; m < C::P; ++m) row += coef<C::P>(m) * S.s[c][h][m];
-                acc += ev.g[h] * row;
+                for (int m = 1; m < C::P; ++m) row = fma(coef<C::P>(m), S.s[c][h][m], row);
+                acc = fma(ev.g[h], row, acc);
             } else {
 #pragma unroll
-                for (int m = 0; m < C::P; ++m) acc += ev.g[m] * S.s[c][h][m];
+                for (int m = 0; m < C::P; ++m) acc = fma(ev.g[m], S.s[c][h][m], acc);
             }
         }
         out += (c == cls) ? acc : 0.0;
@@ -424,9 +425,9 @@ __device__ __forceinline__ void scan_step(State<C> &F, int o, double xto, bool o
             for (int m = 0; m < C::P; ++m)
                 q[m] = UP ? __shfl_up(F.s[c][h][m], dl, WAVE) : __shfl_down(F.s[c][h][m], dl, WAVE);
             if (ok) {
-                if constexpr (C::P == 3) F.s[c][h][2] += E * (q[2] + t * q[1] + t2 * q[0]);
-                if constexpr (C::P >= 2) F.s[c][h][1] += E * (q[1] + t * q[0]);
-                F.s[c][h][0] += E * q[0];
+                if constexpr (C::P == 3) F.s[c][h][2] = fma(E, fma(t2, q[0], fma(t, q[1], q[2])), F.s[c][h][2]);
+                if constexpr (C::P >= 2) F.s[c][h][1] = fma(E, fma(t, q[0], q[1]), F.s[c][h][1]);
+                F.s[c][h][0] = fma(E, q[0], F.s[c][h][0]);
             }
         }
 }
@@ -737,8 +738,8 @@ __device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int b
                     const double x = xs8[k];
                     const double tt = a * (dir == 0 ? x - xprev : xprev - x);
                     const double E = exp(-tt);
-                    if constexpr (C::P == 3) acc[2] = E * (acc[2] + tt * acc[1] + 0.5 * tt * tt * acc[0]);
-                    if constexpr (C::P >= 2) acc[1] = E * (acc[1] + tt * acc[0]);
+                    if constexpr (C::P == 3) acc[2] = E * fma(0.5 * tt * tt, acc[0], fma(tt, acc[1], acc[2]));
+                    if constexpr (C::P >= 2) acc[1] = E * fma(tt, acc[0], acc[1]);
                     acc[0] = E * acc[0];
 #pragma unroll
                     for (int m = 0; m < C::P; ++m) acc[m] += g8[k][m];
@@ -756,9 +757,9 @@ __device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int b
             if (ok) {
                 const double tt = a * (dir == 0 ? xa - xp : xp - xa);
                 const double E = exp(-tt);
-                if constexpr (C::P == 3) acc[2] += E * (q[2] + tt * q[1] + 0.5 * tt * tt * q[0]);
-                if constexpr (C::P >= 2) acc[1] += E * (q[1] + tt * q[0]);
-                acc[0] += E * q[0];
+                if constexpr (C::P == 3) acc[2] = fma(E, fma(0.5 * tt * tt, q[0], fma(tt, q[1], q[2])), acc[2]);
+                if constexpr (C::P >= 2) acc[1] = fma(E, fma(tt, q[0], q[1]), acc[1]);
+                acc[0] = fma(E, q[0], acc[0]);
             }
         }
         // exclusive value entering the chunk
@@ -784,8 +785,8 @@ __device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int b
                     const double xn = anc[t - step];
                     const double tt = a * (dir == 0 ? xn - xe : xe - xn);
                     const double E = exp(-tt);
-                    if constexpr (C::P == 3) ex[2] = E * (ex[2] + tt * ex[1] + 0.5 * tt * tt * ex[0]);
-                    if constexpr (C::P >= 2) ex[1] = E * (ex[1] + tt * ex[0]);
+                    if constexpr (C::P == 3) ex[2] = E * fma(0.5 * tt * tt, ex[0], fma(tt, ex[1], ex[2]));
+                    if constexpr (C::P >= 2) ex[1] = E * fma(tt, ex[0], ex[1]);
                     ex[0] = E * ex[0];
                     xe = xn;
 #pragma unroll
@@ -796,8 +797,8 @@ __device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int b
                     const double tt = a * (dir == 0 ? x - xe : xe - x);
                     const double E = first ? 1.0 : exp(-tt);
                     if (!first) {
-                        if constexpr (C::P == 3) ex[2] = E * (ex[2] + tt * ex[1] + 0.5 * tt * tt * ex[0]);
-                        if constexpr (C::P >= 2) ex[1] = E * (ex[1] + tt * ex[0]);
+                        if constexpr (C::P == 3) ex[2] = E * fma(0.5 * tt * tt, ex[0], fma(tt, ex[1], ex[2]));
+                        if constexpr (C::P >= 2) ex[1] = E * fma(tt, ex[0], ex[1]);
                         ex[0] = E * ex[0];
                     }
 #pragma unroll
@@ -1048,14 +1049,21 @@ size_t sweep_agg_bytes(int64_t n, int d, int W, const mm_kernel &k) {
     return agg_bytes_for(n, W, G);
 }
 
-bool sweep_batch_bytes(mm_plan p, int W, size_t *agg_bytes, size_t *part_bytes) {
-    const int npass = (int)p->passes.size();
-    const size_t slab = (size_t)p->n * W * sizeof(double);
-    if (npass > 0 && (size_t)npass * slab > PART_BUDGET) return false;
+// A batched problem runs all its passes as one group, its partial slabs in a
+// workspace of its own; up to 16 GiB of them per problem.
+constexpr size_t BATCH_PART_BUDGET = size_t(16) << 30;
+
+bool sweep_batch_bytes_n(int64_t n, int npass, int W, size_t *agg_bytes, size_t *part_bytes) {
+    const size_t slab = (size_t)n * W * sizeof(double);
+    if (npass > 0 && (size_t)npass * slab > BATCH_PART_BUDGET) return false;
     const int64_t G = npass > 0 ? npass : 1;
     *part_bytes = (size_t)G * slab;
-    *agg_bytes = agg_bytes_for(p->n, W, G);
+    *agg_bytes = agg_bytes_for(n, W, G);
     return true;
+}
+
+bool sweep_batch_bytes(mm_plan p, int W, size_t *agg_bytes, size_t *part_bytes) {
+    return sweep_batch_bytes_n(p->n, (int)p->passes.size(), W, agg_bytes, part_bytes);
 }
 
 mm_status upload_pass_tables(mm_plan p) {

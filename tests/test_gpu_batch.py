@@ -172,3 +172,37 @@ def test_live_solvers_pin_their_plan(oracle_lib):
     s1.close()
     p1.set_kernel(mm.Kernel(1, "product", 0.3))
     p1.close()
+
+
+@pytest.mark.parametrize("use_graph,nrhs", [(False, 1), (True, 1), (True, 4)])
+def test_mvm_batch_equals_matern_mvm(oracle_lib, use_graph, nrhs):
+    """Batched products of uneven problems: bitwise the single-plan products, over
+    repeated runs with new input and output buffers."""
+    rng = np.random.default_rng(77)
+    probs = []
+    for k in range(9):
+        n = int(np.exp(rng.uniform(np.log(2), np.log(6000)))) if k else 1
+        d = 1 + k % 3
+        two_nu = [1, 3, 5][(k // 3) % 3]
+        form = "l1" if (k % 4 == 3 and two_nu > 1) else "product"
+        probs.append((rng.uniform(0, 1, (n, d)), two_nu, form, float(np.exp(rng.uniform(np.log(0.05), np.log(0.5))))))
+    plans = [mm.Plan(to_gpu(x), mm.Kernel(t, f, l, 1.7)) for x, t, f, l in probs]
+    batch = mm.MvmBatch(plans, nrhs=nrhs, use_graph=use_graph)
+    for rep in range(3):
+        vs = [to_gpu(rng.standard_normal((p.n, nrhs)) if nrhs > 1 else rng.standard_normal(p.n)) for p in plans]
+        ys = batch.run(vs, shift=0.03)
+        for (x, t, f, l), p, v, y in zip(probs, plans, vs, ys):
+            y0 = p.mvm(v, shift=0.03)
+            assert np.array_equal(to_np(y), to_np(y0)), "rep %d n=%d d=%d" % (rep, p.n, p.d)
+    # one problem against the oracle
+    x, t, f, l = probs[4]
+    v = rng.standard_normal(plans[4].n)
+    vs = [to_gpu(rng.standard_normal(p.n) if nrhs == 1 else rng.standard_normal((p.n, nrhs))) for p in plans]
+    vs[4] = to_gpu(v if nrhs == 1 else np.repeat(v[:, None], nrhs, axis=1))
+    ys = batch.run(vs)
+    yref, yabs = oracle.mvm(x, v, t, f, l, s2=1.7, with_abs=True)
+    got = to_np(ys[4]) if nrhs == 1 else to_np(ys[4])[:, 0]
+    assert np.max(np.abs(got - yref) / yabs) <= 1e-10
+    batch.close()
+    for p in plans:
+        p.close()
