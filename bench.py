@@ -222,6 +222,11 @@ def main():
     ap.add_argument("--served-count", type=int, default=8)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--maxit", type=int, default=20000,
+                    help="CG iteration limit (below the default only for short profiling runs)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run a device-to-device copy of this many MiB three times before the "
+                         "steps (a known-size kernel for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -249,7 +254,8 @@ def main():
         if profile:
             plan.profile_enable(True)
         y1 = plan.mvm(v)
-        alpha, beta, info = plan.cg_solve(y, SIGMA2, fixed_effects=True, rtol=RTOL, maxit=20000)
+        alpha, beta, info = plan.cg_solve(y, SIGMA2, fixed_effects=True, rtol=RTOL, maxit=args.maxit,
+                                          raise_on_error=args.maxit >= 20000)
         mean = plan.predict(alpha, z, beta=beta)
         prof = plan.profile_read() if profile else (0.0, 0, 0)
         plan.close()
@@ -257,6 +263,15 @@ def main():
         pts = N * cols + (N + NPREDICT)      # + predict on the union of points
         sweep_bytes = L * (b_pass(N, 1) + info["iters"] * b_pass(N, 4))
         return pts, info, prof, sweep_bytes, (y1, alpha, beta, mean)
+
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib * 131072, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB read + %d MiB written per launch" % (args.calib_copy_mib, args.calib_copy_mib))
+        del src, dst
 
     for w in range(args.warmup):
         log("warmup step %d" % w)

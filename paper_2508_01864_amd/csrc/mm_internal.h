@@ -133,7 +133,7 @@ struct BatchEntry {
 // the group budget (such a problem runs alone through sweep_all).
 bool sweep_batch_bytes(mm_plan p, int W, size_t *agg_bytes, size_t *part_bytes);
 bool sweep_batch_bytes_n(int64_t n, int npass, int W, size_t *agg_bytes, size_t *part_bytes);
-constexpr int ACC_CHUNK = 8192;
+constexpr int ACC_CHUNK = 2048;
 struct AccumDesc {
     const double *ypart;
     double *yacc;
@@ -149,10 +149,12 @@ struct SweepBatch {
         int n_agg = 0, n_carry = 0, n_main = 0;
     };
     std::vector<Cls> classes;
+    std::vector<mm_plan> plans;  // the problems' plans (a lone plan's profiling brackets the main launch)
     DevBuf acc_desc, acc_items;
     int n_acc = 0;
     int W = 1, WB = 1;
     int grid_per_cu = 8;  // persistent grid: workgroups per compute unit (tuned)
+    bool skip_accum = false;  // leave the per-pass partials unsummed (the consumer sums them)
 };
 mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB, SweepBatch &out);
 mm_status sweep_batch_run(SweepBatch &b, hipStream_t s);

@@ -21,12 +21,15 @@ constexpr int BS = 256;
 constexpr int NRED = 256;  // row blocks of the column dot products (fixed: deterministic sums)
 constexpr int NS = 8;      // scalars per column: [0] r.r [1] p.Ap [2] alpha [3] beta
                            // [4] |b| [5] active [6] iterations while active [7] |r|
-constexpr int CHUNK = 4096;
+constexpr int CHUNK = 1024;
+static_assert(NRED == BS, "one thread per reduction block in the scalar kernels");
 
 struct CgDesc {
     const double *B;
     double *X, *R, *P, *Q, *Y;
     double *part;  // NRED x W partial column sums
+    const double *slabs;  // per-pass partial products of P (nslab of n x W), or
+    int nslab;            //   nslab < 0: the product is already summed in Y
     double *sc;    // W x NS
     int *flags;    // [0] active columns after the last update, [1] breakdown seen
     int64_t n;
@@ -53,6 +56,22 @@ __device__ __forceinline__ void block_col_sum(double acc, int W, double *sm, dou
     __syncthreads();
 }
 
+// tot[r] = sum over the NRED row blocks of part[b][r] for every column r < W,
+// by a fixed binary tree (deterministic); one workgroup of BS threads.
+__device__ __forceinline__ void reduce_cols(const double *part, int W, double *red, double *tot) {
+    const int t = threadIdx.x;
+    for (int r = 0; r < W; ++r) {
+        red[t] = part[(int64_t)t * W + r];
+        __syncthreads();
+        for (int h = BS / 2; h > 0; h >>= 1) {
+            if (t < h) red[t] += red[t + h];
+            __syncthreads();
+        }
+        if (t == 0) tot[r] = red[0];
+        __syncthreads();
+    }
+}
+
 // x0 = 0, r0 = b, p0 = r0, partial |b|^2
 __global__ void cg_init_b(const CgDesc *ds, const int2 *items, int nitems) {
     __shared__ double sm[BS];
@@ -74,12 +93,14 @@ __global__ void cg_init_b(const CgDesc *ds, const int2 *items, int nitems) {
 }
 
 __global__ void cg_init_scalars_b(const CgDesc *ds, int nsol) {
+    __shared__ double red[BS];
+    __shared__ double tot[64];
     for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
         const CgDesc d = ds[k];
+        reduce_cols(d.part, d.W, red, tot);
         const int r = threadIdx.x;
         if (r < d.W) {
-            double s = 0.0;
-            for (int b = 0; b < NRED; ++b) s += d.part[(int64_t)b * d.W + r];
+            const double s = tot[r];
             double *c = d.sc + r * NS;
             c[0] = s;
             c[1] = 0.0;
@@ -94,6 +115,7 @@ __global__ void cg_init_scalars_b(const CgDesc *ds, int nsol) {
             d.flags[0] = 0;
             d.flags[1] = 0;
         }
+        __syncthreads();
     }
 }
 
@@ -106,9 +128,17 @@ __global__ void cg_apply_b(const CgDesc *ds, const int2 *items, int nitems) {
         int64_t lo, hi;
         row_range(d.n, it.y, lo, hi);
         double acc = 0.0;
+        const int64_t len = d.n * d.W;
         for (int64_t e = lo * d.W + threadIdx.x; e < hi * d.W; e += BS) {
             const double p = d.P[e];
-            const double q = fma(d.sigma2, p, d.s2 * (p + d.Y[e]));
+            double y;
+            if (d.nslab < 0) {
+                y = d.Y[e];
+            } else {  // the product's per-pass partials, summed in pass order
+                y = 0.0;
+                for (int g = 0; g < d.nslab; ++g) y += d.slabs[(int64_t)g * len + e];
+            }
+            const double q = fma(d.sigma2, p, d.s2 * (p + y));
             d.Q[e] = q;
             acc = fma(p, q, acc);
         }
@@ -118,26 +148,30 @@ __global__ void cg_apply_b(const CgDesc *ds, const int2 *items, int nitems) {
 
 // alpha = r.r / p.Ap per active column; non-positive curvature = breakdown
 __global__ void cg_alpha_b(const CgDesc *ds, int nsol) {
+    __shared__ double red[BS];
+    __shared__ double tot[64];
     for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
         const CgDesc d = ds[k];
+        reduce_cols(d.part, d.W, red, tot);
         const int r = threadIdx.x;
-        if (r >= d.W) continue;
-        double s = 0.0;
-        for (int b = 0; b < NRED; ++b) s += d.part[(int64_t)b * d.W + r];
-        double *c = d.sc + r * NS;
-        c[1] = s;
-        if (c[5] != 0.0) {
-            if (!(s > 0.0)) {
-                d.flags[1] = 1;
-                c[2] = 0.0;
-                c[5] = 0.0;
+        if (r < d.W) {
+            const double s = tot[r];
+            double *c = d.sc + r * NS;
+            c[1] = s;
+            if (c[5] != 0.0) {
+                if (!(s > 0.0)) {
+                    d.flags[1] = 1;
+                    c[2] = 0.0;
+                    c[5] = 0.0;
+                } else {
+                    c[2] = c[0] / s;
+                    c[6] += 1.0;
+                }
             } else {
-                c[2] = c[0] / s;
-                c[6] += 1.0;
+                c[2] = 0.0;
             }
-        } else {
-            c[2] = 0.0;
         }
+        __syncthreads();
     }
 }
 
@@ -169,26 +203,30 @@ __global__ void cg_reset_active_b(const CgDesc *ds, int nsol) {
 
 // beta = r.r(new) / r.r(old); columns reaching the tolerance are frozen
 __global__ void cg_beta_b(const CgDesc *ds, int nsol) {
+    __shared__ double red[BS];
+    __shared__ double tot[64];
     for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
         const CgDesc d = ds[k];
+        reduce_cols(d.part, d.W, red, tot);
         const int r = threadIdx.x;
-        if (r >= d.W) continue;
-        double s = 0.0;
-        for (int b = 0; b < NRED; ++b) s += d.part[(int64_t)b * d.W + r];
-        double *c = d.sc + r * NS;
-        if (c[5] != 0.0) {
-            if (sqrt(s) <= d.rtol * c[4]) {
-                c[5] = 0.0;
-                c[3] = 0.0;
+        if (r < d.W) {
+            const double s = tot[r];
+            double *c = d.sc + r * NS;
+            if (c[5] != 0.0) {
+                if (sqrt(s) <= d.rtol * c[4]) {
+                    c[5] = 0.0;
+                    c[3] = 0.0;
+                } else {
+                    c[3] = s / c[0];
+                    atomicAdd(&d.flags[0], 1);  // integer count of still-active columns
+                }
+                c[7] = sqrt(s);
+                c[0] = s;
             } else {
-                c[3] = s / c[0];
-                atomicAdd(&d.flags[0], 1);  // integer count of still-active columns
+                c[3] = 0.0;
             }
-            c[7] = sqrt(s);
-            c[0] = s;
-        } else {
-            c[3] = 0.0;
         }
+        __syncthreads();
     }
 }
 
@@ -407,6 +445,7 @@ mm_status batch_build(mm_solver_batch b) {
             const int WB = rhs_block((*first)->plan->kernel, (*first)->d, widths[w]);
             MM_TRY(sweep_batch_build(ent, widths[w], WB, b->sweeps[w]));
             b->sweeps[w].grid_per_cu = b->wg_per_cu;
+            b->sweeps[w].skip_accum = true;  // cg_apply sums the per-pass partials itself
         }
     }
     MM_TRY(upload_vec(b->cg_desc, descs));
@@ -559,6 +598,8 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
     d.part = base + 6 * vec;
     d.sc = d.part + (size_t)NRED * W * 8;
     d.flags = reinterpret_cast<int *>(d.sc + (size_t)W * NS);
+    d.slabs = sv->part;
+    d.nslab = sv->batchable ? (int)plan->passes.size() : -1;
     d.n = n;
     d.W = W;
     d.ncols = ncols;

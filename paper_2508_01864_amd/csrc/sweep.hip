@@ -855,6 +855,29 @@ inline unsigned grid_1d(int64_t n) {
 
 inline int tile_index(int T) { return T >= 1024 ? 2 : (T >= 512 ? 1 : 0); }
 
+// When the plan's profiling is on, record an event before the main sweep
+// launch on its stream and return the closing event to record after it.
+mm_status profile_begin(mm_plan p, int passes_covered, hipStream_t s, hipEvent_t *ev1) {
+    *ev1 = nullptr;
+    if (!p->profile) return MM_OK;
+    if (p->prof_used >= 4096) {
+        double ms = 0.0;
+        int64_t cnt = 0;
+        MM_TRY(profile_flush(p, &ms, &cnt));
+    }
+    if (p->prof_used >= p->prof_events.size()) {
+        hipEvent_t e0, e1;
+        MM_HIP_TRY(hipEventCreate(&e0));
+        MM_HIP_TRY(hipEventCreate(&e1));
+        p->prof_events.push_back({e0, e1});
+    }
+    MM_HIP_TRY(hipEventRecord(p->prof_events[p->prof_used].first, s));
+    *ev1 = p->prof_events[p->prof_used].second;
+    p->prof_used++;
+    p->prof_units += (int64_t)passes_covered;
+    return MM_OK;
+}
+
 template <class C>
 mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStream_t s) {
     static_assert(C::T == 256 || C::T == 512 || C::T == 1024, "tile sizes with a cross-tile pass list");
@@ -910,24 +933,7 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
                                    dim3(256), 0, s, A);
         }
         hipEvent_t ev1 = nullptr;
-        if (p->profile) {
-            // bracket the main sweep launch with events on its stream
-            if (p->prof_used >= 4096) {
-                double ms = 0.0;
-                int64_t cnt = 0;
-                MM_TRY(profile_flush(p, &ms, &cnt));
-            }
-            if (p->prof_used >= p->prof_events.size()) {
-                hipEvent_t e0, e1;
-                MM_HIP_TRY(hipEventCreate(&e0));
-                MM_HIP_TRY(hipEventCreate(&e1));
-                p->prof_events.push_back({e0, e1});
-            }
-            MM_HIP_TRY(hipEventRecord(p->prof_events[p->prof_used].first, s));
-            ev1 = p->prof_events[p->prof_used].second;
-            p->prof_used++;
-            p->prof_units += (int64_t)G;
-        }
+        MM_TRY(profile_begin(p, G, s, &ev1));
         hipLaunchKernelGGL((sweep_kernel<C, 0>), dim3((unsigned)(G * ntile), (unsigned)ncb), dim3(WAVE), 0, s, A);
         if (ev1) MM_HIP_TRY(hipEventRecord(ev1, s));
         hipLaunchKernelGGL(accum_kernel, dim3(grid_1d(len)), dim3(BS1), 0, s,
@@ -1159,6 +1165,7 @@ mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB,
     sweep_batch_free(out);
     out.W = W;
     out.WB = WB;
+    for (const BatchEntry &e : probs) out.plans.push_back(e.p);
     // group the problems by kernel configuration
     std::vector<int> keys;
     for (size_t k = 0; k < probs.size(); ++k) {
@@ -1242,14 +1249,18 @@ mm_status sweep_batch_run(SweepBatch &b, hipStream_t s) {
             if (cl.n_carry > 0)
                 hipLaunchKernelGGL((carry_batch_kernel<C>), dim3(persist_grid(cl.n_carry, b.grid_per_cu)), dim3(256),
                                    0, s, descs, static_cast<const int4 *>(cl.items_carry.ptr), cl.n_carry);
-            if (cl.n_main > 0)
+            if (cl.n_main > 0) {
+                hipEvent_t ev1 = nullptr;
+                if (b.plans.size() == 1) MM_TRY(profile_begin(b.plans[0], (int)b.plans[0]->passes.size(), s, &ev1));
                 hipLaunchKernelGGL((sweep_batch_kernel<C, 0>), dim3(persist_grid(cl.n_main, b.grid_per_cu)), dim3(WAVE),
                                    0, s, descs, static_cast<const int4 *>(cl.items_main.ptr), cl.n_main);
+                if (ev1) MM_HIP_TRY(hipEventRecord(ev1, s));
+            }
             return MM_OK;
         }));
     }
-    if (b.n_acc > 0)
-        hipLaunchKernelGGL(accum_batch_kernel, dim3(persist_grid(b.n_acc, 4)), dim3(256), 0, s,
+    if (b.n_acc > 0 && !b.skip_accum)
+        hipLaunchKernelGGL(accum_batch_kernel, dim3(persist_grid(b.n_acc, 16)), dim3(256), 0, s,
                            static_cast<const AccumDesc *>(b.acc_desc.ptr), static_cast<const int2 *>(b.acc_items.ptr),
                            b.n_acc);
     MM_HIP_TRY(hipGetLastError());
@@ -1264,6 +1275,7 @@ void sweep_batch_free(SweepBatch &b) {
         dev_free(cl.items_main);
     }
     b.classes.clear();
+    b.plans.clear();
     dev_free(b.acc_desc);
     dev_free(b.acc_items);
     b.n_acc = 0;
