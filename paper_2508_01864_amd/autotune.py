@@ -21,7 +21,7 @@ from typing import Callable, Dict, Iterable, List, Sequence, Tuple
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SWEEP_WG_PER_CU = (1, 2, 4, 8, 16)
 SIDE_GRID = (512, 2048, 8192)
-DEFAULT = (8, 2048)
+DEFAULT = (16, 2048)
 
 
 def cache_path() -> str:

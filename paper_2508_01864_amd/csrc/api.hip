@@ -147,6 +147,7 @@ void plan_free(mm_plan plan) {
     dev_free(plan->xc);
     dev_free(plan->perm);
     dev_free(plan->structure);
+    dev_free(plan->geo);
     dev_free(plan->vin);
     dev_free(plan->yacc);
     dev_free(plan->agg);

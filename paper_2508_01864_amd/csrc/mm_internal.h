@@ -57,8 +57,13 @@ void dev_free(DevBuf &b);
 //          (x1, x2) order ord2, segments of 2^(l2+1) positions, sorted by x3.
 // ---------------------------------------------------------------------------
 struct Pass {
-    const int32_t *ord = nullptr;   // position -> canonical index (d=2) or q (d=3)
-    const int32_t *ord2 = nullptr;  // d=3: q -> canonical index of level l1
+    const int32_t *ord = nullptr;   // build only: position -> canonical index (d=2) or q (d=3)
+    const int32_t *ord2 = nullptr;  // build only, d=3: q -> canonical index of level l1
+    // geometry in pass order, read by the sweeps (d >= 2):
+    const uint32_t *cf = nullptr;   // canonical index | x1 half << 30 | x2 half << 31
+    const double *xs = nullptr;     // scan (last) coordinate
+    const double *w1 = nullptr;     // |x1 - x1 of the node's split point|
+    const double *w2 = nullptr;     // d=3: |x2 - x2 of the x2 node's split point|
     int l1 = -1;
     int l2 = -1;
     int seg_log2 = 0;               // segment size 2^seg_log2 positions
@@ -89,7 +94,8 @@ struct mm_plan_s {
 
     mm::DevBuf xc;                // d x n canonical coordinates (SoA, x1-rank order)
     mm::DevBuf perm;              // n int32: canonical index -> caller index
-    mm::DevBuf structure;         // all stored orders (int32)
+    mm::DevBuf structure;         // stored orders (int32; released once the pass geometry is built)
+    mm::DevBuf geo;               // per-pass geometry in pass order (cf, xs, w1, w2)
     std::vector<mm::Pass> passes;
     mm::DevBuf pass_dev;          // device table of the passes
     mm::DevBuf pass_xt[3];        // per tile size (256, 512, 1024 positions): passes whose
@@ -153,7 +159,7 @@ struct SweepBatch {
     DevBuf acc_desc, acc_items;
     int n_acc = 0;
     int W = 1, WB = 1;
-    int grid_per_cu = 8;  // persistent grid: workgroups per compute unit (tuned)
+    int grid_per_cu = 16;  // persistent grid: workgroups per compute unit (tuned)
     bool skip_accum = false;  // leave the per-pass partials unsummed (the consumer sums them)
 };
 mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB, SweepBatch &out);

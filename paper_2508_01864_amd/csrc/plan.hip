@@ -306,6 +306,39 @@ __global__ void gather_coords(const double *x, int64_t ldx, int64_t n, int d, co
     }
 }
 
+// Geometry of one pass in pass order.  d = 2 (pass = x1 level l1): the
+// point's x1 half within its node, its x1 offset from the node's split point
+// (the first point of the right half) and its x2.  d = 3 (pass = (l1, l2)):
+// also the x2 half within the x2 node and the x2 offset from that node's split.
+template <int D>
+__global__ void pass_geo_kernel(const int32_t *ord, const int32_t *ord2, int l1, int l2, const double *xc,
+                                int64_t n, uint32_t *cf, double *xs, double *w1, double *w2) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        if constexpr (D == 2) {
+            const int64_t c = ord[p];
+            const uint32_t side1 = (uint32_t)((c >> l1) & 1);
+            int64_t sp = ((c >> (l1 + 1)) << (l1 + 1)) + (int64_t(1) << l1);
+            if (sp > n - 1) sp = n - 1;
+            w1[p] = fabs(xc[c] - xc[sp]);
+            xs[p] = xc[n + c];
+            cf[p] = (uint32_t)c | (side1 << 30);
+        } else {
+            const int64_t q = ord[p];
+            const int64_t c = ord2[q];
+            const uint32_t side1 = (uint32_t)((c >> l1) & 1);
+            const uint32_t side2 = (uint32_t)((q >> l2) & 1);
+            int64_t sp1 = ((c >> (l1 + 1)) << (l1 + 1)) + (int64_t(1) << l1);
+            if (sp1 > n - 1) sp1 = n - 1;
+            int64_t sq2 = ((q >> (l2 + 1)) << (l2 + 1)) + (int64_t(1) << l2);
+            if (sq2 > n - 1) sq2 = n - 1;
+            w1[p] = fabs(xc[c] - xc[sp1]);
+            w2[p] = fabs(xc[n + c] - xc[n + ord2[sq2]]);
+            xs[p] = xc[2 * n + c];
+            cf[p] = (uint32_t)c | (side1 << 30) | (side2 << 31);
+        }
+    }
+}
+
 __global__ void invert_kernel(const int32_t *ord, int64_t n, int32_t *inv) {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x)
@@ -436,10 +469,20 @@ size_t structure_ints(int64_t n, int d) {
     return (size_t)L * n + (size_t)L * (L + 1) / 2 * n;
 }
 
+// Bytes of the per-pass geometry: 4 (index and halves) + 8 (scan coordinate)
+// + 8 per offset coordinate, per point and pass.
+size_t geo_bytes(int64_t n, int d) {
+    if (d == 1 || n < 2) return 0;
+    const int L = ceil_log2(n);
+    const size_t npass = d == 2 ? (size_t)L : (size_t)L * (L + 1) / 2;
+    return npass * (size_t)n * (4 + 8 * (size_t)d);
+}
+
 size_t plan_footprint(int64_t n, int d, int nrhs, const mm_kernel &k) {
     const int R = rhs_block(k, d, nrhs);
     const int64_t W = (nrhs + R - 1) / R * R;
-    size_t b = (size_t)d * n * 8 + (size_t)n * 4 + structure_ints(n, d) * 4;
+    // the stored orders and the geometry coexist while the plan is built
+    size_t b = (size_t)d * n * 8 + (size_t)n * 4 + structure_ints(n, d) * 4 + geo_bytes(n, d);
     b += 2 * (size_t)n * W * 8;                       // product buffers
     b += sweep_agg_bytes(n, d, (int)W, k);
     {
@@ -570,11 +613,41 @@ mm_status plan_build(mm_plan p, const double *x, int64_t ldx, hipStream_t s) {
             }
         }
     }
+    // geometry of every pass in pass order; the orders are not needed afterwards
+    if (d >= 2 && n >= 2) {
+        BUILD_TRY(dev_alloc(p->geo, geo_bytes(n, d)));
+        const size_t np = p->passes.size();
+        double *g = static_cast<double *>(p->geo.ptr);
+        double *gxs = g;
+        double *gw1 = g + np * n;
+        double *gw2 = d == 3 ? g + 2 * np * n : nullptr;
+        uint32_t *gcf = reinterpret_cast<uint32_t *>(g + (size_t)d * np * n);
+        for (size_t i = 0; i < np; ++i) {
+            Pass &ps = p->passes[i];
+            ps.xs = gxs + i * n;
+            ps.w1 = gw1 + i * n;
+            ps.w2 = d == 3 ? gw2 + i * n : nullptr;
+            ps.cf = gcf + i * n;
+            if (d == 2)
+                hipLaunchKernelGGL(pass_geo_kernel<2>, dim3(grid_for(n)), dim3(BS), 0, s, ps.ord, ps.ord2, ps.l1,
+                                   ps.l2, xc, n, const_cast<uint32_t *>(ps.cf), const_cast<double *>(ps.xs),
+                                   const_cast<double *>(ps.w1), nullptr);
+            else
+                hipLaunchKernelGGL(pass_geo_kernel<3>, dim3(grid_for(n)), dim3(BS), 0, s, ps.ord, ps.ord2, ps.l1,
+                                   ps.l2, xc, n, const_cast<uint32_t *>(ps.cf), const_cast<double *>(ps.xs),
+                                   const_cast<double *>(ps.w1), const_cast<double *>(ps.w2));
+        }
+    }
     hipError_t e = hipStreamSynchronize(s);
     cleanup();
     if (e != hipSuccess) {
         set_error("HIP error while building the plan: %s", hipGetErrorString(e));
         return MM_ERR_HIP;
+    }
+    dev_free(p->structure);
+    for (Pass &ps : p->passes) {
+        ps.ord = nullptr;
+        ps.ord2 = nullptr;
     }
     MM_TRY(upload_pass_tables(p));
 #undef BUILD_TRY

@@ -86,8 +86,10 @@ constexpr int F_VALID = 16;    // position < n
 
 // One divide-and-conquer pass as the kernels see it (device table).
 struct PassDev {
-    const int32_t *ord;   // position -> canonical index (d = 2) or q (d = 3)
-    const int32_t *ord2;  // d = 3: q -> canonical index at level l1
+    const uint32_t *cf;   // canonical index | x1 half << 30 | x2 half << 31, in pass order
+    const double *xs;     // scan coordinate in pass order
+    const double *w1;     // x1 offset from the node's split point
+    const double *w2;     // d = 3: x2 offset from the x2 node's split point
     int l1, l2;
     int seg_log2;         // segments of 2^seg_log2 positions
     int pad;
@@ -325,13 +327,20 @@ struct Smem {
     int32_t c[C::T];
     int32_t flags[C::T];
     double xs[C::T];
-    double est[C::T];
+    double est[C::T + 1];  // decay from the previous position; [T]: into the next tile's first
     double geo[C::G > 0 ? C::G : 1][C::T];
 };
 
 template <class C>
 __device__ __forceinline__ int slot(int j) {
     return (j % C::E) * C::RUNS + j / C::E;
+}
+
+// Scan coordinate of pass position p (0 <= p < n).
+template <class C>
+__device__ __forceinline__ double scan_coord(const SweepArgs &A, const PassDev &ps, int64_t p) {
+    if constexpr (C::D == 1) return A.xc[p];
+    else return ps.xs[p];
 }
 
 // Stage the tile's positions: indices, flags, scan coordinate, offsets and
@@ -352,45 +361,47 @@ __device__ __forceinline__ void stage_tile(const SweepArgs &A, const PassDev &ps
         if constexpr (C::D == 1) {
             c = pc;
             sm.xs[sj] = A.xc[c];
-        } else if constexpr (C::D == 2) {
-            c = ps.ord[pc];
-            const int l = ps.l1;
-            flags |= (int)((c >> l) & 1) ? F_SIDE1 : 0;
-            int64_t sp = ((c >> (l + 1)) << (l + 1)) + (int64_t(1) << l);
-            if (sp > n - 1) sp = n - 1;
-            const double w = fabs(A.xc[c] - A.xc[sp]);
-            const double t = A.a * w;
-            sm.geo[0][sj] = exp(-t);
-            sm.geo[1][sj] = t;
-            sm.xs[sj] = A.xc[n + c];
         } else {
-            const int64_t q = ps.ord[pc];
-            c = ps.ord2[q];
-            const int l1 = ps.l1, l2 = ps.l2;
-            flags |= (int)((c >> l1) & 1) ? F_SIDE1 : 0;
-            flags |= (int)((q >> l2) & 1) ? F_SIDE2 : 0;
-            int64_t sp1 = ((c >> (l1 + 1)) << (l1 + 1)) + (int64_t(1) << l1);
-            if (sp1 > n - 1) sp1 = n - 1;
-            int64_t sq2 = ((q >> (l2 + 1)) << (l2 + 1)) + (int64_t(1) << l2);
-            if (sq2 > n - 1) sq2 = n - 1;
-            const double w1 = fabs(A.xc[c] - A.xc[sp1]);
-            const double w2 = fabs(A.xc[n + c] - A.xc[n + ps.ord2[sq2]]);
-            const double t1 = A.a * w1, t2 = A.a * w2;
+            // sequential reads of the pass's stored geometry
+            const uint32_t cf = ps.cf[pc];
+            c = (int64_t)(cf & 0x3fffffffu);
+            flags |= (cf >> 30) & 1u ? F_SIDE1 : 0;
+            const double t1 = A.a * ps.w1[pc];
             sm.geo[0][sj] = exp(-t1);
             sm.geo[1][sj] = t1;
-            sm.geo[2][sj] = exp(-t2);
-            sm.geo[3][sj] = t2;
-            sm.xs[sj] = A.xc[2 * n + c];
+            if constexpr (C::D == 3) {
+                flags |= (cf >> 31) ? F_SIDE2 : 0;
+                const double t2 = A.a * ps.w2[pc];
+                sm.geo[2][sj] = exp(-t2);
+                sm.geo[3][sj] = t2;
+            }
+            sm.xs[sj] = ps.xs[pc];
         }
         sm.c[sj] = (int32_t)c;
         sm.flags[sj] = flags;
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < C::T; j += WAVE) {
-        const int sj = slot<C>(j);
+    // decay exp(-a (x_j - x_{j-1})) into every position from its predecessor,
+    // including across the tile's edges (position p0 from p0 - 1, and the next
+    // tile's first position p0 + T from the tile's last); 1 at segment starts
+    for (int j = threadIdx.x; j <= C::T; j += WAVE) {
+        const int64_t p = p0 + j;
         double e = 1.0;
-        if (j > 0 && !(sm.flags[sj] & F_SEGSTART)) e = exp(-A.a * (sm.xs[sj] - sm.xs[slot<C>(j - 1)]));
-        sm.est[sj] = e;
+        if (p < n && p > 0 && (p & segmask) != 0) {
+            double xcur, xprev;
+            if (j > 0 && j < C::T) {
+                xcur = sm.xs[slot<C>(j)];
+                xprev = sm.xs[slot<C>(j - 1)];
+            } else if (j == 0) {
+                xcur = sm.xs[slot<C>(0)];
+                xprev = scan_coord<C>(A, ps, p - 1);
+            } else {
+                xcur = scan_coord<C>(A, ps, p);
+                xprev = sm.xs[slot<C>(C::T - 1)];
+            }
+            e = exp(-A.a * (xcur - xprev));
+        }
+        sm.est[j < C::T ? slot<C>(j) : C::T] = e;
     }
     __syncthreads();
 }
@@ -448,8 +459,15 @@ __device__ __forceinline__ double scan_elem(const Smem<C> &sm, State<C> &S, int 
         if constexpr (TARGET) S.zero();
     } else {
         const double t = a * (DIR == 0 ? xj - prevx : prevx - xj);
-        const double Ed = (i == 0) ? exp(-t) : sm.est[DIR == 0 ? sj : sj + C::RUNS];
-        S.shift(Ed, t);
+        // the previous position in the scan direction is the anchor of any carry,
+        // so the decay is the staged one between neighbours
+        int ej;
+        if constexpr (DIR == 0) {
+            ej = sj;
+        } else {
+            ej = (e + 1 < C::E) ? sj + C::RUNS : (run + 1 < C::RUNS ? run + 1 : C::T);
+        }
+        S.shift(sm.est[ej], t);
     }
     prevx = xj;
     double geo[C::G > 0 ? C::G : 1];
@@ -506,9 +524,11 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                 double vb[C::BLK];
 #pragma unroll
                 for (int k = 0; k < C::BLK; ++k) {
+                    // staged indices are clamped to valid points: load unconditionally
                     const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
                     const int sj = e * C::RUNS + run;
-                    vb[k] = (sm.flags[sj] & F_VALID) ? vcol[(int64_t)sm.c[sj] * A.W] : 0.0;
+                    const double ld = vcol[(int64_t)sm.c[sj] * A.W];
+                    vb[k] = (sm.flags[sj] & F_VALID) ? ld : 0.0;
                 }
 #pragma unroll
                 for (int k = 0; k < C::BLK; ++k) {
@@ -587,11 +607,18 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                     const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
                     const int sj = e * C::RUNS + run;
                     const bool valid = sm.flags[sj] & F_VALID;
-                    addr[k] = valid ? (int64_t)sm.c[sj] * A.W + col : -1;
-                    vb[k] = valid ? A.vin[addr[k]] : 0.0;
+                    const int64_t ad = (int64_t)sm.c[sj] * A.W + col;  // clamped: always in range
+                    addr[k] = valid ? ad : -1;
+                    const double lv = A.vin[ad];
+                    vb[k] = valid ? lv : 0.0;
                     // the slab already holds this element's earlier values unless this is
                     // the first write of the pass (backward direction of sub-sweep 0)
-                    ob[k] = (valid && (DIR == 0 || hh > 0)) ? slab[addr[k]] : 0.0;
+                    if (DIR == 0 || hh > 0) {
+                        const double lo = slab[ad];
+                        ob[k] = valid ? lo : 0.0;
+                    } else {
+                        ob[k] = 0.0;
+                    }
                 }
 #pragma unroll
                 for (int k = 0; k < C::BLK; ++k) {
@@ -632,7 +659,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, int6
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
             const int sj = e * C::RUNS + run;
-            vr[e] = (sm.flags[sj] & F_VALID) ? A.vin[(int64_t)sm.c[sj] * A.W + col] : 0.0;
+            const double ld = A.vin[(int64_t)sm.c[sj] * A.W + col];  // clamped index
+            vr[e] = (sm.flags[sj] & F_VALID) ? ld : 0.0;
             outv[e] = 0.0;
         }
     }
@@ -1077,7 +1105,7 @@ mm_status upload_pass_tables(mm_plan p) {
     for (int ti = 0; ti < 3; ++ti) p->xt_host[ti].clear();
     for (size_t i = 0; i < p->passes.size(); ++i) {
         const Pass &q = p->passes[i];
-        PassDev dv{q.ord, q.ord2, q.l1, q.l2, q.seg_log2, 0};
+        PassDev dv{q.cf, q.xs, q.w1, q.w2, q.l1, q.l2, q.seg_log2, 0};
         tab.push_back(dv);
         for (int ti = 0; ti < 3; ++ti)
             if (q.seg_log2 > 8 + ti) p->xt_host[ti].push_back((int)i);
