@@ -102,6 +102,7 @@ struct mm_plan_s {
     std::vector<int> xt_host[3];  //   segments span tiles
     mm::DevBuf seg_tab[3];        // per tile size: (pass, first tile, end tile) of those segments
     std::vector<int> seg_off[3];  //   offset of each cross-tile pass's first segment
+    std::vector<int4> seg_host[3];  // host copy of seg_tab
 
     // product work buffers (grow on demand)
     mm::DevBuf vin;               // n x W point-major canonical input

@@ -18,11 +18,11 @@ namespace mm {
 namespace {
 
 constexpr int BS = 256;
-constexpr int NRED = 256;  // row blocks of the column dot products (fixed: deterministic sums)
+constexpr int NRED = 1024;  // row blocks of the column dot products (fixed: deterministic sums)
 constexpr int NS = 8;      // scalars per column: [0] r.r [1] p.Ap [2] alpha [3] beta
                            // [4] |b| [5] active [6] iterations while active [7] |r|
 constexpr int CHUNK = 1024;
-static_assert(NRED == BS, "one thread per reduction block in the scalar kernels");
+static_assert(NRED % BS == 0, "whole row-block partials per thread in the scalar kernels");
 
 struct CgDesc {
     const double *B;
@@ -56,12 +56,15 @@ __device__ __forceinline__ void block_col_sum(double acc, int W, double *sm, dou
     __syncthreads();
 }
 
-// tot[r] = sum over the NRED row blocks of part[b][r] for every column r < W,
-// by a fixed binary tree (deterministic); one workgroup of BS threads.
+// tot[r] = sum over the NRED row blocks of part[b][r] for every column r < W:
+// each thread adds NRED/BS partials in a fixed order, then a fixed binary tree
+// (deterministic); one workgroup of BS threads.
 __device__ __forceinline__ void reduce_cols(const double *part, int W, double *red, double *tot) {
     const int t = threadIdx.x;
     for (int r = 0; r < W; ++r) {
-        red[t] = part[(int64_t)t * W + r];
+        double v = 0.0;
+        for (int j = 0; j < NRED / BS; ++j) v += part[(int64_t)(t + j * BS) * W + r];
+        red[t] = v;
         __syncthreads();
         for (int h = BS / 2; h > 0; h >>= 1) {
             if (t < h) red[t] += red[t + h];

@@ -105,6 +105,7 @@ struct SweepArgs {
     double *agg;           // tile aggregates [2 dirs][G][ntile][W][NHALF][NSLOT]
     double *car;           // tile carries, same layout as agg
     double *anc;           // tile anchors [2 dirs][G][ntile]
+    double *dec;           // decay from the previous tile's anchor (scan order) to the tile's, same layout
     int64_t n;
     int64_t ntile;
     int W;                 // leading width of vin / ypart (columns)
@@ -328,6 +329,7 @@ struct Smem {
     int32_t flags[C::T];
     double xs[C::T];
     double est[C::T + 1];  // decay from the previous position; [T]: into the next tile's first
+    double xedge[2];       // scan coordinate before the tile (p0 - 1) and after it (p0 + T)
     double geo[C::G > 0 ? C::G : 1][C::T];
 };
 
@@ -395,11 +397,17 @@ __device__ __forceinline__ void stage_tile(const SweepArgs &A, const PassDev &ps
             } else if (j == 0) {
                 xcur = sm.xs[slot<C>(0)];
                 xprev = scan_coord<C>(A, ps, p - 1);
+                sm.xedge[0] = xprev;
             } else {
                 xcur = scan_coord<C>(A, ps, p);
                 xprev = sm.xs[slot<C>(C::T - 1)];
+                sm.xedge[1] = xcur;
             }
             e = exp(-A.a * (xcur - xprev));
+        } else if (j == 0) {
+            sm.xedge[0] = sm.xs[slot<C>(0)];
+        } else if (j == C::T) {
+            sm.xedge[1] = sm.xs[slot<C>(C::T - 1)];
         }
         sm.est[j < C::T ? slot<C>(j) : C::T] = e;
     }
@@ -418,14 +426,17 @@ __device__ __forceinline__ int64_t agg_index(const SweepArgs &A, int dir, int pl
     return (((((int64_t)dir * A.G + pl) * A.ntile + tile) * A.W + col) * C::NHALF + hh) * C::NSLOT;
 }
 
-// F <- F + M(|xto - x of the partner|) F(partner), partner o runs away in the
-// scan direction (the same column's lane o*WCOL lanes up or down).
+// One step of the lane scan over runs: F <- F + M(E, t) F(partner), the
+// partner o runs away in the scan direction (the same column's lane o*WCOL
+// lanes up or down).  (t, E) is the transfer from the partner's anchor to this
+// lane's anchor -- the distance, times a, spanned by the runs this lane
+// already covers, and its decay -- so no exponential is evaluated here; the
+// coverage then grows by the partner's.
 template <class C, bool UP>
-__device__ __forceinline__ void scan_step(State<C> &F, int o, double xto, bool ok, double a) {
+__device__ __forceinline__ void scan_step(State<C> &F, double &t, double &E, int o, bool ok) {
     const int dl = o * C::WCOL;
-    const double xp = UP ? __shfl_up(xto, dl, WAVE) : __shfl_down(xto, dl, WAVE);
-    const double t = a * (UP ? xto - xp : xp - xto);
-    const double E = exp(-t);
+    const double tp = UP ? __shfl_up(t, dl, WAVE) : __shfl_down(t, dl, WAVE);
+    const double Ep = UP ? __shfl_up(E, dl, WAVE) : __shfl_down(E, dl, WAVE);
     const double t2 = 0.5 * t * t;
 #pragma unroll
     for (int c = 0; c < C::NCLS; ++c)
@@ -441,6 +452,10 @@ __device__ __forceinline__ void scan_step(State<C> &F, int o, double xto, bool o
                 F.s[c][h][0] = fma(E, q[0], F.s[c][h][0]);
             }
         }
+    if (ok) {
+        t += tp;
+        E *= Ep;
+    }
 }
 
 // Process element e of the lane's run in a scan step: move the state to the
@@ -539,11 +554,21 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
         }
         State<C> Frun;
         if constexpr (MODE == 1) Frun = F;
-        // ---- inclusive scan over the runs of this column
+        // ---- inclusive scan over the runs of this column.  Initial transfer: from
+        // the previous run's anchor to this run's (none for a group's first run).
+        double tr = 0.0, Er = 1.0;
+        {
+            const double xo = DIR == 0 ? __shfl_up(xend, C::WCOL, WAVE) : __shfl_down(xend, C::WCOL, WAVE);
+            const bool has = DIR == 0 ? (lig > 0) : (lig < Gr - 1);
+            if (has) {
+                tr = a * (DIR == 0 ? xend - xo : xo - xend);
+                Er = exp(-tr);
+            }
+        }
 #pragma unroll 1
         for (int o = 1; o < Gr; o <<= 1) {
             const bool ok = DIR == 0 ? (lig >= o) : (lig + o < Gr);
-            scan_step<C, DIR == 0>(F, o, xend, ok, a);
+            scan_step<C, DIR == 0>(F, tr, Er, o, ok);
         }
         // exclusive value
         {
@@ -567,7 +592,16 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                 double *dst = A.agg + agg_index<C>(A, DIR, pl, tile, col, hh);
 #pragma unroll
                 for (int k = 0; k < C::NSLOT; ++k) dst[k] = tot.flat()[k];
-                if (col == 0 && hh == 0) A.anc[((int64_t)DIR * A.G + pl) * A.ntile + tile] = xend;
+                if (col == 0 && hh == 0) {
+                    const int64_t ai = ((int64_t)DIR * A.G + pl) * A.ntile + tile;
+                    A.anc[ai] = xend;
+                    // decay across the tile from the previous tile's anchor; 1 for the
+                    // segment's first tile in the scan direction (no predecessor)
+                    const int64_t tps = seg / C::T;
+                    const bool first = DIR == 0 ? (tile % tps) == 0 : (((tile + 1) % tps) == 0 || tile + 1 == A.ntile);
+                    const double xo = sm.xedge[DIR == 0 ? 0 : 1];
+                    A.dec[ai] = first ? 1.0 : exp(-a * (DIR == 0 ? xend - xo : xo - xend));
+                }
             }
             return;
         }
@@ -707,12 +741,78 @@ __global__ __launch_bounds__(WAVE) void sweep_batch_kernel(const SweepArgs *desc
 // tiles, scan them serially, join the chunks with a lane scan and write the
 // tiles' exclusive values.  `segs` lists (pass, first tile, end tile) of the
 // segments that span several tiles; blockIdx.x indexes them.
+// Segments of at most CARRY_SMALL tiles: one thread per slice scans the
+// segment's tiles serially (loads issued in blocks of 8 ahead of the updates).
+constexpr int CARRY_SMALL = 16;
+
+template <class C>
+__device__ __forceinline__ void carry_small(const SweepArgs &A, int pass, int64_t t0, int64_t t1, int by) {
+    const int sl = by * 256 + (int)threadIdx.x;
+    if (sl >= A.nslice) return;
+    const int pl = pass - A.g0;
+    const int colw = sl % C::WCOL;
+    const int rowcb = sl / C::WCOL;
+    constexpr int ROWS = C::NHALF * C::NCLS * C::NTH;
+    const int row = rowcb % ROWS;
+    const int cb = rowcb / ROWS;
+    const int hh = row / (C::NCLS * C::NTH);
+    const int ch = row % (C::NCLS * C::NTH);
+    const int col = cb * C::WCOL + colw;
+    const double a = A.a;
+    const int64_t nt = t1 - t0;
+#pragma unroll 1
+    for (int dir = 0; dir < 2; ++dir) {
+        const int64_t base = ((int64_t)dir * A.G + pl) * A.ntile;
+        const double *anc = A.anc + base;
+        const double *dec = A.dec + base;
+        auto off = [&](int64_t t) -> int64_t { return agg_index<C>(A, dir, pl, t, col, hh) + (int64_t)ch * C::P; };
+        double ex[C::P];
+#pragma unroll
+        for (int m = 0; m < C::P; ++m) ex[m] = 0.0;
+        double xw = 0.0;
+#pragma unroll 1
+        for (int64_t b = 0; b < nt; b += 8) {
+            double xb[8], db[8], gb[8][C::P];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const bool in = b + k < nt;
+                const int64_t t = dir == 0 ? t0 + (in ? b + k : 0) : t1 - 1 - (in ? b + k : 0);
+                xb[k] = anc[t];
+                db[k] = dec[t];
+#pragma unroll
+                for (int m = 0; m < C::P; ++m) gb[k][m] = in ? A.agg[off(t) + m] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (b + k >= nt) break;
+                const int64_t t = dir == 0 ? t0 + b + k : t1 - 1 - b - k;
+                if (b + k > 0) {
+#pragma unroll
+                    for (int m = 0; m < C::P; ++m) A.car[off(t) + m] = ex[m];
+                    const double tt = a * (dir == 0 ? xb[k] - xw : xw - xb[k]);
+                    const double E = db[k];
+                    if constexpr (C::P == 3) ex[2] = E * fma(0.5 * tt * tt, ex[0], fma(tt, ex[1], ex[2]));
+                    if constexpr (C::P >= 2) ex[1] = E * fma(tt, ex[0], ex[1]);
+                    ex[0] = E * ex[0];
+                }
+#pragma unroll
+                for (int m = 0; m < C::P; ++m) ex[m] += gb[k][m];
+                xw = xb[k];
+            }
+        }
+    }
+}
+
 template <class C>
 __device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int by) {
     const int4 sg = A.segs[bx];
     const int nslice = A.nslice;
     const int pass = sg.x;
     const int64_t t0 = sg.y, t1 = sg.z;
+    if (t1 - t0 <= CARRY_SMALL) {
+        carry_small<C>(A, pass, t0, t1, by);
+        return;
+    }
     const int pl = pass - A.g0;
     const int lane = threadIdx.x & (WAVE - 1);
     const int sl = by * 4 + threadIdx.x / WAVE;
@@ -731,109 +831,151 @@ __device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int b
     const int64_t lo = t0 + lane * chunk;
     const int64_t hi = lo + chunk < t1 ? lo + chunk : t1;
     const int nact = (int)((nt + chunk - 1) / chunk);  // lanes holding tiles
+    const bool active = lane < nact;
+    const int64_t cnt = active ? hi - lo : 0;
 #pragma unroll 1
     for (int dir = 0; dir < 2; ++dir) {
-        const double *anc = A.anc + ((int64_t)dir * A.G + pl) * A.ntile;
+        const int64_t base = ((int64_t)dir * A.G + pl) * A.ntile;
+        const double *anc = A.anc + base;
+        const double *dec = A.dec + base;
         auto off = [&](int64_t t) -> int64_t { return agg_index<C>(A, dir, pl, t, col, hh) + (int64_t)ch * C::P; };
-        // chunk aggregate in the scan direction, anchored at the chunk's last tile
+        // the chunk's tiles in the scan direction: cb0, cb0 + step, ...
         const int64_t cb0 = dir == 0 ? lo : hi - 1;
-        const int64_t cb1 = dir == 0 ? hi - 1 : lo;   // last processed tile
         const int64_t step = dir == 0 ? 1 : -1;
-        const bool active = lane < nact;
+        // the segment's first tile in the scan direction: in lane 0 (forward) or in the
+        // last active lane (backward), always as the chunk's first tile
+        const bool seg_first = dir == 0 ? lane == 0 : lane == nact - 1;
+        // ---- chunk aggregate, anchored at the chunk's last tile, and the chunk's
+        // transfer (distance x a and decay) from the previous chunk's last anchor.
+        // The first block's anchors, aggregates and decays stay in registers.
         double acc[C::P];
 #pragma unroll
         for (int m = 0; m < C::P; ++m) acc[m] = 0.0;
-        // inactive lanes (no tiles) hold a zero state at the segment's largest anchor,
-        // so every shift they take part in is by a non-negative distance
-        double xa = active ? anc[cb1] : anc[t1 - 1];
-        if (active) {
-            double xprev = anc[cb0];
-            const int64_t cnt = hi - lo;
-            // blocks of 8 tiles: issue the loads first, then the dependent updates
-            for (int64_t b = 0; b < cnt; b += 8) {
-                double xs8[8], g8[8][C::P];
+        double xs8[8], g8[8][C::P], e8[8], tt8[8];
+        double Ech = 1.0;
+        double xprev = active ? anc[cb0] : anc[t1 - 1];
+        const double xfirst = xprev;
+        for (int64_t b = 0; b < cnt; b += 8) {
+            double xb[8], db[8], gb[8][C::P];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int64_t t = cb0 + step * (b + k);
-                    const bool in = b + k < cnt;
-                    xs8[k] = in ? anc[t] : 0.0;
+            for (int k = 0; k < 8; ++k) {  // loads first, then the dependent updates
+                const bool in = b + k < cnt;
+                const int64_t t = in ? cb0 + step * (b + k) : cb0;
+                xb[k] = anc[t];
+                db[k] = dec[t];
 #pragma unroll
-                    for (int m = 0; m < C::P; ++m) g8[k][m] = in ? A.agg[off(t) + m] : 0.0;
-                }
+                for (int m = 0; m < C::P; ++m) gb[k][m] = in ? A.agg[off(t) + m] : 0.0;
+            }
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    if (b + k >= cnt) break;
-                    const double x = xs8[k];
-                    const double tt = a * (dir == 0 ? x - xprev : xprev - x);
-                    const double E = exp(-tt);
-                    if constexpr (C::P == 3) acc[2] = E * fma(0.5 * tt * tt, acc[0], fma(tt, acc[1], acc[2]));
-                    if constexpr (C::P >= 2) acc[1] = E * fma(tt, acc[0], acc[1]);
-                    acc[0] = E * acc[0];
+            for (int k = 0; k < 8; ++k) {
+                if (b + k >= cnt) break;
+                const double x = xb[k];
+                const double tt = a * (dir == 0 ? x - xprev : xprev - x);
+                const double E = (b + k == 0) ? 1.0 : db[k];  // exp(-tt), stored per tile
+                Ech *= db[k];
+                if constexpr (C::P == 3) acc[2] = E * fma(0.5 * tt * tt, acc[0], fma(tt, acc[1], acc[2]));
+                if constexpr (C::P >= 2) acc[1] = E * fma(tt, acc[0], acc[1]);
+                acc[0] = E * acc[0];
 #pragma unroll
-                    for (int m = 0; m < C::P; ++m) acc[m] += g8[k][m];
-                    xprev = x;
+                for (int m = 0; m < C::P; ++m) acc[m] += gb[k][m];
+                xprev = x;
+                if (b == 0) {
+                    xs8[k] = x;
+                    e8[k] = db[k];
+                    tt8[k] = tt;
+#pragma unroll
+                    for (int m = 0; m < C::P; ++m) g8[k][m] = gb[k][m];
                 }
             }
         }
-        // inclusive lane scan toward the direction
+        // inactive lanes hold a zero state and an identity transfer
+        const double xa = xprev;
+        const double xbefore = dir == 0 ? __shfl_up(xa, 1, WAVE) : __shfl_down(xa, 1, WAVE);
+        double tr = 0.0, Er = 1.0;
+        if (active && !seg_first) {
+            tr = a * (dir == 0 ? xa - xbefore : xbefore - xa);
+            Er = Ech;
+        }
+        (void)xfirst;
+        // ---- inclusive lane scan toward the direction, transfers carried along
         for (int o = 1; o < WAVE; o <<= 1) {
-            const double xp = dir == 0 ? __shfl_up(xa, o, WAVE) : __shfl_down(xa, o, WAVE);
+            const double tp = dir == 0 ? __shfl_up(tr, o, WAVE) : __shfl_down(tr, o, WAVE);
+            const double Ep = dir == 0 ? __shfl_up(Er, o, WAVE) : __shfl_down(Er, o, WAVE);
             double q[C::P];
 #pragma unroll
             for (int m = 0; m < C::P; ++m) q[m] = dir == 0 ? __shfl_up(acc[m], o, WAVE) : __shfl_down(acc[m], o, WAVE);
             const bool ok = dir == 0 ? (lane >= o) : (lane + o < WAVE);
             if (ok) {
-                const double tt = a * (dir == 0 ? xa - xp : xp - xa);
-                const double E = exp(-tt);
-                if constexpr (C::P == 3) acc[2] = fma(E, fma(0.5 * tt * tt, q[0], fma(tt, q[1], q[2])), acc[2]);
-                if constexpr (C::P >= 2) acc[1] = fma(E, fma(tt, q[0], q[1]), acc[1]);
-                acc[0] = fma(E, q[0], acc[0]);
+                if constexpr (C::P == 3) acc[2] = fma(Er, fma(0.5 * tr * tr, q[0], fma(tr, q[1], q[2])), acc[2]);
+                if constexpr (C::P >= 2) acc[1] = fma(Er, fma(tr, q[0], q[1]), acc[1]);
+                acc[0] = fma(Er, q[0], acc[0]);
+                tr += tp;
+                Er *= Ep;
             }
         }
-        // exclusive value entering the chunk
+        // ---- exclusive value entering the chunk, anchored at the previous chunk's last tile
         double ex[C::P];
-        double xe;
         {
-            const double xp = dir == 0 ? __shfl_up(xa, 1, WAVE) : __shfl_down(xa, 1, WAVE);
             const bool has = dir == 0 ? (lane > 0) : (lane < WAVE - 1);
 #pragma unroll
             for (int m = 0; m < C::P; ++m) {
                 const double q = dir == 0 ? __shfl_up(acc[m], 1, WAVE) : __shfl_down(acc[m], 1, WAVE);
                 ex[m] = has ? q : 0.0;
             }
-            xe = xp;
         }
-        // walk the chunk again, writing each tile's exclusive carry
-        if (active) {
-            for (int64_t t = cb0;; t += step) {
-                const double x = anc[t];
-                const bool first = (dir == 0 ? t == t0 : t == t1 - 1);
-                if (!first) {
-                    // move the carry to the anchor next to t (previous tile in the direction)
-                    const double xn = anc[t - step];
-                    const double tt = a * (dir == 0 ? xn - xe : xe - xn);
-                    const double E = exp(-tt);
-                    if constexpr (C::P == 3) ex[2] = E * fma(0.5 * tt * tt, ex[0], fma(tt, ex[1], ex[2]));
-                    if constexpr (C::P >= 2) ex[1] = E * fma(tt, ex[0], ex[1]);
-                    ex[0] = E * ex[0];
-                    xe = xn;
+        if (!active) continue;
+        // ---- walk the chunk: each tile's carry is the running value anchored at the
+        // previous tile's anchor; then the tile is included
+        auto include = [&](double E, double tt, const double *g) {
+            if constexpr (C::P == 3) ex[2] = E * fma(0.5 * tt * tt, ex[0], fma(tt, ex[1], ex[2]));
+            if constexpr (C::P >= 2) ex[1] = E * fma(tt, ex[0], ex[1]);
+            ex[0] = E * ex[0];
+#pragma unroll
+            for (int m = 0; m < C::P; ++m) ex[m] += g[m];
+        };
+        if (cnt <= 8) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (k >= cnt) break;
+                const int64_t t = cb0 + step * k;
+                if (k == 0 && seg_first) {
+#pragma unroll
+                    for (int m = 0; m < C::P; ++m) ex[m] += g8[0][m];
+                } else {
 #pragma unroll
                     for (int m = 0; m < C::P; ++m) A.car[off(t) + m] = ex[m];
+                    const double tt = k == 0 ? a * (dir == 0 ? xs8[0] - xbefore : xbefore - xs8[0]) : tt8[k];
+                    include(e8[k], tt, g8[k]);
                 }
-                // include tile t
-                {
-                    const double tt = a * (dir == 0 ? x - xe : xe - x);
-                    const double E = first ? 1.0 : exp(-tt);
-                    if (!first) {
-                        if constexpr (C::P == 3) ex[2] = E * fma(0.5 * tt * tt, ex[0], fma(tt, ex[1], ex[2]));
-                        if constexpr (C::P >= 2) ex[1] = E * fma(tt, ex[0], ex[1]);
-                        ex[0] = E * ex[0];
-                    }
+            }
+        } else {
+            double xw = xbefore;
+            for (int64_t b = 0; b < cnt; b += 8) {
+                double xb[8], db[8], gb[8][C::P];
 #pragma unroll
-                    for (int m = 0; m < C::P; ++m) ex[m] += A.agg[off(t) + m];
-                    xe = x;
+                for (int k = 0; k < 8; ++k) {
+                    const bool in = b + k < cnt;
+                    const int64_t t = in ? cb0 + step * (b + k) : cb0;
+                    xb[k] = anc[t];
+                    db[k] = dec[t];
+#pragma unroll
+                    for (int m = 0; m < C::P; ++m) gb[k][m] = in ? A.agg[off(t) + m] : 0.0;
                 }
-                if (t == cb1) break;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (b + k >= cnt) break;
+                    const int64_t t = cb0 + step * (b + k);
+                    if (b + k == 0 && seg_first) {
+#pragma unroll
+                        for (int m = 0; m < C::P; ++m) ex[m] += gb[k][m];
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < C::P; ++m) A.car[off(t) + m] = ex[m];
+                        const double tt = a * (dir == 0 ? xb[k] - xw : xw - xb[k]);
+                        include(db[k], tt, gb[k]);
+                    }
+                    xw = xb[k];
+                }
             }
         }
     }
@@ -937,6 +1079,7 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
     A.agg = static_cast<double *>(p->agg.ptr);
     A.car = A.agg + aggslab;
     A.anc = A.car + aggslab;
+    A.dec = A.anc + (size_t)2 * gmax * ntile;
     for (int g0 = 0; g0 < npass; g0 += gmax) {
         const int G = npass - g0 < gmax ? npass - g0 : gmax;
         A.g0 = g0;
@@ -1028,6 +1171,7 @@ SweepArgs make_args(mm_plan p, const double *vin, double *agg, double *part, int
     A.agg = agg;
     A.car = A.agg + aggslab;
     A.anc = A.car + aggslab;
+    A.dec = A.anc + (size_t)2 * gmax * ntile;
     A.nslice = C::NHALF * C::NCLS * C::NTH * W;
     A.segs = static_cast<const int4 *>(p->seg_tab[ti].ptr);
     A.g0 = 0;
@@ -1066,12 +1210,13 @@ size_t sweep_part_bytes(int64_t n, int npass, int W) {
 
 // Aggregates and carries: per tile and right-hand side at most
 // NHALF*NCLS*NTH*P <= 108 doubles (d = 3, product form, nu = 5/2), two
-// directions, per pass of a group; anchors 2 per tile and pass.  The smallest
+// directions, per pass of a group; anchors and decays 2 each per tile and
+// pass.  The smallest
 // tile (256 positions) gives the most tiles.
 static size_t agg_bytes_for(int64_t n, int W, int64_t G) {
     const int64_t ntile = (n + 255) / 256;
     const int64_t per_rhs = 108;
-    return (size_t)(2 * (2 * G * ntile * (int64_t)W * per_rhs) + 2 * G * ntile + 16) * sizeof(double);
+    return (size_t)(2 * (2 * G * ntile * (int64_t)W * per_rhs) + 4 * G * ntile + 16) * sizeof(double);
 }
 
 size_t sweep_agg_bytes(int64_t n, int d, int W, const mm_kernel &k) {
@@ -1133,6 +1278,7 @@ mm_status upload_pass_tables(mm_plan p) {
             }
         }
         p->seg_off[ti].push_back((int)tab4.size());
+        p->seg_host[ti] = tab4;
         if (!tab4.empty()) {
             MM_TRY(dev_alloc(p->seg_tab[ti], tab4.size() * sizeof(int4)));
             MM_HIP_TRY(hipMemcpy(p->seg_tab[ti].ptr, tab4.data(), tab4.size() * sizeof(int4), hipMemcpyHostToDevice));
@@ -1248,8 +1394,11 @@ mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB,
                         for (int by = 0; by < ncb; ++by) ia.push_back(make_int4((int)m, (int)bx, by, 0));
                 const int nseg = p->seg_off[ti].empty() ? 0 : p->seg_off[ti].back();
                 if (A.ntile > 1)
-                    for (int sg = 0; sg < nseg; ++sg)
-                        for (int by = 0; by < (A.nslice + 3) / 4; ++by) ic.push_back(make_int4((int)m, sg, by, 0));
+                    for (int sg = 0; sg < nseg; ++sg) {
+                        const int4 g = p->seg_host[ti][sg];
+                        const int nby = (g.z - g.y <= CARRY_SMALL) ? (A.nslice + 255) / 256 : (A.nslice + 3) / 4;
+                        for (int by = 0; by < nby; ++by) ic.push_back(make_int4((int)m, sg, by, 0));
+                    }
                 for (int64_t bx = 0; bx < (int64_t)npass * A.ntile; ++bx)
                     for (int by = 0; by < ncb; ++by) im.push_back(make_int4((int)m, (int)bx, by, 0));
             }
