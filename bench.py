@@ -14,11 +14,13 @@ One step is one pass of the whole hot path with the inputs already in HBM:
 over every product of the step) per second of step wall time.
 
 Also printed in the same JSON line:
-  roofline      the divide-and-conquer sweep kernel (one launch covers every
-                pass of a product): algorithmic bytes per launch
-                (passes x N x (4 + 16 x columns)) over its average duration,
-                measured with HIP events on its stream during the timed
-                steps, against the 8 TB/s HBM peak;
+  roofline      the dominant kernel, the divide-and-conquer sweep launch of a CG
+                iteration (one launch covers every pass of the 4-column product):
+                algorithmic bytes per launch (passes x N x (4 + 16 x 4)) over its
+                average duration, measured with HIP events on its stream during
+                the timed solves, against the 8 TB/s HBM peak; `traffic` is the
+                measured HBM bytes per launch from the committed rocprofv3 counter
+                summary, when that summary matches the current kernel source;
   mvm           the plain product alone at 1, 8 and 32 right-hand sides;
   batched       256 independent problems of uneven N, d, nu and lengthscale
                 (N log-uniform in [1e3, 2e5], d in {1,2,3}, nu in {1/2,3/2,5/2}):
@@ -65,6 +67,29 @@ def b_pass(n: int, cols: int) -> float:
     """Algorithmic bytes of one divide-and-conquer pass: 4-byte order index plus,
     per column, an 8-byte weight read and an 8-byte partial-sum write per point."""
     return float(n) * (4.0 + 16.0 * cols)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_main_d2_n100k_nu32_w4.txt")
+SWEEP_SRC = os.path.join(ROOT, "paper_2508_01864_amd", "csrc", "sweep.hip")
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source has changed
+    since the counters were taken (the summary records the source's SHA-256)."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(SWEEP_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.split("=", 1) for line in text.splitlines() if "=" in line and not line.startswith(" "))
+    if fields.get("sweep_hip_sha256", "").strip() != src:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(x, v, seconds: float):
@@ -251,17 +276,20 @@ def main():
 
     def step(profile: bool):
         plan = mm.Plan(x, kern)
-        if profile:
-            plan.profile_enable(True)
         y1 = plan.mvm(v)
+        if profile:                          # bracket the solve's sweep launches only
+            plan.profile_enable(True)
         alpha, beta, info = plan.cg_solve(y, SIGMA2, fixed_effects=True, rtol=RTOL, maxit=args.maxit,
                                           raise_on_error=args.maxit >= 20000)
-        mean = plan.predict(alpha, z, beta=beta)
         prof = plan.profile_read() if profile else (0.0, 0, 0)
+        if profile:
+            plan.profile_enable(False)
+        mean = plan.predict(alpha, z, beta=beta)
         plan.close()
         cols = 1 + 4 * info["iters"]        # plain product + CG columns (y, 1, x1, x2)
         pts = N * cols + (N + NPREDICT)      # + predict on the union of points
-        sweep_bytes = L * (b_pass(N, 1) + info["iters"] * b_pass(N, 4))
+        # algorithmic bytes of the profiled launches: one per CG iteration, L passes, 4 columns
+        sweep_bytes = info["iters"] * L * b_pass(N, 4)
         return pts, info, prof, sweep_bytes, (y1, alpha, beta, mean)
 
     if args.calib_copy_mib > 0:
@@ -371,8 +399,10 @@ def main():
                    "n": N, "d": D, "two_nu": TWO_NU, "form": "product", "lengthscale": ELL,
                    "sigma2": SIGMA2, "rtol": RTOL, "npredict": NPREDICT},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "sweep_kernel (all %d divide-and-conquer passes per launch)" % L,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(),
+                     "algorithmic_bytes_per_launch": L * b_pass(N, 4),
+                     "kernel": "sweep_batch_kernel<d=2, nu=3/2, product, 4 columns> main launch of a CG "
+                               "iteration (all %d divide-and-conquer passes per launch)" % L,
                      "avg_launch_ms": avg_launch_ms, "launches": tot_launch},
         "cpu_baseline": cpu,
         "cg_iters": iters,
