@@ -98,11 +98,12 @@ struct mm_plan_s {
     mm::DevBuf geo;               // per-pass geometry in pass order (cf, xs, w1, w2)
     std::vector<mm::Pass> passes;
     mm::DevBuf pass_dev;          // device table of the passes
-    mm::DevBuf pass_xt[3];        // per tile size (256, 512, 1024 positions): passes whose
-    std::vector<int> xt_host[3];  //   segments span tiles
-    mm::DevBuf seg_tab[3];        // per tile size: (pass, first tile, end tile) of those segments
-    std::vector<int> seg_off[3];  //   offset of each cross-tile pass's first segment
-    std::vector<int4> seg_host[3];  // host copy of seg_tab
+    static constexpr int NTS = 4;  // tile sizes 128, 256, 512, 1024 positions
+    mm::DevBuf pass_xt[NTS];        // per tile size: passes whose segments span tiles
+    std::vector<int> xt_host[NTS];
+    mm::DevBuf seg_tab[NTS];        // per tile size: (pass, first tile, end tile) of those segments
+    std::vector<int> seg_off[NTS];  //   offset of each cross-tile pass's first segment
+    std::vector<int4> seg_host[NTS];  // host copy of seg_tab
 
     // product work buffers (grow on demand)
     mm::DevBuf vin;               // n x W point-major canonical input

@@ -782,7 +782,7 @@ size_t mm_solver_footprint_bytes(int64_t n, int32_t d, int32_t fixed_effects, co
     }
     // work tables of a batch: sweep items (at most three per pass, tile of 256 and
     // column block) and the vector-update items
-    const int64_t ntile = (n + 255) / 256;
+    const int64_t ntile = (n + 127) / 128;
     b += (size_t)3 * (npass + 1) * (ntile + 1) * W * 16 + (size_t)NRED * 8 + (size_t)(n * W / CHUNK + 1) * 8;
     return b;
 }

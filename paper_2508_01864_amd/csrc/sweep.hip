@@ -142,7 +142,7 @@ struct Cfg {
     static constexpr int NCLS = NCLS_ALL / NHALF;
     static constexpr int NSLOT = NCLS * NTH * P;             // doubles per state
     static constexpr int G = 2 * (D - 1);                    // staged geometry doubles
-    static constexpr bool REGOUT = E * NSLOT <= 64;          // keep targets in registers
+    static constexpr bool REGOUT = E <= 8 && E * NSLOT <= 64;  // keep targets in registers (short runs)
     static constexpr int BLK = E < 8 ? E : 8;                // prefetch block of long runs
 };
 
@@ -1023,7 +1023,7 @@ inline unsigned grid_1d(int64_t n) {
     return (unsigned)(g < 1 ? 1 : g);
 }
 
-inline int tile_index(int T) { return T >= 1024 ? 2 : (T >= 512 ? 1 : 0); }
+inline int tile_index(int T) { return T >= 1024 ? 3 : (T >= 512 ? 2 : (T >= 256 ? 1 : 0)); }
 
 // When the plan's profiling is on, record an event before the main sweep
 // launch on its stream and return the closing event to record after it.
@@ -1050,7 +1050,7 @@ mm_status profile_begin(mm_plan p, int passes_covered, hipStream_t s, hipEvent_t
 
 template <class C>
 mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStream_t s) {
-    static_assert(C::T == 256 || C::T == 512 || C::T == 1024, "tile sizes with a cross-tile pass list");
+    static_assert(C::T == 128 || C::T == 256 || C::T == 512 || C::T == 1024, "tile sizes with a cross-tile pass list");
     const KParams kp = kparams(p->kernel, p->d);
     const int64_t n = p->n;
     const int ncb = W / C::WCOL;
@@ -1214,7 +1214,7 @@ size_t sweep_part_bytes(int64_t n, int npass, int W) {
 // pass.  The smallest
 // tile (256 positions) gives the most tiles.
 static size_t agg_bytes_for(int64_t n, int W, int64_t G) {
-    const int64_t ntile = (n + 255) / 256;
+    const int64_t ntile = (n + 127) / 128;
     const int64_t per_rhs = 108;
     return (size_t)(2 * (2 * G * ntile * (int64_t)W * per_rhs) + 4 * G * ntile + 16) * sizeof(double);
 }
@@ -1247,25 +1247,25 @@ bool sweep_batch_bytes(mm_plan p, int W, size_t *agg_bytes, size_t *part_bytes) 
 
 mm_status upload_pass_tables(mm_plan p) {
     std::vector<PassDev> tab;
-    for (int ti = 0; ti < 3; ++ti) p->xt_host[ti].clear();
+    for (int ti = 0; ti < mm_plan_s::NTS; ++ti) p->xt_host[ti].clear();
     for (size_t i = 0; i < p->passes.size(); ++i) {
         const Pass &q = p->passes[i];
         PassDev dv{q.cf, q.xs, q.w1, q.w2, q.l1, q.l2, q.seg_log2, 0};
         tab.push_back(dv);
-        for (int ti = 0; ti < 3; ++ti)
-            if (q.seg_log2 > 8 + ti) p->xt_host[ti].push_back((int)i);
+        for (int ti = 0; ti < mm_plan_s::NTS; ++ti)
+            if (q.seg_log2 > 7 + ti) p->xt_host[ti].push_back((int)i);
     }
     if (tab.empty()) return MM_OK;
     MM_TRY(dev_alloc(p->pass_dev, tab.size() * sizeof(PassDev)));
     MM_HIP_TRY(hipMemcpy(p->pass_dev.ptr, tab.data(), tab.size() * sizeof(PassDev), hipMemcpyHostToDevice));
-    for (int ti = 0; ti < 3; ++ti) {
+    for (int ti = 0; ti < mm_plan_s::NTS; ++ti) {
         if (p->xt_host[ti].empty()) continue;
         MM_TRY(dev_alloc(p->pass_xt[ti], p->xt_host[ti].size() * sizeof(int32_t)));
         MM_HIP_TRY(hipMemcpy(p->pass_xt[ti].ptr, p->xt_host[ti].data(), p->xt_host[ti].size() * sizeof(int32_t),
                              hipMemcpyHostToDevice));
         // segments (pass, first tile, end tile) of the cross-tile passes, and the
         // offset of each pass's first segment (seg_off[k] for xt entry k)
-        const int64_t T = int64_t(256) << ti;
+        const int64_t T = int64_t(128) << ti;
         const int64_t ntile = (p->n + T - 1) / T;
         std::vector<int4> tab4;
         p->seg_off[ti].clear();
