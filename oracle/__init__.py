@@ -15,6 +15,9 @@ Contents (each function cites the passage it follows):
                      the beta_GLS formula) with H = [1, x_1 .. x_d].
 * ``predict``        posterior mean h(z)^T beta + k_z^T alpha (eq. gp_mean,
                      eq. gp_mean_2).
+* ``pivoted_cholesky`` / ``woodbury_apply``  the rank-k pivoted Cholesky
+                     preconditioner P = L L^T + sigma^2 I and its inverse by
+                     the Woodbury identity (Appendix A, 'Preconditioning').
 * ``decomposition``  (sub-module) the paper's weighted-ECDF decomposition
                      evaluated by brute-force masked sums (Props. 1-2 and the
                      Matern examples of Section 2.3); used only to pin the
@@ -236,3 +239,53 @@ def predict(x, alpha, z, two_nu: int, form, ell: float, s2: float, beta=None) ->
     if beta is not None:
         mean = mean + design_matrix(z) @ np.asarray(beta, dtype=np.float64)
     return mean
+
+
+def pivoted_cholesky(x, two_nu: int, form, ell: float, s2: float, max_rank: int, tol: float = 0.0):
+    """Rank-k pivoted Cholesky of K (the preconditioner of Appendix A,
+    'Preconditioning': P = L L^T + sigma^2 I with L L^T the pivoted Cholesky
+    decomposition of K, after Harbrecht, Peters and Schneider).
+
+    Greedy on the residual diagonal d = diag(K - L L^T): step m takes the
+    pivot p = argmax d (the smallest index among equal values), sets
+    L[:, m] = (K[:, p] - L[:, :m] L[p, :m]^T) / sqrt(d_p) and removes
+    L[:, m]^2 from d (negative round-off clamped to zero).  Stops after
+    max_rank columns, when d_p <= 0, or when the residual trace sum(d) is at
+    most tol * trace(K).
+
+    Returns (L of shape (n, rank), pivots, residual trace)."""
+    x = np.asarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+    n = x.shape[0]
+    K = kernel_matrix(x, two_nu, form, ell, s2)
+    d = np.diag(K).copy()
+    trace0 = float(d.sum())
+    L = np.zeros((n, max_rank))
+    piv = []
+    for m in range(max_rank):
+        if float(d.sum()) <= tol * trace0:
+            break
+        p = int(np.argmax(d))
+        dp = float(d[p])
+        if not dp > 0.0:
+            break
+        col = (K[:, p] - L[:, :m] @ L[p, :m]) / np.sqrt(dp)
+        col[p] = np.sqrt(dp)
+        L[:, m] = col
+        d = np.maximum(d - col * col, 0.0)
+        d[p] = 0.0
+        piv.append(p)
+    r = len(piv)
+    return L[:, :r], np.array(piv, dtype=np.int64), float(d.sum())
+
+
+def woodbury_apply(L, sigma2: float, r):
+    """P^{-1} r for P = L L^T + sigma^2 I by the Woodbury identity
+    (Appendix A, 'Preconditioning'):
+    P^{-1} r = r / sigma^2 - L (I_k + L^T L / sigma^2)^{-1} L^T r / sigma^4."""
+    L = np.asarray(L, dtype=np.float64)
+    r = np.asarray(r, dtype=np.float64)
+    k = L.shape[1]
+    M = np.eye(k) + (L.T @ L) / sigma2
+    return r / sigma2 - L @ np.linalg.solve(M, L.T @ r) / (sigma2 * sigma2)
