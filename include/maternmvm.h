@@ -192,6 +192,37 @@ mm_status gp_predict(mm_plan plan, const double *alpha, const double *beta, cons
                      int64_t m, int64_t ldz, double *mean, void *stream);
 
 /*
+ * Rank-k pivoted Cholesky preconditioner (Appendix A, "Preconditioning"):
+ * P = L L^T + sigma2 I with L L^T the pivoted Cholesky decomposition of K,
+ * applied in conjugate gradients through the Woodbury identity
+ *     P^{-1} r = r / sigma2 - L (I_k + L^T L / sigma2)^{-1} L^T r / sigma2^2.
+ * The factorisation is greedy on the residual diagonal diag(K - L L^T): each
+ * column takes the largest residual (smallest caller index among equal
+ * values).  It stops after max_rank columns, when the pivot's residual is not
+ * positive, or when the residual trace is at most tol * trace(K).  It does not
+ * depend on sigma2, so one preconditioner serves solves with any noise level.
+ *   max_rank  1 .. MM_PRECOND_MAX_RANK (capped at n)
+ *   tol       >= 0 (0: always max_rank columns unless the residual vanishes)
+ * Synchronises.  The preconditioner pins its plan (see the solver objects) and
+ * must outlive the solvers that use it (mm_precond_destroy fails otherwise).
+ */
+#define MM_PRECOND_MAX_RANK 256
+typedef struct mm_precond_s *mm_precond;
+
+mm_status mm_precond_create(mm_plan plan, int32_t max_rank, double tol, void *stream, mm_precond *out);
+
+/* Computed rank, residual trace sum(diag(K - L L^T)) and trace(K) (host). */
+mm_status mm_precond_info(mm_precond pc, int32_t *rank, double *trace_residual, double *trace_k);
+
+/* Copy L to device memory (n x rank column-major, leading dimension ldl >= n,
+ * rows in the caller's point order; may be NULL) and the pivots to host
+ * memory (rank caller indices in column order; may be NULL). */
+mm_status mm_precond_factor(mm_precond pc, double *L, int64_t ldl, int32_t *pivots, void *stream);
+
+/* Release a preconditioner (synchronises the device).  NULL is accepted. */
+mm_status mm_precond_destroy(mm_precond pc);
+
+/*
  * Solver objects: the conjugate-gradient solve of gp_cg_solve (Appendix A,
  * Algorithm 2, identity preconditioner, null initial guess; with fixed
  * effects the GLS of Section 3.2) split into steps, so that a caller can
@@ -217,6 +248,19 @@ size_t mm_solver_footprint_bytes(int64_t n, int32_t d, int32_t fixed_effects, co
  * its initialisation on `stream`; *out receives the handle. */
 mm_status mm_solver_create(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects,
                            double rtol, void *stream, mm_solver *out);
+
+/* As mm_solver_create, preconditioned by pc (Algorithm 2 with the solve
+ * s_P of the pivoted Cholesky preconditioner; pc may be NULL for none).  The
+ * Woodbury factors for this sigma2 are formed at creation.  Fixed effects
+ * (at most 8 columns) are supported; the stop test stays on the residual
+ * ||r_c|| <= rtol ||b_c||. */
+mm_status mm_solver_create_pc(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects,
+                              double rtol, mm_precond pc, void *stream, mm_solver *out);
+
+/* gp_cg_solve with the preconditioner pc (may be NULL). */
+mm_status gp_pcg_solve(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects, double rtol,
+                       int32_t maxit, mm_precond pc, double *alpha, double *beta, mm_solve_info *info,
+                       void *stream);
 
 /* Enqueue `iters` further iterations (columns that reached rtol stay frozen;
  * iterating a solved problem changes nothing). */

@@ -80,6 +80,15 @@ _SIGS = {
                                          ctypes.POINTER(_MMSolveInfo), _P]),
     "gp_predict": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double), _P, ctypes.c_int64,
                                   ctypes.c_int64, _P, _P]),
+    "mm_precond_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, _P, ctypes.POINTER(_P)]),
+    "mm_precond_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]),
+    "mm_precond_factor": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), _P]),
+    "mm_precond_destroy": (ctypes.c_int, [_P]),
+    "mm_solver_create_pc": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_double, _P, _P,
+                                           ctypes.POINTER(_P)]),
+    "gp_pcg_solve": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
+                                    _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_MMSolveInfo), _P]),
     "mm_solver_footprint_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                                     ctypes.POINTER(_MMKernel)]),
     "mm_solver_create": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_double, _P,
@@ -265,19 +274,27 @@ class Plan:
                                 _stream_ptr(self._stream)))
 
     def cg_solve(self, y, sigma2: float, fixed_effects: bool = False, rtol: float = 1e-8,
-                 maxit: int = 20000, raise_on_error: bool = True):
-        """alpha = (K + sigma2 I)^{-1} (y - H beta) with the GLS beta when fixed_effects.
+                 maxit: int = 20000, raise_on_error: bool = True, precond=None):
+        """alpha = (K + sigma2 I)^{-1} (y - H beta) with the GLS beta when fixed_effects,
+        optionally preconditioned by a :class:`Precond` of this plan.
         Returns (alpha, beta or None, info dict with iters / converged_cols / relres_max / status)."""
         torch = _torch()
         yc = _colmajor(y, self.n).view(-1)
         alpha = torch.empty_like(yc)
         beta = (ctypes.c_double * (self.d + 1))()
         info = _MMSolveInfo()
-        st = lib().gp_cg_solve(self._h, ctypes.c_void_p(yc.data_ptr()), float(sigma2),
-                               1 if fixed_effects else 0, float(rtol), int(maxit),
-                               ctypes.c_void_p(alpha.data_ptr()),
-                               beta if fixed_effects else None, ctypes.byref(info),
-                               _stream_ptr(self._stream))
+        if precond is None:
+            st = lib().gp_cg_solve(self._h, ctypes.c_void_p(yc.data_ptr()), float(sigma2),
+                                   1 if fixed_effects else 0, float(rtol), int(maxit),
+                                   ctypes.c_void_p(alpha.data_ptr()),
+                                   beta if fixed_effects else None, ctypes.byref(info),
+                                   _stream_ptr(self._stream))
+        else:
+            st = lib().gp_pcg_solve(self._h, ctypes.c_void_p(yc.data_ptr()), float(sigma2),
+                                    1 if fixed_effects else 0, float(rtol), int(maxit), precond.handle,
+                                    ctypes.c_void_p(alpha.data_ptr()),
+                                    beta if fixed_effects else None, ctypes.byref(info),
+                                    _stream_ptr(self._stream))
         msg = last_error()
         if st != MM_OK and raise_on_error:
             raise MaternError(st, msg)
@@ -345,15 +362,17 @@ class Solver:
     poll, finish.  gp_cg_solve runs the same kernels, so results agree bitwise."""
 
     def __init__(self, plan: Plan, y, sigma2: float, fixed_effects: bool = False,
-                 rtol: float = 1e-8, stream=None):
+                 rtol: float = 1e-8, stream=None, precond=None):
         self.plan = plan
+        self.precond = precond
         self.fixed_effects = bool(fixed_effects)
         self._stream = stream
         self._y = _colmajor(y, plan.n).view(-1)   # read by the creation kernels
         self._h = ctypes.c_void_p()
-        _check(lib().mm_solver_create(plan.handle, ctypes.c_void_p(self._y.data_ptr()), float(sigma2),
-                                      1 if fixed_effects else 0, float(rtol), _stream_ptr(stream),
-                                      ctypes.byref(self._h)))
+        _check(lib().mm_solver_create_pc(plan.handle, ctypes.c_void_p(self._y.data_ptr()), float(sigma2),
+                                         1 if fixed_effects else 0, float(rtol),
+                                         precond.handle if precond is not None else None,
+                                         _stream_ptr(stream), ctypes.byref(self._h)))
 
     @property
     def handle(self):
@@ -424,6 +443,52 @@ class SolverBatch:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().mm_solver_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Precond:
+    """Rank-k pivoted Cholesky preconditioner P = L L^T + sigma^2 I of a plan (mm_precond)."""
+
+    def __init__(self, plan: Plan, max_rank: int = 100, tol: float = 0.0, stream=None):
+        self.plan = plan
+        self._stream = stream
+        self._h = ctypes.c_void_p()
+        _check(lib().mm_precond_create(plan.handle, int(max_rank), float(tol), _stream_ptr(stream),
+                                       ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        """(rank, residual trace, trace of K)."""
+        r = ctypes.c_int32()
+        tr = ctypes.c_double()
+        t0 = ctypes.c_double()
+        _check(lib().mm_precond_info(self._h, ctypes.byref(r), ctypes.byref(tr), ctypes.byref(t0)))
+        return r.value, tr.value, t0.value
+
+    def factor(self):
+        """(L as an (n, rank) float64 CUDA tensor with rows in the caller's point order,
+        the pivots' caller indices in column order)."""
+        torch = _torch()
+        rank = self.info()[0]
+        out = torch.zeros((rank, self.plan.n), dtype=torch.float64, device="cuda")
+        piv = (ctypes.c_int32 * max(rank, 1))()
+        if rank > 0:
+            _check(lib().mm_precond_factor(self._h, ctypes.c_void_p(out.data_ptr()), self.plan.n, piv,
+                                           _stream_ptr(self._stream)))
+        return out.t(), np.array(piv[:rank], dtype=np.int64)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().mm_precond_destroy(self._h))
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -122,6 +122,19 @@ struct mm_plan_s {
     int64_t prof_units = 0;       // passes covered by the bracketed launches
 };
 
+// Rank-k pivoted Cholesky preconditioner (precond.hip).
+struct mm_precond_s {
+    mm_plan plan = nullptr;
+    int kmax = 0;                 // columns allocated (row stride of L)
+    int rank = 0;                 // columns computed
+    mm::DevBuf L;                 // n x kmax, row-major, canonical order
+    mm::DevBuf work;              // residual diagonal, reduction partials, state
+    std::vector<double> gram;     // rank x rank: L^T L (host)
+    std::vector<int32_t> pivots;  // caller index of each column's pivot
+    double trace0 = 0.0, trace_res = 0.0;
+    int npins = 0;                // live solvers using it
+};
+
 namespace mm {
 
 // sweep.hip

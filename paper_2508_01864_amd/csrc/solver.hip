@@ -22,6 +22,8 @@ constexpr int NRED = 1024;  // row blocks of the column dot products (fixed: det
 constexpr int NS = 8;      // scalars per column: [0] r.r [1] p.Ap [2] alpha [3] beta
                            // [4] |b| [5] active [6] iterations while active [7] |r|
 constexpr int CHUNK = 1024;
+constexpr int PUB = 1024;     // row blocks of the partial products L^T r (fixed: deterministic)
+constexpr int PC_MAXW = 8;    // columns of a preconditioned solver
 static_assert(NRED % BS == 0, "whole row-block partials per thread in the scalar kernels");
 
 struct CgDesc {
@@ -32,6 +34,14 @@ struct CgDesc {
     int nslab;            //   nslab < 0: the product is already summed in Y
     double *sc;    // W x NS
     int *flags;    // [0] active columns after the last update, [1] breakdown seen
+    // pivoted Cholesky preconditioner (rank 0: none)
+    const double *Lpc;    // n x kmax row-major, canonical order
+    const double *Rinv;   // rank x rank, row-major: inverse of the Cholesky factor of I + L^T L / sigma2
+    double *Z;            // P^{-1} R
+    double *part_rz;      // NRED x W partial r.z
+    double *part_u;       // PUB x rank x W partial L^T r
+    double *wv;           // rank x W
+    int kmax, rank;
     int64_t n;
     int W;
     int ncols;
@@ -101,11 +111,13 @@ __global__ void cg_init_scalars_b(const CgDesc *ds, int nsol) {
     for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
         const CgDesc d = ds[k];
         reduce_cols(d.part, d.W, red, tot);
+        __shared__ double tz[64];
+        if (d.rank > 0) reduce_cols(d.part_rz, d.W, red, tz);
         const int r = threadIdx.x;
         if (r < d.W) {
             const double s = tot[r];
             double *c = d.sc + r * NS;
-            c[0] = s;
+            c[0] = d.rank > 0 ? tz[r] : s;  // r.z (= r.r without preconditioner)
             c[1] = 0.0;
             c[2] = 0.0;
             c[3] = 0.0;
@@ -211,20 +223,23 @@ __global__ void cg_beta_b(const CgDesc *ds, int nsol) {
     for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
         const CgDesc d = ds[k];
         reduce_cols(d.part, d.W, red, tot);
+        __shared__ double tz[64];
+        if (d.rank > 0) reduce_cols(d.part_rz, d.W, red, tz);
         const int r = threadIdx.x;
         if (r < d.W) {
             const double s = tot[r];
+            const double rz = d.rank > 0 ? tz[r] : s;
             double *c = d.sc + r * NS;
             if (c[5] != 0.0) {
                 if (sqrt(s) <= d.rtol * c[4]) {
                     c[5] = 0.0;
                     c[3] = 0.0;
                 } else {
-                    c[3] = s / c[0];
+                    c[3] = rz / c[0];
                     atomicAdd(&d.flags[0], 1);  // integer count of still-active columns
                 }
                 c[7] = sqrt(s);
-                c[0] = s;
+                c[0] = rz;
             } else {
                 c[3] = 0.0;
             }
@@ -243,7 +258,148 @@ __global__ void cg_dir_b(const CgDesc *ds, const int2 *items, int nitems) {
         const int64_t hi = lo + CHUNK < len ? lo + CHUNK : len;
         for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
             const int r = (int)(e % d.W);
-            if (d.sc[r * NS + 5] != 0.0) d.P[e] = fma(d.sc[r * NS + 3], d.P[e], d.R[e]);
+            if (d.sc[r * NS + 5] != 0.0) d.P[e] = fma(d.sc[r * NS + 3], d.P[e], d.rank > 0 ? d.Z[e] : d.R[e]);
+        }
+    }
+}
+
+// ---- preconditioner solve s_P (Woodbury, Appendix A "Preconditioning") ----
+// partial L^T R over the rows of block it.y (of PUB): thread t takes the
+// (column of L, column of R) pairs t, t + BS, ...; rows are read 8 at a time
+__global__ void cg_pa_b(const CgDesc *ds, const int2 *items, int nitems) {
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        const CgDesc d = ds[it.x];
+        const int64_t chunk = (d.n + PUB - 1) / PUB;
+        const int64_t lo = it.y * chunk;
+        const int64_t hi = lo + chunk < d.n ? lo + chunk : d.n;
+        const int rw = d.rank * d.W;
+        for (int e = threadIdx.x; e < rw; e += BS) {
+            const int j = e / d.W, c = e - (e / d.W) * d.W;
+            double acc = 0.0;
+            int64_t row = lo;
+            for (; row + 8 <= hi; row += 8) {
+                double l8[8], r8[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    l8[q] = d.Lpc[(row + q) * d.kmax + j];
+                    r8[q] = d.R[(row + q) * d.W + c];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc = fma(l8[q], r8[q], acc);
+            }
+            for (; row < hi; ++row) acc = fma(d.Lpc[row * d.kmax + j], d.R[row * d.W + c], acc);
+            d.part_u[(int64_t)it.y * rw + e] = acc;
+        }
+    }
+}
+
+// u[e] = sum of the PUB partials of element e (one block per element, fixed tree)
+__global__ void cg_pu_b(const CgDesc *ds, const int2 *items, int nitems) {
+    __shared__ double red[BS];
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        const CgDesc d = ds[it.x];
+        const int rw = d.rank * d.W;
+        const int e = it.y;
+        double v = 0.0;
+        for (int b = threadIdx.x; b < PUB; b += BS) v += d.part_u[(int64_t)b * rw + e];
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int h = BS / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) d.wv[e] = red[0];  // u, replaced by w in place below
+        __syncthreads();
+    }
+}
+
+// w = (I + L^T L / sigma2)^{-1} u = Rinv^T (Rinv u): one block per preconditioned solver
+__global__ void cg_pb_b(const CgDesc *ds, int nsol) {
+    __shared__ double su[MM_PRECOND_MAX_RANK * PC_MAXW];
+    __shared__ double st[MM_PRECOND_MAX_RANK * PC_MAXW];
+    for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
+        const CgDesc d = ds[k];
+        if (d.rank == 0) continue;
+        const int rw = d.rank * d.W;
+        for (int e = threadIdx.x; e < rw; e += BS) su[e] = d.wv[e];
+        __syncthreads();
+        for (int e = threadIdx.x; e < rw; e += BS) {
+            const int j = e / d.W, c = e - (e / d.W) * d.W;
+            double t = 0.0;
+            for (int l = 0; l <= j; ++l) t = fma(d.Rinv[j * d.rank + l], su[l * d.W + c], t);
+            st[e] = t;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < rw; e += BS) {
+            const int j = e / d.W, c = e - (e / d.W) * d.W;
+            double w = 0.0;
+            for (int l = j; l < d.rank; ++l) w = fma(d.Rinv[l * d.rank + j], st[l * d.W + c], w);
+            d.wv[e] = w;
+        }
+        __syncthreads();
+    }
+}
+
+// Z = R / sigma2 - L w / sigma2^2 on the rows of block it.y (of NRED), partial
+// R.Z per column; at initialisation also P = Z
+__global__ void cg_pc_b(const CgDesc *ds, const int2 *items, int nitems, int init) {
+    __shared__ double sw[MM_PRECOND_MAX_RANK * PC_MAXW];
+    __shared__ double red[BS];
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        const CgDesc d = ds[it.x];
+        const int rw = d.rank * d.W;
+        for (int e = threadIdx.x; e < rw; e += BS) sw[e] = d.wv[e];
+        __syncthreads();
+        int64_t lo, hi;
+        row_range(d.n, it.y, lo, hi);
+        const double inv = 1.0 / d.sigma2;
+        double rz[PC_MAXW];
+#pragma unroll
+        for (int c = 0; c < PC_MAXW; ++c) rz[c] = 0.0;
+        for (int64_t row = lo + threadIdx.x; row < hi; row += BS) {
+            double acc[PC_MAXW];
+#pragma unroll
+            for (int c = 0; c < PC_MAXW; ++c) acc[c] = 0.0;
+            const double *lr = d.Lpc + row * d.kmax;
+            int j = 0;
+            for (; j + 8 <= d.rank; j += 8) {  // the row's entries are loaded 8 at a time
+                double l8[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) l8[q] = lr[j + q];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+#pragma unroll
+                    for (int c = 0; c < PC_MAXW; ++c)
+                        if (c < d.W) acc[c] = fma(l8[q], sw[(j + q) * d.W + c], acc[c]);
+            }
+            for (; j < d.rank; ++j) {
+                const double l = lr[j];
+#pragma unroll
+                for (int c = 0; c < PC_MAXW; ++c)
+                    if (c < d.W) acc[c] = fma(l, sw[j * d.W + c], acc[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < PC_MAXW; ++c) {
+                if (c >= d.W) break;
+                const double rv = d.R[row * d.W + c];
+                const double z = fma(-acc[c], inv * inv, rv * inv);
+                d.Z[row * d.W + c] = z;
+                if (init) d.P[row * d.W + c] = z;
+                rz[c] = fma(rv, z, rz[c]);
+            }
+        }
+        for (int c = 0; c < d.W; ++c) {
+            red[threadIdx.x] = rz[c < PC_MAXW ? c : 0];
+            __syncthreads();
+            for (int h = BS / 2; h > 0; h >>= 1) {
+                if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) d.part_rz[(int64_t)it.y * d.W + c] = red[0];
+            __syncthreads();
         }
     }
 }
@@ -366,6 +522,7 @@ struct mm_solver_s {
     bool batchable = true;           // all passes fit one group: may join batches
     int64_t iters = 0;
     mm_solver_batch self = nullptr;  // batch of one for solitary iterations
+    mm_precond pc = nullptr;         // preconditioner (pinned while the solver lives)
 };
 
 struct mm_solver_batch_s {
@@ -373,6 +530,8 @@ struct mm_solver_batch_s {
     std::vector<SweepBatch> sweeps;      // one per distinct width among the members
     DevBuf cg_desc, items_blk, items_chunk, status;
     int n_blk = 0, n_chunk = 0;
+    DevBuf items_pa, items_pu, items_pc;  // preconditioned members only
+    int n_pa = 0, n_pu = 0, n_pc = 0;
     bool plain = false;                  // lone solver too large for a batch workspace
     hipStream_t bs = nullptr;            // private stream for graph capture and replay
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -385,6 +544,21 @@ struct mm_solver_batch_s {
 
 namespace mm {
 namespace {
+
+// Z = P^{-1} R for the preconditioned members (and P = Z when init).
+mm_status precond_enqueue(mm_solver_batch b, hipStream_t s, int init) {
+    const CgDesc *ds = static_cast<const CgDesc *>(b->cg_desc.ptr);
+    const int nsol = (int)b->members.size();
+    hipLaunchKernelGGL(cg_pa_b, dim3(pgrid(b->n_pa, b->grid_cap)), dim3(BS), 0, s, ds,
+                       static_cast<const int2 *>(b->items_pa.ptr), b->n_pa);
+    hipLaunchKernelGGL(cg_pu_b, dim3(pgrid(b->n_pu, b->grid_cap)), dim3(BS), 0, s, ds,
+                       static_cast<const int2 *>(b->items_pu.ptr), b->n_pu);
+    hipLaunchKernelGGL(cg_pb_b, dim3(pgrid(nsol, 1024)), dim3(BS), 0, s, ds, nsol);
+    hipLaunchKernelGGL(cg_pc_b, dim3(pgrid(b->n_pc, b->grid_cap)), dim3(BS), 0, s, ds,
+                       static_cast<const int2 *>(b->items_pc.ptr), b->n_pc, init);
+    MM_HIP_TRY(hipGetLastError());
+    return MM_OK;
+}
 
 // Enqueue `iters` CG iterations of every member of the batch on stream s.
 mm_status batch_enqueue(mm_solver_batch b, int iters, hipStream_t s) {
@@ -402,6 +576,7 @@ mm_status batch_enqueue(mm_solver_batch b, int iters, hipStream_t s) {
         hipLaunchKernelGGL(cg_apply_b, dim3(pgrid(b->n_blk, b->grid_cap)), dim3(BS), 0, s, ds, ib, b->n_blk);
         hipLaunchKernelGGL(cg_alpha_b, dim3(pgrid(nsol, 1024)), dim3(BS), 0, s, ds, nsol);
         hipLaunchKernelGGL(cg_update_b, dim3(pgrid(b->n_blk, b->grid_cap)), dim3(BS), 0, s, ds, ib, b->n_blk);
+        if (b->n_pa > 0) MM_TRY(precond_enqueue(b, s, 0));
         if (it == iters - 1)  // count the columns still active after the last iteration
             hipLaunchKernelGGL(cg_reset_active_b, dim3(pgrid((nsol + BS - 1) / BS, 64)), dim3(BS), 0, s, ds, nsol);
         hipLaunchKernelGGL(cg_beta_b, dim3(pgrid(nsol, 1024)), dim3(BS), 0, s, ds, nsol);
@@ -415,7 +590,7 @@ mm_status batch_enqueue(mm_solver_batch b, int iters, hipStream_t s) {
 
 mm_status batch_build(mm_solver_batch b) {
     std::vector<CgDesc> descs;
-    std::vector<int2> ib, ic;
+    std::vector<int2> ib, ic, ipa, ipu, ipc;
     std::vector<int> widths;
     for (size_t k = 0; k < b->members.size(); ++k) {
         mm_solver s = b->members[k];
@@ -431,6 +606,11 @@ mm_status batch_build(mm_solver_batch b) {
         if (w == widths.size()) widths.push_back(s->W);
         descs.push_back(s->desc);
         for (int blk = 0; blk < NRED; ++blk) ib.push_back(make_int2((int)k, blk));
+        if (s->desc.rank > 0) {
+            for (int blk = 0; blk < PUB; ++blk) ipa.push_back(make_int2((int)k, blk));
+            for (int e = 0; e < s->desc.rank * s->W; ++e) ipu.push_back(make_int2((int)k, e));
+            for (int blk = 0; blk < NRED; ++blk) ipc.push_back(make_int2((int)k, blk));
+        }
         const int64_t nch = (s->desc.n * s->W + CHUNK - 1) / CHUNK;
         for (int64_t c = 0; c < nch; ++c) ic.push_back(make_int2((int)k, (int)c));
     }
@@ -456,6 +636,12 @@ mm_status batch_build(mm_solver_batch b) {
     MM_TRY(upload_vec(b->items_chunk, ic));
     b->n_blk = (int)ib.size();
     b->n_chunk = (int)ic.size();
+    MM_TRY(upload_vec(b->items_pa, ipa));
+    MM_TRY(upload_vec(b->items_pu, ipu));
+    b->n_pu = (int)ipu.size();
+    MM_TRY(upload_vec(b->items_pc, ipc));
+    b->n_pa = (int)ipa.size();
+    b->n_pc = (int)ipc.size();
     MM_TRY(dev_alloc(b->status, b->members.size() * sizeof(int2)));
     return MM_OK;
 }
@@ -468,6 +654,9 @@ void batch_free(mm_solver_batch b) {
     dev_free(b->cg_desc);
     dev_free(b->items_blk);
     dev_free(b->items_chunk);
+    dev_free(b->items_pa);
+    dev_free(b->items_pu);
+    dev_free(b->items_pc);
     dev_free(b->status);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
@@ -550,11 +739,50 @@ mm_status check_solve_args(mm_plan plan, double sigma2, double rtol) {
 
 // Solver with W columns whose right-hand sides are filled by `fill` into B.
 template <class F>
-mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol, hipStream_t s, F &&fill,
-                     mm_solver *out) {
+mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol, mm_precond pc, hipStream_t s,
+                     F &&fill, mm_solver *out) {
     const int64_t n = plan->n;
     const int R = rhs_block(plan->kernel, plan->d, ncols);
     const int W = pow2ceil(ncols > R ? ncols : R);
+    const int rank = pc ? pc->rank : 0;
+    if (pc && pc->plan != plan) {
+        set_error("the preconditioner was built for another plan");
+        return MM_ERR_ARG;
+    }
+    if (rank > 0 && W > PC_MAXW) {
+        set_error("a preconditioned solver takes at most %d columns (got %d)", PC_MAXW, W);
+        return MM_ERR_ARG;
+    }
+    // Woodbury factors for this noise level: Rinv = inverse of the Cholesky factor
+    // of I + L^T L / sigma2 (host, rank x rank)
+    std::vector<double> rinv;
+    if (rank > 0) {
+        const int r = rank;
+        std::vector<double> M((size_t)r * r), C((size_t)r * r, 0.0);
+        for (int i = 0; i < r; ++i)
+            for (int j = 0; j < r; ++j) M[i * r + j] = (i == j ? 1.0 : 0.0) + pc->gram[i * r + j] / sigma2;
+        for (int j = 0; j < r; ++j) {
+            double dj = M[j * r + j];
+            for (int k = 0; k < j; ++k) dj -= C[j * r + k] * C[j * r + k];
+            if (!(dj > 0.0)) {
+                set_error("preconditioner Gram factor is not positive definite");
+                return MM_ERR_NOTPD;
+            }
+            C[j * r + j] = std::sqrt(dj);
+            for (int i = j + 1; i < r; ++i) {
+                double t = M[i * r + j];
+                for (int k = 0; k < j; ++k) t -= C[i * r + k] * C[j * r + k];
+                C[i * r + j] = t / C[j * r + j];
+            }
+        }
+        rinv.assign((size_t)r * r, 0.0);  // forward substitution on the identity
+        for (int c = 0; c < r; ++c)
+            for (int i = c; i < r; ++i) {
+                double t = (i == c) ? 1.0 : 0.0;
+                for (int k = c; k < i; ++k) t -= C[i * r + k] * rinv[k * r + c];
+                rinv[i * r + c] = t / C[i * r + i];
+            }
+    }
     mm_solver sv = new (std::nothrow) mm_solver_s();
     if (!sv) {
         set_error("host allocation failed");
@@ -571,7 +799,11 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
     size_t agg_b = 0, part_b = 0;
     sv->batchable = sweep_batch_bytes(plan, W, &agg_b, &part_b);
     agg_b = (agg_b + 255) & ~size_t(255);
-    mm_status st = dev_alloc(sv->buf, (6 * vec + (size_t)NRED * W * 8 + (size_t)W * NS + 8) * sizeof(double));
+    const size_t pcd = rank > 0 ? vec + (size_t)NRED * W + (size_t)PUB * rank * W + (size_t)rank * W +
+                                      (size_t)rank * rank
+                                : 0;
+    mm_status st =
+        dev_alloc(sv->buf, (6 * vec + (size_t)NRED * W * 8 + (size_t)W * NS + 8 + pcd) * sizeof(double));
     if (st == MM_OK) {
         if (sv->batchable) {
             st = dev_alloc(sv->ws, agg_b + part_b);
@@ -601,6 +833,27 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
     d.part = base + 6 * vec;
     d.sc = d.part + (size_t)NRED * W * 8;
     d.flags = reinterpret_cast<int *>(d.sc + (size_t)W * NS);
+    if (rank > 0) {
+        double *q = d.sc + (size_t)W * NS + 8;
+        d.Z = q;
+        d.part_rz = q + vec;
+        d.part_u = d.part_rz + (size_t)NRED * W;
+        d.wv = d.part_u + (size_t)PUB * rank * W;
+        double *rv = d.wv + (size_t)rank * W;
+        d.Rinv = rv;
+        d.Lpc = static_cast<const double *>(pc->L.ptr);
+        d.kmax = pc->kmax;
+        d.rank = rank;
+        if (hipMemcpyAsync(rv, rinv.data(), rinv.size() * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            dev_free(sv->ws);
+            dev_free(sv->buf);
+            delete sv;
+            set_error("copy of the preconditioner factors failed");
+            return MM_ERR_HIP;
+        }
+        sv->pc = pc;
+    }
     d.slabs = sv->part;
     d.nslab = sv->batchable ? (int)plan->passes.size() : -1;
     d.n = n;
@@ -626,6 +879,7 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
         const CgDesc *ds = static_cast<const CgDesc *>(b->cg_desc.ptr);
         hipLaunchKernelGGL(cg_init_b, dim3(pgrid(b->n_blk, 2048)), dim3(BS), 0, s, ds,
                            static_cast<const int2 *>(b->items_blk.ptr), b->n_blk);
+        if (b->n_pa > 0) st = precond_enqueue(b, s, 1);  // z0 = P^{-1} r0, p0 = z0
         hipLaunchKernelGGL(cg_init_scalars_b, dim3(1), dim3(BS), 0, s, ds, 1);
         if (hipGetLastError() != hipSuccess) {
             set_error("solver initialisation launch failed");
@@ -642,6 +896,7 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
     }
     sv->self = b;
     plan->npins++;
+    if (sv->pc) sv->pc->npins++;
     plan->last_stream = s;
     *out = sv;
     return MM_OK;
@@ -787,9 +1042,9 @@ size_t mm_solver_footprint_bytes(int64_t n, int32_t d, int32_t fixed_effects, co
     return b;
 }
 
-mm_status mm_solver_create(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects, double rtol,
-                           void *stream, mm_solver *out) {
-    clear_error();
+namespace {
+mm_status solver_create_impl(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects, double rtol,
+                             mm_precond pc, void *stream, mm_solver *out) {
     if (!out) {
         set_error("out is NULL");
         return MM_ERR_ARG;
@@ -802,7 +1057,7 @@ mm_status mm_solver_create(mm_plan plan, const double *y, double sigma2, int32_t
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int ncols = fixed_effects ? plan->d + 2 : 1;
-    return solver_new(plan, ncols, fixed_effects ? 1 : 0, sigma2, rtol, s,
+    return solver_new(plan, ncols, fixed_effects ? 1 : 0, sigma2, rtol, pc, s,
                       [&](double *B, int W) {
                           hipLaunchKernelGGL(fe_rhs_kernel, dim3(grid1(plan->n)), dim3(BS), 0, s, y,
                                              static_cast<const int32_t *>(plan->perm.ptr),
@@ -810,6 +1065,19 @@ mm_status mm_solver_create(mm_plan plan, const double *y, double sigma2, int32_t
                                              fixed_effects ? 1 : 0, W, B);
                       },
                       out);
+}
+}  // namespace
+
+mm_status mm_solver_create(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects, double rtol,
+                           void *stream, mm_solver *out) {
+    clear_error();
+    return solver_create_impl(plan, y, sigma2, fixed_effects, rtol, nullptr, stream, out);
+}
+
+mm_status mm_solver_create_pc(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects, double rtol,
+                              mm_precond pc, void *stream, mm_solver *out) {
+    clear_error();
+    return solver_create_impl(plan, y, sigma2, fixed_effects, rtol, pc, stream, out);
 }
 
 mm_status mm_solver_iterate(mm_solver solver, int32_t iters, void *stream) {
@@ -862,6 +1130,7 @@ mm_status mm_solver_destroy(mm_solver solver) {
         delete solver->self;
     }
     solver->plan->npins--;
+    if (solver->pc) solver->pc->npins--;
     dev_free(solver->ws);
     dev_free(solver->buf);
     delete solver;
@@ -944,9 +1213,9 @@ mm_status mm_solver_batch_destroy(mm_solver_batch batch) {
     return MM_OK;
 }
 
-mm_status gp_cg_solve(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects, double rtol,
-                      int32_t maxit, double *alpha, double *beta, mm_solve_info *info, void *stream) {
-    clear_error();
+namespace {
+mm_status pcg_impl(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects, double rtol, int32_t maxit,
+                   mm_precond pc, double *alpha, double *beta, mm_solve_info *info, void *stream) {
     MM_TRY(check_solve_args(plan, sigma2, rtol));
     if (!y || !alpha) {
         set_error("y and alpha must be non-NULL");
@@ -962,7 +1231,7 @@ mm_status gp_cg_solve(mm_plan plan, const double *y, double sigma2, int32_t fixe
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     mm_solver sv = nullptr;
-    MM_TRY(mm_solver_create(plan, y, sigma2, fixed_effects, rtol, stream, &sv));
+    MM_TRY(solver_create_impl(plan, y, sigma2, fixed_effects, rtol, pc, stream, &sv));
     mm_status st = solver_run(sv, maxit, s);
     if (st == MM_OK) st = mm_solver_finish(sv, alpha, beta, info, stream);
     if (st != MM_OK && st != MM_ERR_NOCONV && st != MM_ERR_BREAKDOWN) {
@@ -973,6 +1242,19 @@ mm_status gp_cg_solve(mm_plan plan, const double *y, double sigma2, int32_t fixe
     mm_solver_destroy(sv);
     if (st != MM_OK) set_error("%s", msg.c_str());
     return st;
+}
+}  // namespace
+
+mm_status gp_cg_solve(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects, double rtol,
+                      int32_t maxit, double *alpha, double *beta, mm_solve_info *info, void *stream) {
+    clear_error();
+    return pcg_impl(plan, y, sigma2, fixed_effects, rtol, maxit, nullptr, alpha, beta, info, stream);
+}
+
+mm_status gp_pcg_solve(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects, double rtol,
+                       int32_t maxit, mm_precond pc, double *alpha, double *beta, mm_solve_info *info, void *stream) {
+    clear_error();
+    return pcg_impl(plan, y, sigma2, fixed_effects, rtol, maxit, pc, alpha, beta, info, stream);
 }
 
 mm_status gp_cg_solve_multi(mm_plan plan, const double *Bc, int64_t ldb, int32_t nrhs, double sigma2, double rtol,
@@ -993,7 +1275,7 @@ mm_status gp_cg_solve_multi(mm_plan plan, const double *Bc, int64_t ldb, int32_t
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     mm_solver sv = nullptr;
-    MM_TRY(solver_new(plan, nrhs, 0, sigma2, rtol, s,
+    MM_TRY(solver_new(plan, nrhs, 0, sigma2, rtol, nullptr, s,
                       [&](double *B, int W) {
                           hipLaunchKernelGGL(gather_cols_kernel, dim3(grid1(plan->n * W)), dim3(BS), 0, s, Bc, ldb,
                                              nrhs, static_cast<const int32_t *>(plan->perm.ptr), plan->n, B, W);
