@@ -36,7 +36,8 @@ struct CgDesc {
     int *flags;    // [0] active columns after the last update, [1] breakdown seen
     // pivoted Cholesky preconditioner (rank 0: none)
     const double *Lpc;    // n x kmax row-major, canonical order
-    const double *Rinv;   // rank x rank, row-major: inverse of the Cholesky factor of I + L^T L / sigma2
+    const double *Minv;   // rank x rank: (I + L^T L / sigma2)^{-1}, formed as Rinv^T Rinv (Rinv: inverse Cholesky factor)
+    double *ub;           // rank x W: L^T R
     double *Z;            // P^{-1} R
     double *part_rz;      // NRED x W partial r.z
     double *part_u;       // PUB x rank x W partial L^T r
@@ -310,34 +311,28 @@ __global__ void cg_pu_b(const CgDesc *ds, const int2 *items, int nitems) {
             if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
             __syncthreads();
         }
-        if (threadIdx.x == 0) d.wv[e] = red[0];  // u, replaced by w in place below
+        if (threadIdx.x == 0) d.ub[e] = red[0];
         __syncthreads();
     }
 }
 
-// w = (I + L^T L / sigma2)^{-1} u = Rinv^T (Rinv u): one block per preconditioned solver
-__global__ void cg_pb_b(const CgDesc *ds, int nsol) {
-    __shared__ double su[MM_PRECOND_MAX_RANK * PC_MAXW];
-    __shared__ double st[MM_PRECOND_MAX_RANK * PC_MAXW];
-    for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
-        const CgDesc d = ds[k];
-        if (d.rank == 0) continue;
-        const int rw = d.rank * d.W;
-        for (int e = threadIdx.x; e < rw; e += BS) su[e] = d.wv[e];
+// w = (I + L^T L / sigma2)^{-1} u with the stored inverse Minv = Rinv^T Rinv:
+// one block per (solver, row j of Minv), fixed-tree dot products
+__global__ void cg_pb_b(const CgDesc *ds, const int2 *items, int nitems) {
+    __shared__ double red[BS];
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        const CgDesc d = ds[it.x];
+        const int j = it.y / d.W, c = it.y - (it.y / d.W) * d.W;
+        double v = 0.0;
+        for (int l = threadIdx.x; l < d.rank; l += BS) v = fma(d.Minv[j * d.rank + l], d.ub[l * d.W + c], v);
+        red[threadIdx.x] = v;
         __syncthreads();
-        for (int e = threadIdx.x; e < rw; e += BS) {
-            const int j = e / d.W, c = e - (e / d.W) * d.W;
-            double t = 0.0;
-            for (int l = 0; l <= j; ++l) t = fma(d.Rinv[j * d.rank + l], su[l * d.W + c], t);
-            st[e] = t;
+        for (int h = BS / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
         }
-        __syncthreads();
-        for (int e = threadIdx.x; e < rw; e += BS) {
-            const int j = e / d.W, c = e - (e / d.W) * d.W;
-            double w = 0.0;
-            for (int l = j; l < d.rank; ++l) w = fma(d.Rinv[l * d.rank + j], st[l * d.W + c], w);
-            d.wv[e] = w;
-        }
+        if (threadIdx.x == 0) d.wv[it.y] = red[0];
         __syncthreads();
     }
 }
@@ -553,7 +548,8 @@ mm_status precond_enqueue(mm_solver_batch b, hipStream_t s, int init) {
                        static_cast<const int2 *>(b->items_pa.ptr), b->n_pa);
     hipLaunchKernelGGL(cg_pu_b, dim3(pgrid(b->n_pu, b->grid_cap)), dim3(BS), 0, s, ds,
                        static_cast<const int2 *>(b->items_pu.ptr), b->n_pu);
-    hipLaunchKernelGGL(cg_pb_b, dim3(pgrid(nsol, 1024)), dim3(BS), 0, s, ds, nsol);
+    hipLaunchKernelGGL(cg_pb_b, dim3(pgrid(b->n_pu, b->grid_cap)), dim3(BS), 0, s, ds,
+                       static_cast<const int2 *>(b->items_pu.ptr), b->n_pu);
     hipLaunchKernelGGL(cg_pc_b, dim3(pgrid(b->n_pc, b->grid_cap)), dim3(BS), 0, s, ds,
                        static_cast<const int2 *>(b->items_pc.ptr), b->n_pc, init);
     MM_HIP_TRY(hipGetLastError());
@@ -755,7 +751,7 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
     }
     // Woodbury factors for this noise level: Rinv = inverse of the Cholesky factor
     // of I + L^T L / sigma2 (host, rank x rank)
-    std::vector<double> rinv;
+    std::vector<double> rinv, minv;
     if (rank > 0) {
         const int r = rank;
         std::vector<double> M((size_t)r * r), C((size_t)r * r, 0.0);
@@ -782,6 +778,15 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
                 for (int k = c; k < i; ++k) t -= C[i * r + k] * rinv[k * r + c];
                 rinv[i * r + c] = t / C[i * r + i];
             }
+        // M^{-1} = Rinv^T Rinv: symmetric positive definite by construction
+        minv.assign((size_t)r * r, 0.0);
+        for (int i = 0; i < r; ++i)
+            for (int j = 0; j <= i; ++j) {
+                double t = 0.0;
+                for (int k = i; k < r; ++k) t += rinv[k * r + i] * rinv[k * r + j];
+                minv[i * r + j] = t;
+                minv[j * r + i] = t;
+            }
     }
     mm_solver sv = new (std::nothrow) mm_solver_s();
     if (!sv) {
@@ -799,7 +804,7 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
     size_t agg_b = 0, part_b = 0;
     sv->batchable = sweep_batch_bytes(plan, W, &agg_b, &part_b);
     agg_b = (agg_b + 255) & ~size_t(255);
-    const size_t pcd = rank > 0 ? vec + (size_t)NRED * W + (size_t)PUB * rank * W + (size_t)rank * W +
+    const size_t pcd = rank > 0 ? vec + (size_t)NRED * W + (size_t)PUB * rank * W + (size_t)2 * rank * W +
                                       (size_t)rank * rank
                                 : 0;
     mm_status st =
@@ -839,12 +844,13 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
         d.part_rz = q + vec;
         d.part_u = d.part_rz + (size_t)NRED * W;
         d.wv = d.part_u + (size_t)PUB * rank * W;
-        double *rv = d.wv + (size_t)rank * W;
-        d.Rinv = rv;
+        d.ub = d.wv + (size_t)rank * W;
+        double *rv = d.ub + (size_t)rank * W;
+        d.Minv = rv;
         d.Lpc = static_cast<const double *>(pc->L.ptr);
         d.kmax = pc->kmax;
         d.rank = rank;
-        if (hipMemcpyAsync(rv, rinv.data(), rinv.size() * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
+        if (hipMemcpyAsync(rv, minv.data(), minv.size() * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
             dev_free(sv->ws);
             dev_free(sv->buf);
