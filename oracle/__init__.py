@@ -15,6 +15,12 @@ Contents (each function cites the passage it follows):
                      the beta_GLS formula) with H = [1, x_1 .. x_d].
 * ``predict``        posterior mean h(z)^T beta + k_z^T alpha (eq. gp_mean,
                      eq. gp_mean_2).
+* ``cg_lanczos`` / ``lanczos_tridiagonal`` / ``logquad_from_cg``  CG
+                     coefficients, the Lanczos matrix built from them and the
+                     quadrature ||z||^2 e_1^T log(T) e_1 of the stochastic
+                     log-determinant (Appendix A, Algorithm 2 and eq.
+                     approximationLogDet); ``quad_log_exact``, ``logdet_exact``
+                     the dense quantities they estimate.
 * ``pivoted_cholesky`` / ``woodbury_apply``  the rank-k pivoted Cholesky
                      preconditioner P = L L^T + sigma^2 I and its inverse by
                      the Woodbury identity (Appendix A, 'Preconditioning').
@@ -289,3 +295,68 @@ def woodbury_apply(L, sigma2: float, r):
     k = L.shape[1]
     M = np.eye(k) + (L.T @ L) / sigma2
     return r / sigma2 - L @ np.linalg.solve(M, L.T @ r) / (sigma2 * sigma2)
+
+
+def cg_lanczos(A, b, steps: int, rtol: float = 0.0):
+    """Conjugate gradients on dense A with a null start, recording the step
+    sizes alpha_k and ratios beta_k (Appendix A, Algorithm 2 without
+    preconditioner).  Like the algorithm, it returns when the residual meets
+    the tolerance; beta is recorded only for iterations that continue.
+    Returns (alphas, betas) as arrays."""
+    A = np.asarray(A, dtype=np.float64)
+    r = np.asarray(b, dtype=np.float64).copy()
+    x = np.zeros_like(r)
+    p = r.copy()
+    rr = float(r @ r)
+    bnorm = np.sqrt(rr)
+    alphas, betas = [], []
+    for _ in range(steps):
+        Ap = A @ p
+        alpha = rr / float(p @ Ap)
+        alphas.append(alpha)
+        x += alpha * p
+        r -= alpha * Ap
+        rr_new = float(r @ r)
+        if np.sqrt(rr_new) <= rtol * bnorm:
+            break
+        beta = rr_new / rr
+        betas.append(beta)
+        p = r + beta * p
+        rr = rr_new
+    return np.array(alphas), np.array(betas)
+
+
+def lanczos_tridiagonal(alphas, betas):
+    """The Lanczos tridiagonal matrix from CG coefficients (Algorithm 2):
+    T[k,k] = 1/alpha_k + beta_{k-1}/alpha_{k-1} (beta_0/alpha_0 = 0) and
+    T[k,k+1] = T[k+1,k] = sqrt(beta_k)/alpha_k, of size m = len(betas)
+    (the iterations that continued)."""
+    m = len(betas)
+    T = np.zeros((m, m))
+    for k in range(m):
+        T[k, k] = 1.0 / alphas[k] + (betas[k - 1] / alphas[k - 1] if k > 0 else 0.0)
+        if k + 1 < m:
+            T[k, k + 1] = T[k + 1, k] = np.sqrt(betas[k]) / alphas[k]
+    return T
+
+
+def logquad_from_cg(alphas, betas, znorm2: float) -> float:
+    """||z||^2 e_1^T log(T) e_1 (eq. approximationLogDet with the exact norm of
+    the probe in place of sqrt(N))."""
+    T = lanczos_tridiagonal(alphas, betas)
+    w, Q = np.linalg.eigh(T)
+    return float(znorm2 * np.sum(Q[0, :] ** 2 * np.log(w)))
+
+
+def quad_log_exact(A, Z) -> np.ndarray:
+    """z_i^T log(A) z_i for each column of Z, by the dense eigendecomposition."""
+    w, Q = np.linalg.eigh(np.asarray(A, dtype=np.float64))
+    P = Q.T @ np.asarray(Z, dtype=np.float64)
+    if P.ndim == 1:
+        P = P[:, None]
+    return (np.log(w)[:, None] * P * P).sum(axis=0)
+
+
+def logdet_exact(A) -> float:
+    """log det A = 2 sum log diag(chol(A)) (textbook Cholesky of this module)."""
+    return float(2.0 * np.sum(np.log(np.diag(cholesky(np.asarray(A, dtype=np.float64))))))
