@@ -309,6 +309,34 @@ mm_status mm_solver_batch_poll(mm_solver_batch batch, int32_t *active, void *str
 mm_status mm_solver_batch_destroy(mm_solver_batch batch);
 
 /*
+ * Stochastic log-determinant of K + sigma2 I (Appendix A: Hutchinson's
+ * estimator with partial Lanczos decompositions taken from conjugate
+ * gradients, Algorithm 2 and eq. approximationLogDet):
+ *     log det(K + sigma2 I) ~ (1/l) sum_i ||z_i||^2 e_1^T log(T_i) e_1,
+ * where T_i is the Lanczos matrix of CG started from probe z_i with a null
+ * initial guess (for Rademacher probes ||z_i||^2 = n, the paper's form).
+ *   Z       device, n x nprobes column-major probes (caller order; the caller
+ *           draws them, e.g. Rademacher or standard normal)
+ *   nprobes 1..64
+ *   steps   maximal CG (Lanczos) steps per probe
+ *   rtol    a probe stops early when ||r|| <= rtol ||z|| (0: run all steps)
+ *   logdet  host, the estimate
+ *   quad    host, nprobes per-probe terms ||z_i||^2 e_1^T log(T_i) e_1 (may be NULL)
+ *   lanczos_steps host, nprobes sizes of the T_i (may be NULL)
+ * No preconditioner (the preconditioned estimator needs probes drawn from the
+ * preconditioner's distribution).  Synchronises.
+ */
+mm_status gp_logdet(mm_plan plan, double sigma2, const double *Z, int64_t ldz, int32_t nprobes,
+                    int32_t steps, double rtol, double *logdet, double *quad, int32_t *lanczos_steps,
+                    void *stream);
+
+/* Host only: e_1^T log(T) e_1 for the m x m Lanczos matrix built from CG
+ * coefficients alpha[0..m-1], beta[0..m-2] (Algorithm 2): T[k][k] = 1/alpha_k +
+ * beta_{k-1}/alpha_{k-1}, T[k][k+1] = sqrt(beta_k)/alpha_k.  MM_ERR_BREAKDOWN if
+ * the spectrum is not positive. */
+mm_status mm_lanczos_logquad(const double *alpha, const double *beta, int32_t m, double *out);
+
+/*
  * Batched products over independent point sets: y_k = (K_k + diag_shift I) v_k
  * for every plan k of the batch (Section 2, eq. Ky, per problem), with one
  * gather launch, one launch per kernel configuration and sweep phase, and one

@@ -89,6 +89,11 @@ _SIGS = {
                                            ctypes.POINTER(_P)]),
     "gp_pcg_solve": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
                                     _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_MMSolveInfo), _P]),
+    "gp_logdet": (ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_int32), _P]),
+    "mm_lanczos_logquad": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                          ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "mm_solver_footprint_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                                     ctypes.POINTER(_MMKernel)]),
     "mm_solver_create": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_double, _P,
@@ -339,6 +344,18 @@ class Plan:
                                 ctypes.c_void_p(mean.data_ptr()), _stream_ptr(self._stream)))
         return mean
 
+    def logdet(self, sigma2: float, probes, steps: int = 200, rtol: float = 0.0):
+        """Stochastic log det(K + sigma2 I) from CG-Lanczos quadratures of the probe
+        columns (n, l).  Returns (estimate, per-probe terms, Lanczos sizes)."""
+        Zc = _colmajor(probes, self.n)
+        k = Zc.shape[0]
+        est = ctypes.c_double()
+        quad = (ctypes.c_double * k)()
+        steps_out = (ctypes.c_int32 * k)()
+        _check(lib().gp_logdet(self._h, float(sigma2), ctypes.c_void_p(Zc.data_ptr()), self.n, k, int(steps),
+                               float(rtol), ctypes.byref(est), quad, steps_out, _stream_ptr(self._stream)))
+        return est.value, np.array(quad[:]), np.array(steps_out[:])
+
     def profile_enable(self, on: bool = True):
         _check(lib().mm_plan_profile_enable(self._h, 1 if on else 0))
 
@@ -538,6 +555,17 @@ class MvmBatch:
             self.close()
         except Exception:
             pass
+
+
+def lanczos_logquad(alpha, beta) -> float:
+    """e_1^T log(T) e_1 of the Lanczos matrix of CG coefficients (host computation)."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    m = len(a)
+    out = ctypes.c_double()
+    bp = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if len(b) else None
+    _check(lib().mm_lanczos_logquad(a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), bp, m, ctypes.byref(out)))
+    return out.value
 
 
 def levels(n: int) -> int:

@@ -43,6 +43,9 @@ struct CgDesc {
     double *part_u;       // PUB x rank x W partial L^T r
     double *wv;           // rank x W
     int kmax, rank;
+    // Lanczos coefficients (Algorithm 2): alpha_k, beta_k of column r at [(k * W + r) * 2 + {0, 1}]
+    double *tlog;
+    int tlog_cap;
     int64_t n;
     int W;
     int ncols;
@@ -181,6 +184,8 @@ __global__ void cg_alpha_b(const CgDesc *ds, int nsol) {
                     c[5] = 0.0;
                 } else {
                     c[2] = c[0] / s;
+                    const int it = (int)c[6];
+                    if (d.tlog && it < d.tlog_cap) d.tlog[((int64_t)it * d.W + r) * 2] = c[2];
                     c[6] += 1.0;
                 }
             } else {
@@ -237,6 +242,8 @@ __global__ void cg_beta_b(const CgDesc *ds, int nsol) {
                     c[3] = 0.0;
                 } else {
                     c[3] = rz / c[0];
+                    const int it = (int)c[6] - 1;
+                    if (d.tlog && it >= 0 && it < d.tlog_cap) d.tlog[((int64_t)it * d.W + r) * 2 + 1] = c[3];
                     atomicAdd(&d.flags[0], 1);  // integer count of still-active columns
                 }
                 c[7] = sqrt(s);
@@ -734,9 +741,70 @@ mm_status check_solve_args(mm_plan plan, double sigma2, double rtol) {
 }
 
 // Solver with W columns whose right-hand sides are filled by `fill` into B.
+// e_1^T log(T) e_1 for the Lanczos matrix T of CG coefficients (Algorithm 2):
+// T[k][k] = 1/alpha_k + beta_{k-1}/alpha_{k-1}, T[k][k+1] = sqrt(beta_k)/alpha_k.
+// The eigenvalues come from implicit symmetric QR steps with Wilkinson shifts
+// on the tridiagonal matrix (Golub & Van Loan, the symmetric tridiagonal QR
+// algorithm), accumulating only the first row q of the eigenvector matrix, so
+// that e_1^T log(T) e_1 = sum_k q_k^2 log(lambda_k).  False if it does not
+// converge or an eigenvalue is not positive.
+bool lanczos_logquad(const std::vector<double> &alpha, const std::vector<double> &beta, int m, double *out) {
+    std::vector<double> a(m), b(m > 1 ? m - 1 : 1, 0.0), q(m, 0.0);
+    for (int k = 0; k < m; ++k) {
+        a[k] = 1.0 / alpha[k] + (k > 0 ? beta[k - 1] / alpha[k - 1] : 0.0);
+        if (k + 1 < m) b[k] = std::sqrt(beta[k]) / alpha[k];
+    }
+    q[0] = 1.0;
+    const double eps = 2.220446049250313e-16;
+    int hi = m - 1, iter = 0;
+    while (hi > 0) {
+        if (std::fabs(b[hi - 1]) <= eps * (std::fabs(a[hi - 1]) + std::fabs(a[hi]))) {
+            b[hi - 1] = 0.0;
+            --hi;
+            iter = 0;
+            continue;
+        }
+        int lo = hi - 1;
+        while (lo > 0 && std::fabs(b[lo - 1]) > eps * (std::fabs(a[lo - 1]) + std::fabs(a[lo]))) --lo;
+        if (++iter > 200) return false;
+        // Wilkinson shift: the eigenvalue of the trailing 2x2 block closer to a[hi]
+        const double dd = 0.5 * (a[hi - 1] - a[hi]);
+        const double bb = b[hi - 1] * b[hi - 1];
+        const double den = dd + std::copysign(std::sqrt(dd * dd + bb), dd);
+        const double mu = den != 0.0 ? a[hi] - bb / den : a[hi];
+        double x = a[lo] - mu, z = b[lo];
+        for (int k = lo; k < hi; ++k) {
+            // rotation J = [c s; -s c] on coordinates (k, k+1) with J [x; z] = [r; 0]
+            const double r = std::hypot(x, z);
+            const double c = r > 0.0 ? x / r : 1.0, sn = r > 0.0 ? z / r : 0.0;
+            if (k > lo) b[k - 1] = r;
+            const double ak = a[k], ak1 = a[k + 1], bk = b[k];
+            a[k] = c * c * ak + 2.0 * c * sn * bk + sn * sn * ak1;
+            a[k + 1] = sn * sn * ak - 2.0 * c * sn * bk + c * c * ak1;
+            b[k] = c * sn * (ak1 - ak) + (c * c - sn * sn) * bk;
+            if (k + 1 < hi) {
+                x = b[k];
+                z = sn * b[k + 1];
+                b[k + 1] = c * b[k + 1];
+            }
+            // Q <- Q J^T on columns k, k+1 (first row only)
+            const double qk = q[k], qk1 = q[k + 1];
+            q[k] = c * qk + sn * qk1;
+            q[k + 1] = -sn * qk + c * qk1;
+        }
+    }
+    double sum = 0.0;
+    for (int k = 0; k < m; ++k) {
+        if (!(a[k] > 0.0)) return false;
+        sum += q[k] * q[k] * std::log(a[k]);
+    }
+    *out = sum;
+    return true;
+}
+
 template <class F>
 mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol, mm_precond pc, hipStream_t s,
-                     F &&fill, mm_solver *out) {
+                     F &&fill, mm_solver *out, int tlog_cap = 0) {
     const int64_t n = plan->n;
     const int R = rhs_block(plan->kernel, plan->d, ncols);
     const int W = pow2ceil(ncols > R ? ncols : R);
@@ -807,8 +875,9 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
     const size_t pcd = rank > 0 ? vec + (size_t)NRED * W + (size_t)PUB * rank * W + (size_t)2 * rank * W +
                                       (size_t)rank * rank
                                 : 0;
+    const size_t tld = (size_t)tlog_cap * W * 2;
     mm_status st =
-        dev_alloc(sv->buf, (6 * vec + (size_t)NRED * W * 8 + (size_t)W * NS + 8 + pcd) * sizeof(double));
+        dev_alloc(sv->buf, (6 * vec + (size_t)NRED * W * 8 + (size_t)W * NS + 8 + pcd + tld) * sizeof(double));
     if (st == MM_OK) {
         if (sv->batchable) {
             st = dev_alloc(sv->ws, agg_b + part_b);
@@ -838,6 +907,10 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
     d.part = base + 6 * vec;
     d.sc = d.part + (size_t)NRED * W * 8;
     d.flags = reinterpret_cast<int *>(d.sc + (size_t)W * NS);
+    if (tlog_cap > 0) {
+        d.tlog = d.sc + (size_t)W * NS + 8 + pcd;
+        d.tlog_cap = tlog_cap;
+    }
     if (rank > 0) {
         double *q = d.sc + (size_t)W * NS + 8;
         d.Z = q;
@@ -1261,6 +1334,90 @@ mm_status gp_pcg_solve(mm_plan plan, const double *y, double sigma2, int32_t fix
                        int32_t maxit, mm_precond pc, double *alpha, double *beta, mm_solve_info *info, void *stream) {
     clear_error();
     return pcg_impl(plan, y, sigma2, fixed_effects, rtol, maxit, pc, alpha, beta, info, stream);
+}
+
+mm_status mm_lanczos_logquad(const double *alpha, const double *beta, int32_t m, double *out) {
+    clear_error();
+    if (!alpha || !out || m < 1 || (m > 1 && !beta)) {
+        set_error("alpha, out (and beta for m > 1) are required, m >= 1");
+        return MM_ERR_ARG;
+    }
+    std::vector<double> al(alpha, alpha + m), be(m, 0.0);
+    for (int k = 0; k + 1 < m; ++k) be[k] = beta[k];
+    double q = 0.0;
+    if (!lanczos_logquad(al, be, m, &q)) {
+        set_error("the Lanczos matrix did not converge to a positive spectrum");
+        return MM_ERR_BREAKDOWN;
+    }
+    *out = q;
+    return MM_OK;
+}
+
+mm_status gp_logdet(mm_plan plan, double sigma2, const double *Zc, int64_t ldz, int32_t nprobes, int32_t steps,
+                    double rtol, double *logdet, double *quad, int32_t *lanczos_steps, void *stream) {
+    clear_error();
+    MM_TRY(check_solve_args(plan, sigma2, rtol > 0.0 ? rtol : 1.0));
+    if (!Zc || !logdet) {
+        set_error("Z and logdet must be non-NULL");
+        return MM_ERR_ARG;
+    }
+    if (nprobes < 1 || nprobes > 64 || steps < 1 || ldz < plan->n || !(rtol >= 0.0)) {
+        set_error("nprobes in [1, 64], steps >= 1, ldz >= n and rtol >= 0 are required");
+        return MM_ERR_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    mm_solver sv = nullptr;
+    MM_TRY(solver_new(plan, nprobes, 0, sigma2, rtol > 0.0 ? rtol : 1e-300, nullptr, s,
+                      [&](double *B, int W) {
+                          hipLaunchKernelGGL(gather_cols_kernel, dim3(grid1(plan->n * W)), dim3(BS), 0, s, Zc, ldz,
+                                             nprobes, static_cast<const int32_t *>(plan->perm.ptr), plan->n, B, W);
+                      },
+                      &sv, steps));
+    mm_status st = solver_run(sv, steps, s);
+    const int W = sv->W;
+    std::vector<double> hsc((size_t)W * NS), tl((size_t)steps * W * 2);
+    if (st == MM_OK) {
+        if (hipMemcpyAsync(hsc.data(), sv->desc.sc, hsc.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(tl.data(), sv->desc.tlog, tl.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            set_error("HIP error reading the Lanczos coefficients");
+            st = MM_ERR_HIP;
+        }
+    }
+    double sum = 0.0;
+    for (int r = 0; r < nprobes && st == MM_OK; ++r) {
+        const double *c = hsc.data() + (size_t)r * NS;
+        const int na = (int)c[6];                         // alphas recorded
+        const int m = c[5] != 0.0 ? na : na - 1;          // iterations that continued (Algorithm 2)
+        const double znorm2 = c[4] * c[4];
+        double q = 0.0;
+        if (m >= 1) {
+            std::vector<double> al(m), be(m, 0.0);
+            for (int k = 0; k < m; ++k) {
+                al[k] = tl[((size_t)k * W + r) * 2];
+                if (k + 1 < m) be[k] = tl[((size_t)k * W + r) * 2 + 1];
+            }
+            if (!lanczos_logquad(al, be, m, &q)) {
+                set_error("probe %d: the Lanczos matrix did not converge to a positive spectrum", r);
+                st = MM_ERR_BREAKDOWN;
+                break;
+            }
+            q *= znorm2;
+        } else if (na == 1) {
+            // solved exactly in one step: T = [1 / alpha_1]
+            q = znorm2 * std::log(1.0 / tl[(size_t)r * 2]);
+        }
+        if (quad) quad[r] = q;
+        if (lanczos_steps) lanczos_steps[r] = m > 0 ? m : na;
+        sum += q;
+    }
+    if (st == MM_OK) *logdet = sum / nprobes;
+    std::string msg = last_error_str();
+    mm_solver_destroy(sv);
+    if (st != MM_OK) set_error("%s", msg.c_str());
+    return st;
 }
 
 mm_status gp_cg_solve_multi(mm_plan plan, const double *Bc, int64_t ldb, int32_t nrhs, double sigma2, double rtol,
