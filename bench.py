@@ -157,6 +157,57 @@ def bench_pcg(mm, x, y, kern, rank, reps=2):
     return out
 
 
+def bench_config3(dev, steps, rank):
+    """d=3, N=500k, nu=5/2, lengthscale 0.3, x ~ N(0, I): one product with the 32
+    Rademacher probes (product and L1 forms), the stochastic log-determinant from
+    those probes (`steps` Lanczos steps), and one CG solve of the sin/cos
+    targets (sigma2 0.01) preconditioned with the rank-`rank` pivoted Cholesky."""
+    import torch
+    import paper_2508_01864_amd as mm
+    import workloads
+    p = workloads.config3()
+    n = p.n
+    x = torch.as_tensor(p.x, device=dev)
+    Z = torch.as_tensor(p.v, device=dev)          # (n, 32) Rademacher
+    out = {"workload": "d=3 N=%d nu=5/2 ell=0.3 x~N(0,I3), 32 Rademacher probes" % n}
+    for form in ("product", "l1"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = mm.Plan(x, mm.Kernel(5, form, 0.3))
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        Zc = Z.t().contiguous()
+        Yc = torch.empty_like(Zc)
+        plan.mvm_raw(Zc, Yc, 32)
+        ms = _events_ms(lambda: plan.mvm_raw(Zc, Yc, 32), 2)
+        out[form] = {"plan_build_s": tb, "mvm32_ms": ms, "points_per_s": n * 32 / (ms * 1e-3)}
+        log("config 3 %s: 32-column product %.1f ms" % (form, ms))
+        if form == "product":
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            est, quad, msteps = plan.logdet(0.01, Z, steps=steps, rtol=0.0)
+            torch.cuda.synchronize()
+            out["logdet"] = {"estimate": est, "steps": int(msteps.max()), "probes": 32,
+                             "stderr": float(np.std(quad, ddof=1) / np.sqrt(len(quad))),
+                             "seconds": time.perf_counter() - t0}
+            log("config 3 log det ~ %.6e (%d steps)" % (est, int(msteps.max())))
+            y = torch.as_tensor(p.y, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pc = mm.Precond(plan, max_rank=rank)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            alpha, _, info = plan.cg_solve(y, 0.01, rtol=1e-8, maxit=4000, precond=pc, raise_on_error=False)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            out["pcg_solve"] = {"rank": rank, "precond_s": t1 - t0, "solve_s": t2 - t1, "iters": info["iters"],
+                                "status": info["status"], "relres": info["relres_max"]}
+            log("config 3 PCG: %d iterations, %.2f s" % (info["iters"], t2 - t1))
+            pc.close()
+        plan.close()
+    return out
+
+
 def bench_batched(dev, count, iters):
     """256 uneven problems: batched vs one-at-a-time, products and CG iterations."""
     import torch
@@ -283,6 +334,10 @@ def main():
     ap.add_argument("--served-count", type=int, default=8)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--config3", action="store_true",
+                    help="also run the d=3 N=500k nu=5/2 section: one 32-probe product, the "
+                         "stochastic log-determinant from those probes and one preconditioned solve")
+    ap.add_argument("--logdet-steps", type=int, default=30)
     ap.add_argument("--pcg-rank", type=int, default=100,
                     help="rank of the pivoted Cholesky preconditioner of the extra PCG section (0: skip)")
     ap.add_argument("--maxit", type=int, default=20000,
@@ -410,6 +465,11 @@ def main():
         log("preconditioned solve: rank %d" % args.pcg_rank)
         pcg_out = bench_pcg(mm, x, y, kern, args.pcg_rank)
 
+    c3_out = None
+    if args.config3:
+        log("config 3: d=3 N=500k nu=5/2, 32 probes")
+        c3_out = bench_config3(dev, args.logdet_steps, args.pcg_rank or 100)
+
     batched_out = None
     if not args.no_batched:
         log("batched: %d problems" % args.batched_count)
@@ -452,6 +512,7 @@ def main():
         "true_relres": true_res,
         "mvm": mvm_rows,
         "pcg": pcg_out,
+        "config3": c3_out,
         "batched": batched_out,
         "served": served_out,
     }
