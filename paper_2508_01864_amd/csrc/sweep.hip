@@ -102,7 +102,7 @@ struct SweepArgs {
     const int32_t *xt;     // indices of the passes whose segments span several tiles
     const double *vin;     // n x W point-major canonical input
     double *ypart;         // G slabs of n x W: one partial result per pass of the group
-    double *agg;           // tile aggregates [2 dirs][G][ntile][W][NHALF][NSLOT]
+    double *agg;           // tile aggregates [2 dirs][G][ntile][W][NSUB][NSLOT]
     double *car;           // tile carries, same layout as agg
     double *anc;           // tile anchors [2 dirs][G][ntile]
     double *dec;           // decay from the previous tile's anchor (scan order) to the tile's, same layout
@@ -136,14 +136,19 @@ struct Cfg {
     static constexpr int NTH = PROD ? IPow<P, D - 1>::v : 1; // non-scan channel rows
     // source classes (orthants of the non-scan coordinates) and how many
     // sub-sweeps they are split over so that one state fits the register file
+    // (each sub-sweep repeats the scan for its classes)
     static constexpr int NCLS_ALL = (D == 1) ? 1 : (D == 2 ? 2 : 4);
     static constexpr int FULLSLOT = NCLS_ALL * NTH * P;
-    static constexpr int NHALF = (D == 3) ? (FULLSLOT <= 16 ? 1 : (FULLSLOT <= 32 ? 2 : 4)) : 1;
-    static constexpr int NCLS = NCLS_ALL / NHALF;
+    static constexpr int NSUB = (D == 3) ? (FULLSLOT <= 16 ? 1 : (FULLSLOT <= 32 ? 2 : 4)) : 1;
+    static constexpr int NCLS = NCLS_ALL / NSUB;
     static constexpr int NSLOT = NCLS * NTH * P;             // doubles per state
     static constexpr int G = 2 * (D - 1);                    // staged geometry doubles
-    static constexpr bool REGOUT = E <= 8 && E * NSLOT <= 64;  // keep targets in registers (short runs)
-    static constexpr int BLK = E < 8 ? E : 8;                // prefetch block of long runs
+    // keep the targets' sums in registers over the sweep (runs of 4, small states)
+    static constexpr bool REGOUT = E <= 4 && E * NSLOT <= 64;
+    // elements per block of a run's loads.  Short runs take two blocks: with
+    // one, the block loop disappears, every load of the run is hoisted and
+    // the state spills (d = 3).
+    static constexpr int BLK = E <= 8 ? E / 2 : 8;
 };
 
 template <class C>
@@ -216,6 +221,8 @@ __device__ __forceinline__ void elem_vectors(const double *geo, ElemVec<C> &ev) 
             src_vec<P>(geo[2 * k], geo[2 * k + 1], sv[k]);
             tgt_vec<P>(geo[2 * k], geo[2 * k + 1], gv[k]);
         }
+        // row th holds channel (th mod P) of the first coordinate and
+        // (th div P) of the second
 #pragma unroll
         for (int th = 0; th < C::NTH; ++th) {
             double fs = 1.0, gs = 1.0;
@@ -289,7 +296,7 @@ __device__ __forceinline__ double read_target(const State<C> &S, int cls, const 
 // Source / target class of an element in sub-sweep `hh`.  d = 2: the x1 half
 // (sources of one half feed targets of the other).  d = 3: the (x1, x2)
 // halves; a source class feeds the targets in the opposite halves of both.
-// With NHALF > 1 each sub-sweep carries only part of the classes.
+// With NSUB > 1 each sub-sweep carries only part of the classes.
 template <class C>
 __device__ __forceinline__ void classes(int flags, int hh, int &scls, int &tcls) {
     if constexpr (C::D == 1) {
@@ -303,10 +310,10 @@ __device__ __forceinline__ void classes(int flags, int hh, int &scls, int &tcls)
         const int s1 = flags & F_SIDE1;
         const int s2 = (flags & F_SIDE2) ? 1 : 0;
         const int full = s1 * 2 + s2;
-        if constexpr (C::NHALF == 1) {
+        if constexpr (C::NSUB == 1) {
             scls = full;
             tcls = 3 - full;
-        } else if constexpr (C::NHALF == 2) {
+        } else if constexpr (C::NSUB == 2) {
             scls = (s1 == hh) ? s2 : -1;
             tcls = (s1 == 1 - hh) ? 1 - s2 : -1;
         } else {
@@ -423,7 +430,7 @@ __device__ __forceinline__ void load_geo(const Smem<C> &sm, int sj, double (&geo
 template <class C>
 __device__ __forceinline__ int64_t agg_index(const SweepArgs &A, int dir, int pl, int64_t tile, int col,
                                              int hh) {
-    return (((((int64_t)dir * A.G + pl) * A.ntile + tile) * A.W + col) * C::NHALF + hh) * C::NSLOT;
+    return (((((int64_t)dir * A.G + pl) * A.ntile + tile) * A.W + col) * C::NSUB + hh) * C::NSLOT;
 }
 
 // One step of the lane scan over runs: F <- F + M(E, t) F(partner), the
@@ -700,7 +707,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, int6
     }
 
 #pragma unroll 1
-    for (int hh = 0; hh < C::NHALF; ++hh) {
+    for (int hh = 0; hh < C::NSUB; ++hh) {
         run_direction<C, MODE, 1>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab);
         run_direction<C, MODE, 0>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab);
     }
@@ -752,7 +759,7 @@ __device__ __forceinline__ void carry_small(const SweepArgs &A, int pass, int64_
     const int pl = pass - A.g0;
     const int colw = sl % C::WCOL;
     const int rowcb = sl / C::WCOL;
-    constexpr int ROWS = C::NHALF * C::NCLS * C::NTH;
+    constexpr int ROWS = C::NSUB * C::NCLS * C::NTH;
     const int row = rowcb % ROWS;
     const int cb = rowcb / ROWS;
     const int hh = row / (C::NCLS * C::NTH);
@@ -819,7 +826,7 @@ __device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int b
     if (sl >= nslice) return;
     const int colw = sl % C::WCOL;
     const int rowcb = sl / C::WCOL;  // (column block, row)
-    constexpr int ROWS = C::NHALF * C::NCLS * C::NTH;
+    constexpr int ROWS = C::NSUB * C::NCLS * C::NTH;
     const int row = rowcb % ROWS;
     const int cb = rowcb / ROWS;
     const int hh = row / (C::NCLS * C::NTH);
@@ -1075,7 +1082,7 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
     A.ntile = ntile;
     A.W = W;
     A.a = kp.a;
-    const size_t aggslab = (size_t)2 * gmax * ntile * W * C::NHALF * C::NSLOT;
+    const size_t aggslab = (size_t)2 * gmax * ntile * W * C::NSUB * C::NSLOT;
     A.agg = static_cast<double *>(p->agg.ptr);
     A.car = A.agg + aggslab;
     A.anc = A.car + aggslab;
@@ -1096,7 +1103,7 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
             // segments of the group's cross-tile passes: a contiguous range of the plan's table
             const std::vector<int> &so = p->seg_off[ti];
             const int s0 = so[k0], s1 = so[k1];
-            const int nslice = C::NHALF * C::NCLS * C::NTH * W;
+            const int nslice = C::NSUB * C::NCLS * C::NTH * W;
             A.nslice = nslice;
             A.segs = static_cast<const int4 *>(p->seg_tab[ti].ptr) + s0;
             if (s1 > s0)
@@ -1167,12 +1174,12 @@ SweepArgs make_args(mm_plan p, const double *vin, double *agg, double *part, int
     A.ntile = ntile;
     A.W = W;
     A.a = kp.a;
-    const size_t aggslab = (size_t)2 * gmax * ntile * W * C::NHALF * C::NSLOT;
+    const size_t aggslab = (size_t)2 * gmax * ntile * W * C::NSUB * C::NSLOT;
     A.agg = agg;
     A.car = A.agg + aggslab;
     A.anc = A.car + aggslab;
     A.dec = A.anc + (size_t)2 * gmax * ntile;
-    A.nslice = C::NHALF * C::NCLS * C::NTH * W;
+    A.nslice = C::NSUB * C::NCLS * C::NTH * W;
     A.segs = static_cast<const int4 *>(p->seg_tab[ti].ptr);
     A.g0 = 0;
     A.k0 = 0;
@@ -1209,10 +1216,9 @@ size_t sweep_part_bytes(int64_t n, int npass, int W) {
 }
 
 // Aggregates and carries: per tile and right-hand side at most
-// NHALF*NCLS*NTH*P <= 108 doubles (d = 3, product form, nu = 5/2), two
+// NSUB*NSLOT = 4*NTH*P <= 108 doubles (d = 3, product form, nu = 5/2), two
 // directions, per pass of a group; anchors and decays 2 each per tile and
-// pass.  The smallest
-// tile (256 positions) gives the most tiles.
+// pass.  The smallest tile (128 positions) gives the most tiles.
 static size_t agg_bytes_for(int64_t n, int W, int64_t G) {
     const int64_t ntile = (n + 127) / 128;
     const int64_t per_rhs = 108;
