@@ -72,13 +72,14 @@ def b_pass(n: int, cols: int) -> float:
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_main_d2_n100k_nu32_w4.txt")
-SWEEP_SRC = os.path.join(ROOT, "paper_2508_01864_amd", "csrc", "sweep.hip")
+SWEEP_SRC = os.path.join(ROOT, "paper_2508_01864_amd", "csrc", "sweep_core.h")
 
 
 def recorded_traffic():
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source has changed
-    since the counters were taken (the summary records the source's SHA-256)."""
+    since the counters were taken (the summary records the SHA-256 of the
+    kernels' source, sweep_core.h)."""
     import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
@@ -86,7 +87,7 @@ def recorded_traffic():
     except OSError:
         return None
     fields = dict(line.split("=", 1) for line in text.splitlines() if "=" in line and not line.startswith(" "))
-    if fields.get("sweep_hip_sha256", "").strip() != src:
+    if fields.get("sweep_core_sha256", "").strip() != src:
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])

@@ -138,6 +138,19 @@ mm_status matern_mvm(mm_plan plan, const double *v, int64_t ldv, double *y, int6
                      int32_t nrhs, double diag_shift, void *stream);
 
 /*
+ * Exact product with the lengthscale derivative of the kernel matrix (the
+ * gradients of the Section 2.3 examples, for every nu and both forms):
+ *     y = (dK/d lengthscale) v.
+ * With t = sqrt(2 nu) r / lengthscale the profile derivative is
+ * -t k'(t) / lengthscale, a profile with one more channel in the basis of the
+ * decomposition; the product form sums over the coordinates the products with
+ * one factor differentiated.  The diagonal of K does not depend on the
+ * lengthscale.  Arguments, layouts and errors as matern_mvm (no diag_shift).
+ */
+mm_status matern_mvm_dlengthscale(mm_plan plan, const double *v, int64_t ldv, double *y, int64_t ldy,
+                                  int32_t nrhs, void *stream);
+
+/*
  * Gaussian-process solve by conjugate gradients (Appendix A, Algorithm 2 with
  * the identity preconditioner and a null initial guess), each iteration one
  * product of the fast MVM:
@@ -329,6 +342,51 @@ mm_status mm_solver_batch_destroy(mm_solver_batch batch);
 mm_status gp_logdet(mm_plan plan, double sigma2, const double *Z, int64_t ldz, int32_t nprobes,
                     int32_t steps, double rtol, double *logdet, double *quad, int32_t *lanczos_steps,
                     void *stream);
+
+/*
+ * Log marginal likelihood and its gradient (eq. gp_log_likelihood and eq.
+ * gp_log_likelihood_derivative; Appendix A), zero mean, A = K + sigma2 I:
+ *     L = -1/2 y^T A^{-1} y - 1/2 log det A - n/2 log(2 pi),
+ *     dL/dtheta = 1/2 alpha^T (dA/dtheta) alpha - 1/2 tr(A^{-1} dA/dtheta),
+ * alpha = A^{-1} y.  One multi-column CG solves [y, z_1 .. z_l] together
+ * (null start, each column to rtol) and records the Lanczos coefficients of
+ * the probe columns.  Then
+ *   log det A          ~ (1/l) sum_i ||z_i||^2 e_1^T log(T_i) e_1
+ *                        (eq. approximationLogDet),
+ *   tr(A^{-1} dK/dl)   ~ (1/l) sum_i (A^{-1} z_i)^T (dK/dl z_i)
+ *                        (Hutchinson; one derivative product of the probes),
+ *   tr(A^{-1})         ~ (1/l) sum_i z_i^T A^{-1} z_i,
+ * and for the output scale tr(A^{-1} dK/d outputscale2) = (n - sigma2
+ * tr(A^{-1})) / outputscale2 with the same probes.
+ *   y        device, n targets (caller order)
+ *   Z        device, n x nprobes column-major probes (caller order),
+ *            leading dimension ldz >= n; 1 <= nprobes <= 63 (nprobes = 31
+ *            fills a 32-column sweep)
+ *   maxit    iteration limit >= 1 (also the largest Lanczos matrix)
+ *   rtol     per-column stop test ||r_c|| <= rtol ||b_c|| (> 0)
+ *   info     host, the estimates
+ *   alpha    device, n outputs A^{-1} y (caller order), or NULL
+ * Returns MM_ERR_NOCONV (info still written) when a column did not reach
+ * rtol within maxit, MM_ERR_NOTPD for the L1 form with nu >= 3/2, d >= 2.
+ * Synchronises.
+ */
+typedef struct {
+    double lml;                  /* the log marginal likelihood estimate */
+    double quad;                 /* y^T A^{-1} y */
+    double logdet;               /* stochastic log det A */
+    double dlml_dlengthscale;
+    double dlml_dsigma2;
+    double dlml_doutputscale2;
+    double trace_dk_dlengthscale; /* estimate of tr(A^{-1} dK/dl) */
+    double trace_inv;            /* estimate of tr(A^{-1}) */
+    double relres_max;           /* largest final relative residual over the columns */
+    int32_t iters;               /* CG iterations */
+    int32_t converged;           /* 1 when every column reached rtol */
+} mm_lml_info;
+
+mm_status gp_lml(mm_plan plan, const double *y, double sigma2, const double *Z, int64_t ldz,
+                 int32_t nprobes, int32_t maxit, double rtol, mm_lml_info *info, double *alpha,
+                 void *stream);
 
 /* Host only: e_1^T log(T) e_1 for the m x m Lanczos matrix built from CG
  * coefficients alpha[0..m-1], beta[0..m-2] (Algorithm 2): T[k][k] = 1/alpha_k +

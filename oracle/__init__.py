@@ -24,6 +24,13 @@ Contents (each function cites the passage it follows):
 * ``pivoted_cholesky`` / ``woodbury_apply``  the rank-k pivoted Cholesky
                      preconditioner P = L L^T + sigma^2 I and its inverse by
                      the Woodbury identity (Appendix A, 'Preconditioning').
+* ``dprofile_dell`` / ``dkernel_matrix_dell`` / ``mvm_dell``  the lengthscale
+                     derivative of the kernel (the gradients of the Section
+                     2.3 examples; the product rule for the product form).
+* ``lml_exact`` / ``lml_grad_exact`` / ``hutchinson_terms``  the log marginal
+                     likelihood and its gradient (eq. gp_log_likelihood, eq.
+                     gp_log_likelihood_derivative) by dense algebra, and the
+                     terms of the stochastic trace estimator (Appendix A).
 * ``decomposition``  (sub-module) the paper's weighted-ECDF decomposition
                      evaluated by brute-force masked sums (Props. 1-2 and the
                      Matern examples of Section 2.3); used only to pin the
@@ -360,3 +367,90 @@ def quad_log_exact(A, Z) -> np.ndarray:
 def logdet_exact(A) -> float:
     """log det A = 2 sum log diag(chol(A)) (textbook Cholesky of this module)."""
     return float(2.0 * np.sum(np.log(np.diag(cholesky(np.asarray(A, dtype=np.float64))))))
+
+
+def dprofile_dell(two_nu: int, r, ell: float) -> np.ndarray:
+    """d/d ell of k_nu(r / ell) for the scaled Matern profiles (the lengthscale
+    gradients printed with the L1 examples of Section 2.3):
+    nu = 1/2: r / ell^2 exp(-r / ell);
+    nu = 3/2: 3 r^2 / ell^3 exp(-sqrt(3) r / ell);
+    nu = 5/2: 5/3 (r^2 / ell^3 + sqrt(5) r^3 / ell^4) exp(-sqrt(5) r / ell)."""
+    r = np.asarray(r, dtype=np.float64)
+    if two_nu == 1:
+        return r / ell ** 2 * np.exp(-r / ell)
+    if two_nu == 3:
+        return 3.0 * r ** 2 / ell ** 3 * np.exp(-np.sqrt(3.0) * r / ell)
+    if two_nu == 5:
+        return 5.0 / 3.0 * (r ** 2 / ell ** 3 + np.sqrt(5.0) * r ** 3 / ell ** 4) * np.exp(-np.sqrt(5.0) * r / ell)
+    raise ValueError("two_nu must be 1, 3 or 5")
+
+
+def dkernel_matrix_dell(x, two_nu: int, form, ell: float, s2: float = 1.0, z=None) -> np.ndarray:
+    """Dense d K(Z, X) / d ell (Z defaults to X).  L1 form: s2 times the
+    profile derivative of the L1 distance.  Product form (eq. product_kernel):
+    the derivative of a product, s2 sum_j dk(|u_j|)/d ell prod_{k != j}
+    k(|u_k| / ell), with the one-dimensional profiles of ``profile``."""
+    x = _points(x)
+    zz = x if z is None else _points(z)
+    U = np.abs(zz[:, None, :] - x[None, :, :])          # (m, n, d)
+    if FORMS[form] == FORM_L1:
+        return s2 * dprofile_dell(two_nu, U.sum(axis=2), ell)
+    d = x.shape[1]
+    F = np.stack([profile(two_nu, U[:, :, k] / ell) for k in range(d)], axis=2)
+    G = np.stack([dprofile_dell(two_nu, U[:, :, k], ell) for k in range(d)], axis=2)
+    out = np.zeros(U.shape[:2])
+    for j in range(d):
+        term = G[:, :, j].copy()
+        for k in range(d):
+            if k != j:
+                term = term * F[:, :, k]
+        out += term
+    return s2 * out
+
+
+def mvm_dell(x, v, two_nu: int, form, ell: float, s2: float = 1.0, z=None):
+    """Dense y = (dK(Z, X)/d ell) v and its absolute counterpart (dK/d ell)|v|
+    (every entry of dK/d ell is non-negative)."""
+    D = dkernel_matrix_dell(x, two_nu, form, ell, s2, z=z)
+    v = np.asarray(v, dtype=np.float64)
+    return D @ v, D @ np.abs(v)
+
+
+def lml_exact(x, y, two_nu: int, form, ell: float, s2: float, sigma2: float) -> float:
+    """Log marginal likelihood with zero mean (eq. gp_log_likelihood):
+    -1/2 y^T A^{-1} y - 1/2 log det A - n/2 log(2 pi), A = K + sigma2 I, by
+    the textbook Cholesky of this module."""
+    A = kernel_matrix(x, two_nu, form, ell, s2, sigma2=sigma2)
+    L = cholesky(A)
+    y = np.asarray(y, dtype=np.float64)
+    alpha = cholesky_solve(L, y)
+    n = len(y)
+    return float(-0.5 * y @ alpha - np.sum(np.log(np.diag(L))) - 0.5 * n * np.log(2.0 * np.pi))
+
+
+def lml_grad_exact(x, y, two_nu: int, form, ell: float, s2: float, sigma2: float):
+    """Gradient of ``lml_exact`` (eq. gp_log_likelihood_derivative),
+    1/2 alpha^T dA alpha - 1/2 tr(A^{-1} dA), for the lengthscale
+    (dA = dK/d ell), the noise variance (dA = I) and the output scale s2
+    (dA = K / s2), with the dense inverse.  Returns (d_ell, d_sigma2, d_s2)."""
+    K = kernel_matrix(x, two_nu, form, ell, s2)
+    A = K + sigma2 * np.eye(K.shape[0])
+    L = cholesky(A)
+    Ainv = cholesky_solve(L, np.eye(K.shape[0]))
+    alpha = Ainv @ np.asarray(y, dtype=np.float64)
+    D = dkernel_matrix_dell(x, two_nu, form, ell, s2)
+    g_ell = 0.5 * alpha @ D @ alpha - 0.5 * np.sum(Ainv * D.T)
+    g_sig = 0.5 * alpha @ alpha - 0.5 * np.trace(Ainv)
+    g_s2 = (0.5 * alpha @ K @ alpha - 0.5 * np.sum(Ainv * K.T)) / s2
+    return float(g_ell), float(g_sig), float(g_s2)
+
+
+def hutchinson_terms(A, M, Z) -> np.ndarray:
+    """z_i^T A^{-1} M z_i for each probe column of Z (the terms of the
+    stochastic trace estimator of Appendix A, 'Stochastic trace estimation'),
+    with a dense solve."""
+    Z = np.asarray(Z, dtype=np.float64)
+    if Z.ndim == 1:
+        Z = Z[:, None]
+    U = cholesky_solve(cholesky(np.asarray(A, dtype=np.float64)), Z)
+    return np.einsum("ij,ij->j", U, np.asarray(M, dtype=np.float64) @ Z)

@@ -56,6 +56,14 @@ class _MMSolveInfo(ctypes.Structure):
                 ("relres_max", ctypes.c_double)]
 
 
+class _MMLmlInfo(ctypes.Structure):
+    _fields_ = [("lml", ctypes.c_double), ("quad", ctypes.c_double), ("logdet", ctypes.c_double),
+                ("dlml_dlengthscale", ctypes.c_double), ("dlml_dsigma2", ctypes.c_double),
+                ("dlml_doutputscale2", ctypes.c_double), ("trace_dk_dlengthscale", ctypes.c_double),
+                ("trace_inv", ctypes.c_double), ("relres_max", ctypes.c_double),
+                ("iters", ctypes.c_int32), ("converged", ctypes.c_int32)]
+
+
 # name -> (restype, argtypes)
 _P = ctypes.c_void_p
 _SIGS = {
@@ -72,6 +80,9 @@ _SIGS = {
     "mm_plan_destroy": (ctypes.c_int, [_P]),
     "matern_mvm": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int32,
                                   ctypes.c_double, _P]),
+    "matern_mvm_dlengthscale": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int32, _P]),
+    "gp_lml": (ctypes.c_int, [_P, _P, ctypes.c_double, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.c_double, ctypes.POINTER(_MMLmlInfo), _P, _P]),
     "gp_cg_solve": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                    ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(_MMSolveInfo), _P]),
@@ -271,6 +282,45 @@ class Plan:
                                 ctypes.c_void_p(yc.data_ptr()), self.n, nrhs, float(shift),
                                 _stream_ptr(self._stream)))
         return yc.view(-1) if v.dim() == 1 else yc.t()
+
+    def mvm_dlengthscale(self, v, out=None):
+        """y = (dK/d lengthscale) v for v of shape (n,) or (n, nrhs)."""
+        torch = _torch()
+        vc = _colmajor(v, self.n)
+        nrhs = vc.shape[0]
+        yc = out if out is not None else torch.empty_like(vc)
+        _check(lib().matern_mvm_dlengthscale(self._h, ctypes.c_void_p(vc.data_ptr()), self.n,
+                                             ctypes.c_void_p(yc.data_ptr()), self.n, nrhs,
+                                             _stream_ptr(self._stream)))
+        return yc.view(-1) if v.dim() == 1 else yc.t()
+
+    def mvm_dlengthscale_raw(self, vc, yc, nrhs: int):
+        """Derivative product on preallocated column-major buffers (nrhs, n)."""
+        _check(lib().matern_mvm_dlengthscale(self._h, ctypes.c_void_p(vc.data_ptr()), self.n,
+                                             ctypes.c_void_p(yc.data_ptr()), self.n, int(nrhs),
+                                             _stream_ptr(self._stream)))
+
+    def lml(self, y, sigma2: float, probes, maxit: int = 20000, rtol: float = 1e-8,
+            raise_on_error: bool = True, want_alpha: bool = False):
+        """Log marginal likelihood (zero mean) and its gradient in the lengthscale,
+        the noise variance and the output scale, with the stochastic log-determinant
+        and trace estimates from the probe columns (n, l), l <= 63.  Returns a dict
+        (and alpha = A^{-1} y when want_alpha)."""
+        torch = _torch()
+        yc = _colmajor(y, self.n).view(-1)
+        Zc = _colmajor(probes, self.n)
+        k = Zc.shape[0]
+        info = _MMLmlInfo()
+        alpha = torch.empty_like(yc) if want_alpha else None
+        st = lib().gp_lml(self._h, ctypes.c_void_p(yc.data_ptr()), float(sigma2), ctypes.c_void_p(Zc.data_ptr()),
+                          self.n, k, int(maxit), float(rtol), ctypes.byref(info),
+                          ctypes.c_void_p(alpha.data_ptr()) if want_alpha else None, _stream_ptr(self._stream))
+        msg = last_error()
+        if st != MM_OK and raise_on_error:
+            raise MaternError(st, msg)
+        out = {name: getattr(info, name) for name, _ in _MMLmlInfo._fields_}
+        out["status"] = STATUS_NAMES[st]
+        return (out, alpha) if want_alpha else out
 
     def mvm_raw(self, vc, yc, nrhs: int, shift: float = 0.0):
         """Product on preallocated column-major buffers (no copies): vc, yc of shape (nrhs, n)."""

@@ -49,14 +49,16 @@ __global__ void scatter_out_kernel(const double *vin, const double *yacc, int W,
     }
 }
 
-__global__ void fill_int_kernel(int *p, int n, int val) {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = val;
-}
-
-__global__ void fill_kernel(double *p, int64_t n, double val) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-         e += (int64_t)gridDim.x * blockDim.x)
-        p[e] = val;
+// y[perm[c], r] = scale * yacc[c, r]: the derivative product has no diagonal term
+__global__ void scale_out_kernel(const double *yacc, int W, int nrhs, const int32_t *perm, int64_t n,
+                                 double scale, double *y, int64_t ldy) {
+    const int64_t total = n * nrhs;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / n);
+        const int64_t c = e - (int64_t)r * n;
+        y[(int64_t)r * ldy + perm[c]] = scale * yacc[c * W + r];
+    }
 }
 
 // union points for prediction: [canonical x ; z] column-major, and weights [alpha ; 0]
@@ -119,11 +121,11 @@ mm_status profile_flush(mm_plan p, double *ms_out, int64_t *cnt_out) {
     return MM_OK;
 }
 
-mm_status ensure_work(mm_plan p, int W) {
+mm_status ensure_work(mm_plan p, int W, bool der) {
     const size_t vbytes = (size_t)p->n * W * sizeof(double);
     MM_TRY(dev_reserve(p->vin, vbytes));
     MM_TRY(dev_reserve(p->yacc, vbytes));
-    MM_TRY(dev_reserve(p->agg, sweep_agg_bytes(p->n, p->d, W, p->kernel)));
+    MM_TRY(dev_reserve(p->agg, sweep_agg_bytes(p->n, p->d, W, p->kernel, der)));
     MM_TRY(dev_reserve(p->part, sweep_part_bytes(p->n, (int)p->passes.size(), W)));
     return MM_OK;
 }
@@ -301,6 +303,39 @@ mm_status matern_mvm(mm_plan plan, const double *v, int64_t ldv, double *y, int6
     launch_gather_in(v, ldv, nrhs, perm, plan->n, vin, W, s);
     MM_TRY(sweep_into(plan, vin, yacc, W, R, s));
     launch_scatter_out(vin, yacc, W, nrhs, perm, plan->n, plan->kernel.outputscale2, diag_shift, y, ldy, s);
+    MM_HIP_TRY(hipGetLastError());
+    return MM_OK;
+}
+
+mm_status matern_mvm_dlengthscale(mm_plan plan, const double *v, int64_t ldv, double *y, int64_t ldy,
+                                  int32_t nrhs, void *stream) {
+    clear_error();
+    if (!plan || !v || !y) {
+        set_error("plan, v and y must be non-NULL");
+        return MM_ERR_ARG;
+    }
+    if (nrhs < 1 || nrhs > 256) {
+        set_error("nrhs must be in [1, 256] (got %d)", nrhs);
+        return MM_ERR_ARG;
+    }
+    if (ldv < plan->n || ldy < plan->n) {
+        set_error("ldv and ldy must be >= n");
+        return MM_ERR_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->last_stream = s;
+    const int R = rhs_block(plan->kernel, plan->d, nrhs);
+    const int W = (nrhs + R - 1) / R * R;
+    MM_TRY(ensure_work(plan, W, true));
+    const int32_t *perm = static_cast<const int32_t *>(plan->perm.ptr);
+    double *vin = static_cast<double *>(plan->vin.ptr);
+    double *yacc = static_cast<double *>(plan->yacc.ptr);
+    launch_gather_in(v, ldv, nrhs, perm, plan->n, vin, W, s);
+    MM_TRY(sweep_all_dl(plan, vin, yacc, W, R, s));
+    // dK/dl = outputscale2 / l * (l dk/dl sums)
+    const double scale = plan->kernel.outputscale2 / plan->kernel.lengthscale;
+    hipLaunchKernelGGL(scale_out_kernel, dim3(grid1(plan->n * nrhs)), dim3(BS), 0, s, yacc, W, nrhs, perm,
+                       plan->n, scale, y, ldy);
     MM_HIP_TRY(hipGetLastError());
     return MM_OK;
 }

@@ -153,7 +153,8 @@ struct BatchEntry {
 // plan's passes run as one group; false if their partial slabs would exceed
 // the group budget (such a problem runs alone through sweep_all).
 bool sweep_batch_bytes(mm_plan p, int W, size_t *agg_bytes, size_t *part_bytes);
-bool sweep_batch_bytes_n(int64_t n, int npass, int W, size_t *agg_bytes, size_t *part_bytes);
+bool sweep_batch_bytes_n(int64_t n, int d, const mm_kernel &k, int npass, int W, size_t *agg_bytes,
+                         size_t *part_bytes);
 constexpr int ACC_CHUNK = 2048;
 struct AccumDesc {
     const double *ypart;
@@ -181,8 +182,11 @@ mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB,
 mm_status sweep_batch_run(SweepBatch &b, hipStream_t s);
 void sweep_batch_free(SweepBatch &b);
 mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int R, hipStream_t s);
+// yacc <- the off-diagonal sums of l dK/dl applied to vin (unscaled; canonical order)
+mm_status sweep_all_dl(mm_plan p, const double *vin, double *yacc, int W, int R, hipStream_t s);
 int rhs_block(const mm_kernel &k, int d, int nrhs);
-size_t sweep_agg_bytes(int64_t n, int d, int W, const mm_kernel &k);
+size_t sweep_agg_bytes(int64_t n, int d, int W, const mm_kernel &k, bool der = false);
+int agg_per_rhs(int d, const mm_kernel &k, bool der);
 size_t sweep_part_bytes(int64_t n, int npass, int W);
 int group_passes(mm_plan p, int W);
 mm_status upload_pass_tables(mm_plan p);
@@ -190,7 +194,8 @@ mm_status upload_pass_tables(mm_plan p);
 // mvm.hip helpers
 mm_status mvm_internal(mm_plan p, const double *vin, double *yout, int W, int nrhs,
                        double shift, hipStream_t s);
-mm_status ensure_work(mm_plan p, int W);
+// reserve the plan's product buffers for W columns (der: also the lengthscale-derivative sweeps)
+mm_status ensure_work(mm_plan p, int W, bool der = false);
 
 // permutation kernels
 void launch_gather_in(const double *v, int64_t ldv, int nrhs, const int32_t *perm, int64_t n,

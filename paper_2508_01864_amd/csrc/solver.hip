@@ -508,6 +508,44 @@ mm_status upload_vec(DevBuf &b, const std::vector<T> &v) {
     return MM_OK;
 }
 
+// Right-hand sides of the likelihood solve: column 0 the targets, columns
+// 1..l the probes, the padding zero (canonical rows).
+__global__ void gather_lml_kernel(const double *y, const double *Z, int64_t ldz, int l, const int32_t *perm,
+                                  int64_t n, double *B, int W) {
+    const int64_t total = n * W;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / W;
+        const int r = (int)(e - c * W);
+        const int64_t i = perm[c];
+        B[e] = r == 0 ? y[i] : (r <= l ? Z[(int64_t)(r - 1) * ldz + i] : 0.0);
+    }
+}
+
+// Inputs of the derivative product: alpha = X[:, 0] and the probes B[:, 1..].
+__global__ void lml_mix_kernel(const double *X, const double *B, int64_t n, int W, double *V) {
+    const int64_t total = n * W;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+        V[e] = (e % W) == 0 ? X[e] : B[e];
+}
+
+// Per row block and column: partial sums of X.B, X.D and X.X (three NRED x W
+// slabs of part).
+__global__ void lml_dots_kernel(const double *X, const double *B, const double *D, int64_t n, int W, double *part) {
+    __shared__ double sm[BS];
+    int64_t lo, hi;
+    row_range(n, blockIdx.x, lo, hi);
+    double xb = 0.0, xd = 0.0, xx = 0.0;
+    for (int64_t e = lo * W + threadIdx.x; e < hi * W; e += BS) {
+        const double x = X[e];
+        xb = fma(x, B[e], xb);
+        xd = fma(x, D[e], xd);
+        xx = fma(x, x, xx);
+    }
+    block_col_sum(xb, W, sm, part, blockIdx.x);
+    block_col_sum(xd, W, sm, part + (size_t)NRED * W, blockIdx.x);
+    block_col_sum(xx, W, sm, part + (size_t)2 * NRED * W, blockIdx.x);
+}
+
 }  // namespace
 }  // namespace mm
 
@@ -550,7 +588,6 @@ namespace {
 // Z = P^{-1} R for the preconditioned members (and P = Z when init).
 mm_status precond_enqueue(mm_solver_batch b, hipStream_t s, int init) {
     const CgDesc *ds = static_cast<const CgDesc *>(b->cg_desc.ptr);
-    const int nsol = (int)b->members.size();
     hipLaunchKernelGGL(cg_pa_b, dim3(pgrid(b->n_pa, b->grid_cap)), dim3(BS), 0, s, ds,
                        static_cast<const int2 *>(b->items_pa.ptr), b->n_pa);
     hipLaunchKernelGGL(cg_pu_b, dim3(pgrid(b->n_pu, b->grid_cap)), dim3(BS), 0, s, ds,
@@ -740,7 +777,6 @@ mm_status check_solve_args(mm_plan plan, double sigma2, double rtol) {
     return MM_OK;
 }
 
-// Solver with W columns whose right-hand sides are filled by `fill` into B.
 // e_1^T log(T) e_1 for the Lanczos matrix T of CG coefficients (Algorithm 2):
 // T[k][k] = 1/alpha_k + beta_{k-1}/alpha_{k-1}, T[k][k+1] = sqrt(beta_k)/alpha_k.
 // The eigenvalues come from implicit symmetric QR steps with Wilkinson shifts
@@ -799,6 +835,31 @@ bool lanczos_logquad(const std::vector<double> &alpha, const std::vector<double>
         sum += q[k] * q[k] * std::log(a[k]);
     }
     *out = sum;
+    return true;
+}
+
+// ||z||^2 e_1^T log(T) e_1 of solver column r from its recorded CG
+// coefficients: c the column's scalars (NS), tl the coefficient log
+// [iteration][W][alpha, beta].  The iterations that continued past their
+// alpha define T (Algorithm 2).  False if T has no positive spectrum.
+bool column_logquad(const double *c, const std::vector<double> &tl, int W, int r, double *q, int *msteps) {
+    const int na = (int)c[6];                  // alphas recorded
+    const int m = c[5] != 0.0 ? na : na - 1;   // iterations that continued
+    const double znorm2 = c[4] * c[4];
+    *q = 0.0;
+    *msteps = m > 0 ? m : na;
+    if (m >= 1) {
+        std::vector<double> al(m), be(m, 0.0);
+        for (int k = 0; k < m; ++k) {
+            al[k] = tl[((size_t)k * W + r) * 2];
+            if (k + 1 < m) be[k] = tl[((size_t)k * W + r) * 2 + 1];
+        }
+        if (!lanczos_logquad(al, be, m, q)) return false;
+        *q *= znorm2;
+    } else if (na == 1) {
+        // solved exactly in one step: T = [1 / alpha_1]
+        *q = znorm2 * std::log(1.0 / tl[(size_t)r * 2]);
+    }
     return true;
 }
 
@@ -1109,7 +1170,7 @@ size_t mm_solver_footprint_bytes(int64_t n, int32_t d, int32_t fixed_effects, co
     const int npass = n < 2 ? 0 : (d == 1 ? 1 : (d == 2 ? L : L * (L + 1) / 2));
     size_t b = ((size_t)6 * n * W + (size_t)NRED * W * 8 + (size_t)W * NS + 8) * sizeof(double);
     size_t agg_b = 0, part_b = 0;
-    if (sweep_batch_bytes_n(n, npass, W, &agg_b, &part_b)) {
+    if (sweep_batch_bytes_n(n, d, *kernel, npass, W, &agg_b, &part_b)) {
         b += ((agg_b + 255) & ~size_t(255)) + part_b;
     } else {  // a lone solver sweeps in the plan's work buffers
         b += 2 * (size_t)n * W * sizeof(double) + sweep_agg_bytes(n, d, W, *kernel) + sweep_part_bytes(n, npass, W);
@@ -1388,32 +1449,128 @@ mm_status gp_logdet(mm_plan plan, double sigma2, const double *Zc, int64_t ldz, 
     }
     double sum = 0.0;
     for (int r = 0; r < nprobes && st == MM_OK; ++r) {
-        const double *c = hsc.data() + (size_t)r * NS;
-        const int na = (int)c[6];                         // alphas recorded
-        const int m = c[5] != 0.0 ? na : na - 1;          // iterations that continued (Algorithm 2)
-        const double znorm2 = c[4] * c[4];
         double q = 0.0;
-        if (m >= 1) {
-            std::vector<double> al(m), be(m, 0.0);
-            for (int k = 0; k < m; ++k) {
-                al[k] = tl[((size_t)k * W + r) * 2];
-                if (k + 1 < m) be[k] = tl[((size_t)k * W + r) * 2 + 1];
-            }
-            if (!lanczos_logquad(al, be, m, &q)) {
-                set_error("probe %d: the Lanczos matrix did not converge to a positive spectrum", r);
-                st = MM_ERR_BREAKDOWN;
-                break;
-            }
-            q *= znorm2;
-        } else if (na == 1) {
-            // solved exactly in one step: T = [1 / alpha_1]
-            q = znorm2 * std::log(1.0 / tl[(size_t)r * 2]);
+        int ms = 0;
+        if (!column_logquad(hsc.data() + (size_t)r * NS, tl, W, r, &q, &ms)) {
+            set_error("probe %d: the Lanczos matrix did not converge to a positive spectrum", r);
+            st = MM_ERR_BREAKDOWN;
+            break;
         }
         if (quad) quad[r] = q;
-        if (lanczos_steps) lanczos_steps[r] = m > 0 ? m : na;
+        if (lanczos_steps) lanczos_steps[r] = ms;
         sum += q;
     }
     if (st == MM_OK) *logdet = sum / nprobes;
+    std::string msg = last_error_str();
+    mm_solver_destroy(sv);
+    if (st != MM_OK) set_error("%s", msg.c_str());
+    return st;
+}
+
+mm_status gp_lml(mm_plan plan, const double *y, double sigma2, const double *Zc, int64_t ldz, int32_t nprobes,
+                 int32_t maxit, double rtol, mm_lml_info *info, double *alpha, void *stream) {
+    clear_error();
+    MM_TRY(check_solve_args(plan, sigma2, rtol));
+    if (!y || !Zc || !info) {
+        set_error("y, Z and info must be non-NULL");
+        return MM_ERR_ARG;
+    }
+    if (nprobes < 1 || nprobes > 63 || maxit < 1 || ldz < plan->n) {
+        set_error("nprobes in [1, 63], maxit >= 1 and ldz >= n are required");
+        return MM_ERR_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = plan->n;
+    const int32_t *perm = static_cast<const int32_t *>(plan->perm.ptr);
+    mm_solver sv = nullptr;
+    MM_TRY(solver_new(plan, 1 + nprobes, 0, sigma2, rtol, nullptr, s,
+                      [&](double *B, int W) {
+                          hipLaunchKernelGGL(gather_lml_kernel, dim3(grid1(n * W)), dim3(BS), 0, s, y, Zc, ldz,
+                                             nprobes, perm, n, B, W);
+                      },
+                      &sv, maxit));
+    const int W = sv->W;
+    mm_status st = solver_run(sv, maxit, s);
+    int conv = 0, brk = 0;
+    double rel = 0.0;
+    mm_solve_info inf{};
+    if (st == MM_OK) st = solver_summary(sv, s, &conv, &brk, &rel, &inf);
+    std::vector<double> hsc((size_t)W * NS), tl((size_t)maxit * W * 2), hp((size_t)3 * NRED * W);
+    if (st == MM_OK && hipMemcpyAsync(hsc.data(), sv->desc.sc, hsc.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
+                           hipSuccess) {
+        set_error("HIP error reading the solver scalars");
+        st = MM_ERR_HIP;
+    }
+    if (st == MM_OK && hipMemcpyAsync(tl.data(), sv->desc.tlog, tl.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                      s) != hipSuccess) {
+        set_error("HIP error reading the Lanczos coefficients");
+        st = MM_ERR_HIP;
+    }
+    // the derivative product of [alpha, z_1 .. z_l] in the plan's work buffers
+    // (free again: the solve has finished), then the column dot products
+    if (st == MM_OK) st = ensure_work(plan, W, true);
+    if (st == MM_OK) {
+        double *V = static_cast<double *>(plan->vin.ptr);
+        double *D = static_cast<double *>(plan->yacc.ptr);
+        hipLaunchKernelGGL(lml_mix_kernel, dim3(grid1(n * W)), dim3(BS), 0, s, sv->desc.X, sv->desc.B, n, W, V);
+        st = sweep_all_dl(plan, V, D, W, rhs_block(plan->kernel, plan->d, W), s);
+        if (st == MM_OK) {
+            hipLaunchKernelGGL(lml_dots_kernel, dim3(NRED), dim3(BS), 0, s, sv->desc.X, sv->desc.B, D, n, W,
+                               sv->desc.part);
+            if (alpha)
+                hipLaunchKernelGGL(col_out_kernel, dim3(grid1(n)), dim3(BS), 0, s, sv->desc.X, perm, n, W, 1, alpha, n);
+            if (hipMemcpyAsync(hp.data(), sv->desc.part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
+                    hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                set_error("HIP error in the likelihood products");
+                st = MM_ERR_HIP;
+            }
+        }
+    }
+    if (st == MM_OK) {
+        // column sums of the row-block partials, in block order
+        std::vector<double> xb(W, 0.0), xd(W, 0.0), xx(W, 0.0);
+        for (int b = 0; b < NRED; ++b)
+            for (int r = 0; r < W; ++r) {
+                xb[r] += hp[(size_t)b * W + r];
+                xd[r] += hp[(size_t)(NRED + b) * W + r];
+                xx[r] += hp[(size_t)(2 * NRED + b) * W + r];
+            }
+        const double s2 = plan->kernel.outputscale2, ell = plan->kernel.lengthscale;
+        double ld = 0.0, tr_inv = 0.0, tr_dk = 0.0, tr_k = 0.0;
+        for (int r = 1; r <= nprobes && st == MM_OK; ++r) {
+            double q = 0.0;
+            int ms = 0;
+            const double *c = hsc.data() + (size_t)r * NS;
+            if (!column_logquad(c, tl, W, r, &q, &ms)) {
+                set_error("probe %d: the Lanczos matrix did not converge to a positive spectrum", r - 1);
+                st = MM_ERR_BREAKDOWN;
+                break;
+            }
+            ld += q;
+            tr_inv += xb[r];                               // z^T A^-1 z
+            tr_dk += xd[r];                                // (A^-1 z)^T (l dK/dl / s2) z
+            tr_k += c[4] * c[4] - sigma2 * xb[r];          // z^T A^-1 K z = |z|^2 - sigma2 z^T A^-1 z
+        }
+        if (st == MM_OK) {
+            const double inv_l = 1.0 / nprobes;
+            mm_lml_info o{};
+            o.quad = xb[0];
+            o.logdet = ld * inv_l;
+            o.lml = -0.5 * o.quad - 0.5 * o.logdet - 0.5 * (double)n * std::log(2.0 * M_PI);
+            o.trace_inv = tr_inv * inv_l;
+            o.trace_dk_dlengthscale = s2 / ell * tr_dk * inv_l;
+            o.dlml_dlengthscale = 0.5 * (s2 / ell) * xd[0] - 0.5 * o.trace_dk_dlengthscale;
+            o.dlml_dsigma2 = 0.5 * xx[0] - 0.5 * o.trace_inv;
+            // dK/d s2 = K / s2; alpha^T K alpha = y^T alpha - sigma2 alpha^T alpha
+            o.dlml_doutputscale2 = (0.5 * (xb[0] - sigma2 * xx[0]) - 0.5 * tr_k * inv_l) / s2;
+            o.relres_max = inf.relres_max;
+            o.iters = inf.iters;
+            o.converged = conv == 1 + nprobes ? 1 : 0;
+            *info = o;
+            st = status_of(conv, 1 + nprobes, brk, inf.iters, rel);
+        }
+    }
     std::string msg = last_error_str();
     mm_solver_destroy(sv);
     if (st != MM_OK) set_error("%s", msg.c_str());

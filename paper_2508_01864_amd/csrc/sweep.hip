@@ -1,1193 +1,12 @@
-// Divide-and-conquer weighted-ECDF sweeps: the hot loop of the exact Matern
-// kernel product.
-//
-// The paper writes the kernel sum over the 2^d sign orthants as weighted
-// empirical CDFs (eq. ECDFdelta; Prop. 1 for the L1 kernel, Prop. 2 for the
-// product kernel; the Matern instances in Section 2.3) and evaluates all of
-// them with a divide-and-conquer over presorted coordinates (Section 2.2).
-// Here every pair of distinct points meets in exactly one "pass": the level
-// of the x1-rank tree where they fall into different halves (and, in d = 3,
-// the level of the x2-rank tree inside that node).  Within a pass the points
-// of each node are listed in the order of the last coordinate, and the
-// orthant sums become bidirectional segmented scans:
-//   forward scan (<=)  gives the orthants with delta_last = +1,
-//   backward scan (>)  gives delta_last = -1,
-//   the source/target classes (which half of the x1 node, and in d = 3 of
-//   the x2 node) give the remaining signs.
-//
-// Numerics.  The paper's weights exp(+a delta.x) (eq. matern_weights) grow
-// without bound and their polynomial companions cancel.  Instead the scan
-// carries, per orthant class, the vector
-//     S_m = sum_i v_i (a r_i)^m / m! exp(-a r_i),   m = 0..P-1,
-// where r_i is the distance from source i to the current scan position.
-// Moving the position by Delta >= 0 is the linear map
-//     S_m <- exp(-a Delta) sum_{q<=m} (a Delta)^(m-q)/(m-q)! S_q,
-// whose coefficients lie in [0, 1]; the offsets of the other coordinates are
-// measured from the node's split point, so every factor is a bounded,
-// non-negative number and no sign cancellation occurs apart from v's own
-// signs.  The profile is recovered with the coefficients
-//     k(a r) = sum_m c_m (a r)^m / m! exp(-a r),
-//     c = [1] (nu=1/2), [1, 1] (nu=3/2), [1, 1, 2/3] (nu=5/2),
-// which restate Appendix C eq. matern_1_2 / 3_2 / 5_2 in this basis.
+// Host side of the sweeps: workspace sizing, pass tables, the per-product
+// launch sequence and the batched launches.  The kernels and their
+// configurations are in sweep_core.h.
 
-#include "mm_internal.h"
+#include "sweep_core.h"
 
-#include <cstdlib>
+#include <algorithm>
 
 namespace mm {
-namespace {
-
-constexpr int WG = 256;
-constexpr int WAVE = 64;
-constexpr int NWAVE = WG / WAVE;
-
-template <int B, int E>
-struct IPow { static constexpr int v = B * IPow<B, E - 1>::v; };
-template <int B>
-struct IPow<B, 0> { static constexpr int v = 1; };
-
-// c_m coefficients of the profile in the scaled-power basis.
-template <int P>
-__device__ __forceinline__ double coef(int m) {
-    if constexpr (P == 3) return m == 2 ? (2.0 / 3.0) : 1.0;
-    return 1.0;
-}
-
-// Source factor s_m(E, t) = E t^m / m!  (t = a w, E = exp(-t)).
-template <int P>
-__device__ __forceinline__ void src_vec(double E, double t, double (&sv)[P]) {
-    sv[0] = E;
-    if constexpr (P > 1) sv[1] = E * t;
-    if constexpr (P > 2) sv[2] = E * t * t * 0.5;
-}
-
-// Target factor g_q(E, t) = E sum_{m>=q} c_m t^(m-q)/(m-q)!: the profile
-// coefficients moved across an offset t (k(a(u+w)) = sum_q g_q(u) s_q(w)).
-template <int P>
-__device__ __forceinline__ void tgt_vec(double E, double t, double (&gv)[P]) {
-    if constexpr (P == 1) {
-        gv[0] = E;
-    } else if constexpr (P == 2) {
-        gv[0] = E * (1.0 + t);
-        gv[1] = E;
-    } else {
-        gv[0] = E * fma(t * (1.0 / 3.0), t, 1.0 + t);
-        gv[1] = E * fma(t, 2.0 / 3.0, 1.0);
-        gv[2] = E * (2.0 / 3.0);
-    }
-}
-
-// Flags stored with each staged element.
-constexpr int F_SIDE1 = 1;     // x1 half (d >= 2)
-constexpr int F_SIDE2 = 2;     // x2 half (d = 3)
-constexpr int F_SEGSTART = 4;  // first position of a segment
-constexpr int F_SEGEND = 8;    // last position of a segment (or of the array)
-constexpr int F_VALID = 16;    // position < n
-
-// One divide-and-conquer pass as the kernels see it (device table).
-struct PassDev {
-    const uint32_t *cf;   // canonical index | x1 half << 30 | x2 half << 31, in pass order
-    const double *xs;     // scan coordinate in pass order
-    const double *w1;     // x1 offset from the node's split point
-    const double *w2;     // d = 3: x2 offset from the x2 node's split point
-    int l1, l2;
-    int seg_log2;         // segments of 2^seg_log2 positions
-    int pad;
-};
-
-// Kernel arguments for one group of passes.
-struct SweepArgs {
-    const double *xc;      // d x n canonical coordinates
-    const PassDev *passes; // every pass of the plan
-    const int32_t *xt;     // indices of the passes whose segments span several tiles
-    const double *vin;     // n x W point-major canonical input
-    double *ypart;         // G slabs of n x W: one partial result per pass of the group
-    double *agg;           // tile aggregates [2 dirs][G][ntile][W][NSUB][NSLOT]
-    double *car;           // tile carries, same layout as agg
-    double *anc;           // tile anchors [2 dirs][G][ntile]
-    double *dec;           // decay from the previous tile's anchor (scan order) to the tile's, same layout
-    int64_t n;
-    int64_t ntile;
-    int W;                 // leading width of vin / ypart (columns)
-    int g0;                // first pass of the group
-    int k0;                // first entry of xt inside the group
-    int G;                 // passes in the group
-    int nslice;            // carry-scan slices (sub-sweep x class x row x column)
-    const int4 *segs;      // the plan's cross-tile segments (pass, first tile, end tile)
-    double a;
-};
-
-// Static configuration of a sweep instance.  A workgroup is one wave.  Its 64
-// lanes are WCOL right-hand-side columns times RUNS runs: lane (run, col)
-// scans the E consecutive positions run*E .. run*E+E-1 of a tile of
-// T = RUNS*E positions for one column.  The runs of a column are joined by a
-// lane scan of log2(RUNS) steps; tiles of a segment are joined through the
-// tile aggregates and the tile carry scan.  The tile's geometry is staged once
-// in LDS and read by every column (broadcast).
-template <int D_, int P_, bool PROD_, int WCOL_, int E_>
-struct Cfg {
-    static constexpr int D = D_;
-    static constexpr int P = P_;
-    static constexpr bool PROD = PROD_;
-    static constexpr int WCOL = WCOL_;
-    static constexpr int RUNS = WAVE / WCOL;
-    static constexpr int E = E_;
-    static constexpr int T = RUNS * E;                       // tile positions
-    static constexpr int NTH = PROD ? IPow<P, D - 1>::v : 1; // non-scan channel rows
-    // source classes (orthants of the non-scan coordinates) and how many
-    // sub-sweeps they are split over so that one state fits the register file
-    // (each sub-sweep repeats the scan for its classes)
-    static constexpr int NCLS_ALL = (D == 1) ? 1 : (D == 2 ? 2 : 4);
-    static constexpr int FULLSLOT = NCLS_ALL * NTH * P;
-    static constexpr int NSUB = (D == 3) ? (FULLSLOT <= 16 ? 1 : (FULLSLOT <= 32 ? 2 : 4)) : 1;
-    static constexpr int NCLS = NCLS_ALL / NSUB;
-    static constexpr int NSLOT = NCLS * NTH * P;             // doubles per state
-    static constexpr int G = 2 * (D - 1);                    // staged geometry doubles
-    // keep the targets' sums in registers over the sweep (runs of 4, small states)
-    static constexpr bool REGOUT = E <= 4 && E * NSLOT <= 64;
-    // elements per block of a run's loads.  Short runs take two blocks: with
-    // one, the block loop disappears, every load of the run is hoisted and
-    // the state spills (d = 3).
-    static constexpr int BLK = E <= 8 ? E / 2 : 8;
-};
-
-template <class C>
-struct State {
-    double s[C::NCLS][C::NTH][C::P];
-
-    __device__ __forceinline__ void zero() {
-#pragma unroll
-        for (int c = 0; c < C::NCLS; ++c)
-#pragma unroll
-            for (int h = 0; h < C::NTH; ++h)
-#pragma unroll
-                for (int m = 0; m < C::P; ++m) s[c][h][m] = 0.0;
-    }
-
-    // this <- M(E, t) this
-    __device__ __forceinline__ void shift(double E, double t) {
-        const double t2 = 0.5 * t * t;
-#pragma unroll
-        for (int c = 0; c < C::NCLS; ++c)
-#pragma unroll
-            for (int h = 0; h < C::NTH; ++h) {
-                if constexpr (C::P == 3) s[c][h][2] = E * fma(t2, s[c][h][0], fma(t, s[c][h][1], s[c][h][2]));
-                if constexpr (C::P >= 2) s[c][h][1] = E * fma(t, s[c][h][0], s[c][h][1]);
-                s[c][h][0] = E * s[c][h][0];
-            }
-    }
-
-    // this <- this + M(E, t) o
-    __device__ __forceinline__ void add_shifted(const State &o, double E, double t) {
-        const double t2 = 0.5 * t * t;
-#pragma unroll
-        for (int c = 0; c < C::NCLS; ++c)
-#pragma unroll
-            for (int h = 0; h < C::NTH; ++h) {
-                if constexpr (C::P == 3)
-                    s[c][h][2] = fma(E, fma(t2, o.s[c][h][0], fma(t, o.s[c][h][1], o.s[c][h][2])), s[c][h][2]);
-                if constexpr (C::P >= 2) s[c][h][1] = fma(E, fma(t, o.s[c][h][0], o.s[c][h][1]), s[c][h][1]);
-                s[c][h][0] = fma(E, o.s[c][h][0], s[c][h][0]);
-            }
-    }
-
-    __device__ __forceinline__ double *flat() { return &s[0][0][0]; }
-    __device__ __forceinline__ const double *flat() const { return &s[0][0][0]; }
-};
-
-// Geometry of one element (source and target vectors) derived from its staged offsets.
-//   product form: f[th] = prod_k s_{th_k}(w_k) (source, enters the m = 0 slot),
-//                 g[th] = prod_k g_{th_k}(w_k) (target, times the profile coefficients c_m);
-//   L1 form:      f[m] = s_m(W), g[m] = g_m(W) with W the summed offset.
-template <class C>
-struct ElemVec {
-    double f[C::PROD ? C::NTH : C::P];
-    double g[C::PROD ? C::NTH : C::P];
-};
-
-template <class C>
-__device__ __forceinline__ void elem_vectors(const double *geo, ElemVec<C> &ev) {
-    constexpr int P = C::P;
-    if constexpr (C::D == 1) {  // no other coordinate: unit source and target
-        static_assert(C::D != 1 || C::PROD, "d = 1 uses the product path");
-        ev.f[0] = 1.0;
-        ev.g[0] = 1.0;
-        return;
-    } else if constexpr (C::PROD) {
-        double sv[C::D - 1][P];
-        double gv[C::D - 1][P];
-#pragma unroll
-        for (int k = 0; k < C::D - 1; ++k) {
-            src_vec<P>(geo[2 * k], geo[2 * k + 1], sv[k]);
-            tgt_vec<P>(geo[2 * k], geo[2 * k + 1], gv[k]);
-        }
-        // row th holds channel (th mod P) of the first coordinate and
-        // (th div P) of the second
-#pragma unroll
-        for (int th = 0; th < C::NTH; ++th) {
-            double fs = 1.0, gs = 1.0;
-            int rem = th;
-#pragma unroll
-            for (int k = 0; k < C::D - 1; ++k) {
-                const int idx = rem % P;
-                rem /= P;
-                fs *= sv[k][idx];
-                gs *= gv[k][idx];
-            }
-            ev.f[th] = fs;
-            ev.g[th] = gs;
-        }
-    } else {
-        // L1: offsets add up; exp of the sum is the product of the exps.
-        double E = 1.0, t = 0.0;
-#pragma unroll
-        for (int k = 0; k < C::D - 1; ++k) {
-            E *= geo[2 * k];
-            t += geo[2 * k + 1];
-        }
-        src_vec<P>(E, t, ev.f);
-        tgt_vec<P>(E, t, ev.g);
-    }
-}
-
-// S[cls] += v * source vector.  The class is selected through the value
-// (v or 0) rather than a branch so the state stays in registers.
-template <class C>
-__device__ __forceinline__ void add_source(State<C> &S, int cls, const ElemVec<C> &ev, double v) {
-#pragma unroll
-    for (int c = 0; c < C::NCLS; ++c) {
-        const double vc = (c == cls) ? v : 0.0;
-#pragma unroll
-        for (int h = 0; h < C::NTH; ++h) {
-            if constexpr (C::PROD) {
-                S.s[c][h][0] = fma(ev.f[h], vc, S.s[c][h][0]);
-            } else {
-#pragma unroll
-                for (int m = 0; m < C::P; ++m) S.s[c][h][m] = fma(ev.f[m], vc, S.s[c][h][m]);
-            }
-        }
-    }
-}
-
-// target vector . S[cls]
-template <class C>
-__device__ __forceinline__ double read_target(const State<C> &S, int cls, const ElemVec<C> &ev) {
-    double out = 0.0;
-#pragma unroll
-    for (int c = 0; c < C::NCLS; ++c) {
-        double acc = 0.0;
-#pragma unroll
-        for (int h = 0; h < C::NTH; ++h) {
-            if constexpr (C::PROD) {
-                double row = S.s[c][h][0];
-#pragma unroll
-                for (int m = 1; m < C::P; ++m) row = fma(coef<C::P>(m), S.s[c][h][m], row);
-                acc = fma(ev.g[h], row, acc);
-            } else {
-#pragma unroll
-                for (int m = 0; m < C::P; ++m) acc = fma(ev.g[m], S.s[c][h][m], acc);
-            }
-        }
-        out += (c == cls) ? acc : 0.0;
-    }
-    return out;
-}
-
-// Source / target class of an element in sub-sweep `hh`.  d = 2: the x1 half
-// (sources of one half feed targets of the other).  d = 3: the (x1, x2)
-// halves; a source class feeds the targets in the opposite halves of both.
-// With NSUB > 1 each sub-sweep carries only part of the classes.
-template <class C>
-__device__ __forceinline__ void classes(int flags, int hh, int &scls, int &tcls) {
-    if constexpr (C::D == 1) {
-        scls = 0;
-        tcls = 0;
-    } else if constexpr (C::D == 2) {
-        const int s1 = flags & F_SIDE1;
-        scls = s1;
-        tcls = 1 - s1;
-    } else {
-        const int s1 = flags & F_SIDE1;
-        const int s2 = (flags & F_SIDE2) ? 1 : 0;
-        const int full = s1 * 2 + s2;
-        if constexpr (C::NSUB == 1) {
-            scls = full;
-            tcls = 3 - full;
-        } else if constexpr (C::NSUB == 2) {
-            scls = (s1 == hh) ? s2 : -1;
-            tcls = (s1 == 1 - hh) ? 1 - s2 : -1;
-        } else {
-            scls = (full == hh) ? 0 : -1;
-            tcls = (3 - full == hh) ? 0 : -1;
-        }
-    }
-    if (!(flags & F_VALID)) {
-        scls = -1;
-        tcls = -1;
-    }
-}
-
-// Staged tile in LDS, stored [element of the run][run]: lanes of different
-// runs read different banks, lanes of the same run (different columns) read
-// the same address (broadcast).  Local position j lives at slot(j).
-template <class C>
-struct Smem {
-    int32_t c[C::T];
-    int32_t flags[C::T];
-    double xs[C::T];
-    double est[C::T + 1];  // decay from the previous position; [T]: into the next tile's first
-    double xedge[2];       // scan coordinate before the tile (p0 - 1) and after it (p0 + T)
-    double geo[C::G > 0 ? C::G : 1][C::T];
-};
-
-template <class C>
-__device__ __forceinline__ int slot(int j) {
-    return (j % C::E) * C::RUNS + j / C::E;
-}
-
-// Scan coordinate of pass position p (0 <= p < n).
-template <class C>
-__device__ __forceinline__ double scan_coord(const SweepArgs &A, const PassDev &ps, int64_t p) {
-    if constexpr (C::D == 1) return A.xc[p];
-    else return ps.xs[p];
-}
-
-// Stage the tile's positions: indices, flags, scan coordinate, offsets and
-// the decay between consecutive positions.
-template <class C>
-__device__ __forceinline__ void stage_tile(const SweepArgs &A, const PassDev &ps, Smem<C> &sm,
-                                           int64_t p0) {
-    const int64_t n = A.n;
-    const int64_t segmask = (int64_t(1) << ps.seg_log2) - 1;
-    for (int j = threadIdx.x; j < C::T; j += WAVE) {
-        const int64_t p = p0 + j;
-        const int64_t pc = p < n ? p : n - 1;
-        int flags = p < n ? F_VALID : 0;
-        if (p < n && (p & segmask) == 0) flags |= F_SEGSTART;
-        if (p >= n - 1 || ((p + 1) & segmask) == 0) flags |= F_SEGEND;
-        const int sj = slot<C>(j);
-        int64_t c;
-        if constexpr (C::D == 1) {
-            c = pc;
-            sm.xs[sj] = A.xc[c];
-        } else {
-            // sequential reads of the pass's stored geometry
-            const uint32_t cf = ps.cf[pc];
-            c = (int64_t)(cf & 0x3fffffffu);
-            flags |= (cf >> 30) & 1u ? F_SIDE1 : 0;
-            const double t1 = A.a * ps.w1[pc];
-            sm.geo[0][sj] = exp(-t1);
-            sm.geo[1][sj] = t1;
-            if constexpr (C::D == 3) {
-                flags |= (cf >> 31) ? F_SIDE2 : 0;
-                const double t2 = A.a * ps.w2[pc];
-                sm.geo[2][sj] = exp(-t2);
-                sm.geo[3][sj] = t2;
-            }
-            sm.xs[sj] = ps.xs[pc];
-        }
-        sm.c[sj] = (int32_t)c;
-        sm.flags[sj] = flags;
-    }
-    __syncthreads();
-    // decay exp(-a (x_j - x_{j-1})) into every position from its predecessor,
-    // including across the tile's edges (position p0 from p0 - 1, and the next
-    // tile's first position p0 + T from the tile's last); 1 at segment starts
-    for (int j = threadIdx.x; j <= C::T; j += WAVE) {
-        const int64_t p = p0 + j;
-        double e = 1.0;
-        if (p < n && p > 0 && (p & segmask) != 0) {
-            double xcur, xprev;
-            if (j > 0 && j < C::T) {
-                xcur = sm.xs[slot<C>(j)];
-                xprev = sm.xs[slot<C>(j - 1)];
-            } else if (j == 0) {
-                xcur = sm.xs[slot<C>(0)];
-                xprev = scan_coord<C>(A, ps, p - 1);
-                sm.xedge[0] = xprev;
-            } else {
-                xcur = scan_coord<C>(A, ps, p);
-                xprev = sm.xs[slot<C>(C::T - 1)];
-                sm.xedge[1] = xcur;
-            }
-            e = exp(-A.a * (xcur - xprev));
-        } else if (j == 0) {
-            sm.xedge[0] = sm.xs[slot<C>(0)];
-        } else if (j == C::T) {
-            sm.xedge[1] = sm.xs[slot<C>(C::T - 1)];
-        }
-        sm.est[j < C::T ? slot<C>(j) : C::T] = e;
-    }
-    __syncthreads();
-}
-
-template <class C>
-__device__ __forceinline__ void load_geo(const Smem<C> &sm, int sj, double (&geo)[C::G > 0 ? C::G : 1]) {
-#pragma unroll
-    for (int k = 0; k < C::G; ++k) geo[k] = sm.geo[k][sj];
-}
-
-template <class C>
-__device__ __forceinline__ int64_t agg_index(const SweepArgs &A, int dir, int pl, int64_t tile, int col,
-                                             int hh) {
-    return (((((int64_t)dir * A.G + pl) * A.ntile + tile) * A.W + col) * C::NSUB + hh) * C::NSLOT;
-}
-
-// One step of the lane scan over runs: F <- F + M(E, t) F(partner), the
-// partner o runs away in the scan direction (the same column's lane o*WCOL
-// lanes up or down).  (t, E) is the transfer from the partner's anchor to this
-// lane's anchor -- the distance, times a, spanned by the runs this lane
-// already covers, and its decay -- so no exponential is evaluated here; the
-// coverage then grows by the partner's.
-template <class C, bool UP>
-__device__ __forceinline__ void scan_step(State<C> &F, double &t, double &E, int o, bool ok) {
-    const int dl = o * C::WCOL;
-    const double tp = UP ? __shfl_up(t, dl, WAVE) : __shfl_down(t, dl, WAVE);
-    const double Ep = UP ? __shfl_up(E, dl, WAVE) : __shfl_down(E, dl, WAVE);
-    const double t2 = 0.5 * t * t;
-#pragma unroll
-    for (int c = 0; c < C::NCLS; ++c)
-#pragma unroll
-        for (int h = 0; h < C::NTH; ++h) {
-            double q[C::P];
-#pragma unroll
-            for (int m = 0; m < C::P; ++m)
-                q[m] = UP ? __shfl_up(F.s[c][h][m], dl, WAVE) : __shfl_down(F.s[c][h][m], dl, WAVE);
-            if (ok) {
-                if constexpr (C::P == 3) F.s[c][h][2] = fma(E, fma(t2, q[0], fma(t, q[1], q[2])), F.s[c][h][2]);
-                if constexpr (C::P >= 2) F.s[c][h][1] = fma(E, fma(t, q[0], q[1]), F.s[c][h][1]);
-                F.s[c][h][0] = fma(E, q[0], F.s[c][h][0]);
-            }
-        }
-    if (ok) {
-        t += tp;
-        E *= Ep;
-    }
-}
-
-// Process element e of the lane's run in a scan step: move the state to the
-// element (or reset at a segment boundary), read the target value, add the
-// source.  Returns the target value.
-template <class C, int DIR, bool TARGET>
-__device__ __forceinline__ double scan_elem(const Smem<C> &sm, State<C> &S, int e, int i, int run, int hh,
-                                            double &prevx, double v, double a) {
-    constexpr int BOUND = DIR == 0 ? F_SEGSTART : F_SEGEND;
-    const int sj = e * C::RUNS + run;
-    const int fl = sm.flags[sj];
-    int sc, tc;
-    classes<C>(fl, hh, sc, tc);
-    const double xj = sm.xs[sj];
-    if (fl & BOUND) {
-        if constexpr (TARGET) S.zero();
-    } else {
-        const double t = a * (DIR == 0 ? xj - prevx : prevx - xj);
-        // the previous position in the scan direction is the anchor of any carry,
-        // so the decay is the staged one between neighbours
-        int ej;
-        if constexpr (DIR == 0) {
-            ej = sj;
-        } else {
-            ej = (e + 1 < C::E) ? sj + C::RUNS : (run + 1 < C::RUNS ? run + 1 : C::T);
-        }
-        S.shift(sm.est[ej], t);
-    }
-    prevx = xj;
-    double geo[C::G > 0 ? C::G : 1];
-    load_geo<C>(sm, sj, geo);
-    ElemVec<C> ev;
-    elem_vectors<C>(geo, ev);
-    double out = 0.0;
-    if constexpr (TARGET) out = read_target<C>(S, tc, ev);
-    add_source<C>(S, sc, ev, v);
-    return out;
-}
-
-// One scan direction over this lane's run, with every carry.
-// DIR 0: forward (increasing positions; sources at or before the target in
-//        the last coordinate: delta_last = +1);
-// DIR 1: backward (decreasing positions; sources strictly after: delta_last = -1).
-// MODE 0: target values go to outv (short runs) or to the pass's slab (long
-//         runs: the backward direction, run first, stores; the forward adds);
-// MODE 1: the tile's total is written to the aggregates.
-template <class C, int MODE, int DIR>
-__device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev &ps, const Smem<C> &sm,
-                                              int hh, int64_t tile, int pl, int col, int run,
-                                              const double (&vr)[C::REGOUT ? C::E : 1],
-                                              double (&outv)[C::REGOUT ? C::E : 1], double *slab) {
-    const int seg = 1 << (ps.seg_log2 < 30 ? ps.seg_log2 : 30);
-    // runs per segment group (1 when segments fit in a run)
-    const int Gr = seg <= C::E ? 1 : (seg >= C::T ? C::RUNS : seg / C::E);
-    const int lig = run & (Gr - 1);
-    const double a = A.a;
-    const int ebeg = DIR == 0 ? 0 : C::E - 1;
-    const int eend = DIR == 0 ? C::E - 1 : 0;
-    const double xbeg = sm.xs[ebeg * C::RUNS + run];
-    const double xend = sm.xs[eend * C::RUNS + run];
-    const double *vcol = A.vin + col;
-
-    State<C> Ex;  // carry entering the run, anchored at xex
-    Ex.zero();
-    double xex = xbeg;
-
-    if (Gr > 1) {
-        // ---- run aggregate (anchored at xend)
-        State<C> F;
-        F.zero();
-        double px = xbeg;
-        if constexpr (C::REGOUT) {
-#pragma unroll
-            for (int i = 0; i < C::E; ++i) {
-                const int e = DIR == 0 ? i : C::E - 1 - i;
-                scan_elem<C, DIR, false>(sm, F, e, i, run, hh, px, vr[e], a);
-            }
-        } else {
-#pragma unroll 1
-            for (int b = 0; b < C::E; b += C::BLK) {
-                double vb[C::BLK];
-#pragma unroll
-                for (int k = 0; k < C::BLK; ++k) {
-                    // staged indices are clamped to valid points: load unconditionally
-                    const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
-                    const int sj = e * C::RUNS + run;
-                    const double ld = vcol[(int64_t)sm.c[sj] * A.W];
-                    vb[k] = (sm.flags[sj] & F_VALID) ? ld : 0.0;
-                }
-#pragma unroll
-                for (int k = 0; k < C::BLK; ++k) {
-                    const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
-                    scan_elem<C, DIR, false>(sm, F, e, b + k, run, hh, px, vb[k], a);
-                }
-            }
-        }
-        State<C> Frun;
-        if constexpr (MODE == 1) Frun = F;
-        // ---- inclusive scan over the runs of this column.  Initial transfer: from
-        // the previous run's anchor to this run's (none for a group's first run).
-        double tr = 0.0, Er = 1.0;
-        {
-            const double xo = DIR == 0 ? __shfl_up(xend, C::WCOL, WAVE) : __shfl_down(xend, C::WCOL, WAVE);
-            const bool has = DIR == 0 ? (lig > 0) : (lig < Gr - 1);
-            if (has) {
-                tr = a * (DIR == 0 ? xend - xo : xo - xend);
-                Er = exp(-tr);
-            }
-        }
-#pragma unroll 1
-        for (int o = 1; o < Gr; o <<= 1) {
-            const bool ok = DIR == 0 ? (lig >= o) : (lig + o < Gr);
-            scan_step<C, DIR == 0>(F, tr, Er, o, ok);
-        }
-        // exclusive value
-        {
-            const int dl = C::WCOL;
-            const double xp = DIR == 0 ? __shfl_up(xend, dl, WAVE) : __shfl_down(xend, dl, WAVE);
-            const bool has = DIR == 0 ? (lig > 0) : (lig < Gr - 1);
-#pragma unroll
-            for (int k = 0; k < C::NSLOT; ++k) {
-                const double q = DIR == 0 ? __shfl_up(F.flat()[k], dl, WAVE) : __shfl_down(F.flat()[k], dl, WAVE);
-                Ex.flat()[k] = has ? q : 0.0;
-            }
-            if (has) xex = xp;
-        }
-        if constexpr (MODE == 1) {
-            // tile total: inclusive value of the run that ends the tile in this direction
-            if (run == (DIR == 0 ? C::RUNS - 1 : 0)) {
-                State<C> tot = Ex;
-                const double t = a * (DIR == 0 ? xend - xex : xex - xend);
-                tot.shift(exp(-t), t);
-                tot.add_shifted(Frun, 1.0, 0.0);
-                double *dst = A.agg + agg_index<C>(A, DIR, pl, tile, col, hh);
-#pragma unroll
-                for (int k = 0; k < C::NSLOT; ++k) dst[k] = tot.flat()[k];
-                if (col == 0 && hh == 0) {
-                    const int64_t ai = ((int64_t)DIR * A.G + pl) * A.ntile + tile;
-                    A.anc[ai] = xend;
-                    // decay across the tile from the previous tile's anchor; 1 for the
-                    // segment's first tile in the scan direction (no predecessor)
-                    const int64_t tps = seg / C::T;
-                    const bool first = DIR == 0 ? (tile % tps) == 0 : (((tile + 1) % tps) == 0 || tile + 1 == A.ntile);
-                    const double xo = sm.xedge[DIR == 0 ? 0 : 1];
-                    A.dec[ai] = first ? 1.0 : exp(-a * (DIR == 0 ? xend - xo : xo - xend));
-                }
-            }
-            return;
-        }
-        // ---- carry from the other tiles of the segment (tile carry scan)
-        if (seg > C::T && A.ntile > 1) {
-            const int64_t tps = seg / C::T;
-            const bool has_nb = DIR == 0 ? (tile % tps) != 0 : (((tile + 1) % tps) != 0 && tile + 1 < A.ntile);
-            if (has_nb) {
-                State<C> cf;
-                const double *src = A.car + agg_index<C>(A, DIR, pl, tile, col, hh);
-#pragma unroll
-                for (int k = 0; k < C::NSLOT; ++k) cf.flat()[k] = src[k];
-                const double anc = A.anc[((int64_t)DIR * A.G + pl) * A.ntile + (DIR == 0 ? tile - 1 : tile + 1)];
-                if (run == (DIR == 0 ? 0 : C::RUNS - 1)) xex = anc;
-                const double t = a * (DIR == 0 ? xex - anc : anc - xex);
-                Ex.add_shifted(cf, exp(-t), t);
-            }
-        }
-    }
-    if constexpr (MODE == 0) {
-        // ---- the scan proper: targets read the state, then sources enter it
-        State<C> S = Ex;
-        double px = xex;
-        if constexpr (C::REGOUT) {
-#pragma unroll
-            for (int i = 0; i < C::E; ++i) {
-                const int e = DIR == 0 ? i : C::E - 1 - i;
-                outv[e] += scan_elem<C, DIR, true>(sm, S, e, i, run, hh, px, vr[e], a);
-            }
-        } else {
-#pragma unroll 1
-            for (int b = 0; b < C::E; b += C::BLK) {
-                double vb[C::BLK], ob[C::BLK];
-                int64_t addr[C::BLK];
-#pragma unroll
-                for (int k = 0; k < C::BLK; ++k) {
-                    const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
-                    const int sj = e * C::RUNS + run;
-                    const bool valid = sm.flags[sj] & F_VALID;
-                    const int64_t ad = (int64_t)sm.c[sj] * A.W + col;  // clamped: always in range
-                    addr[k] = valid ? ad : -1;
-                    const double lv = A.vin[ad];
-                    vb[k] = valid ? lv : 0.0;
-                    // the slab already holds this element's earlier values unless this is
-                    // the first write of the pass (backward direction of sub-sweep 0)
-                    if (DIR == 0 || hh > 0) {
-                        const double lo = slab[ad];
-                        ob[k] = valid ? lo : 0.0;
-                    } else {
-                        ob[k] = 0.0;
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < C::BLK; ++k) {
-                    const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
-                    const double val = scan_elem<C, DIR, true>(sm, S, e, b + k, run, hh, px, vb[k], a);
-                    if (addr[k] >= 0) slab[addr[k]] = ob[k] + val;
-                }
-            }
-        }
-    }
-}
-
-// MODE 0: one (pass, tile, column block) of the group; targets' sums go to
-// the pass's slab.  MODE 1: tile aggregates of the passes whose segments span
-// several tiles.
-template <class C, int MODE>
-__device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, int64_t bx, int by) {
-    int pass;
-    int64_t tile;
-    if constexpr (MODE == 0) {
-        pass = A.g0 + (int)(bx / A.ntile);
-        tile = bx % A.ntile;
-    } else {
-        pass = A.xt[A.k0 + (int)(bx / A.ntile)];
-        tile = bx % A.ntile;
-    }
-    const int pl = pass - A.g0;
-    const PassDev ps = A.passes[pass];
-    const int lane = threadIdx.x;
-    const int col = by * C::WCOL + lane % C::WCOL;
-    const int run = lane / C::WCOL;
-    const int64_t p0 = tile * C::T;
-    stage_tile<C>(A, ps, sm, p0);
-    double *slab = A.ypart + (int64_t)pl * A.n * A.W;
-
-    double vr[C::REGOUT ? C::E : 1], outv[C::REGOUT ? C::E : 1];
-    if constexpr (C::REGOUT) {
-#pragma unroll
-        for (int e = 0; e < C::E; ++e) {
-            const int sj = e * C::RUNS + run;
-            const double ld = A.vin[(int64_t)sm.c[sj] * A.W + col];  // clamped index
-            vr[e] = (sm.flags[sj] & F_VALID) ? ld : 0.0;
-            outv[e] = 0.0;
-        }
-    }
-
-#pragma unroll 1
-    for (int hh = 0; hh < C::NSUB; ++hh) {
-        run_direction<C, MODE, 1>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab);
-        run_direction<C, MODE, 0>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab);
-    }
-
-    if constexpr (MODE == 0 && C::REGOUT) {
-#pragma unroll
-        for (int e = 0; e < C::E; ++e) {
-            const int sj = e * C::RUNS + run;
-            if (sm.flags[sj] & F_VALID) slab[(int64_t)sm.c[sj] * A.W + col] = outv[e];
-        }
-    }
-}
-
-template <class C, int MODE>
-__global__ __launch_bounds__(WAVE) void sweep_kernel(SweepArgs A) {
-    __shared__ Smem<C> sm;
-    sweep_body<C, MODE>(A, sm, blockIdx.x, blockIdx.y);
-}
-
-// Batched: every item (problem, block x, block y) of a table runs the same body
-// with its problem's arguments; a fixed grid walks the table (persistent).
-template <class C, int MODE>
-__global__ __launch_bounds__(WAVE) void sweep_batch_kernel(const SweepArgs *descs, const int4 *items, int nitems) {
-    __shared__ Smem<C> sm;
-    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
-        const int4 it = items[i];
-        const SweepArgs A = descs[it.x];
-        sweep_body<C, MODE>(A, sm, it.y, it.z);
-        __syncthreads();
-    }
-}
-
-// Exclusive scans of the tile aggregates over the tiles of each segment, in
-// both directions: car[t] = the sum over the segment's tiles before t
-// (forward) or after t (backward) of their aggregates, moved to the anchor
-// next to t.  One wave per (segment, slice): a slice is one (sub-sweep,
-// class, channel row, column) P-vector.  Lanes take chunks of consecutive
-// tiles, scan them serially, join the chunks with a lane scan and write the
-// tiles' exclusive values.  `segs` lists (pass, first tile, end tile) of the
-// segments that span several tiles; blockIdx.x indexes them.
-// Segments of at most CARRY_SMALL tiles: one thread per slice scans the
-// segment's tiles serially (loads issued in blocks of 8 ahead of the updates).
-constexpr int CARRY_SMALL = 16;
-
-template <class C>
-__device__ __forceinline__ void carry_small(const SweepArgs &A, int pass, int64_t t0, int64_t t1, int by) {
-    const int sl = by * 256 + (int)threadIdx.x;
-    if (sl >= A.nslice) return;
-    const int pl = pass - A.g0;
-    const int colw = sl % C::WCOL;
-    const int rowcb = sl / C::WCOL;
-    constexpr int ROWS = C::NSUB * C::NCLS * C::NTH;
-    const int row = rowcb % ROWS;
-    const int cb = rowcb / ROWS;
-    const int hh = row / (C::NCLS * C::NTH);
-    const int ch = row % (C::NCLS * C::NTH);
-    const int col = cb * C::WCOL + colw;
-    const double a = A.a;
-    const int64_t nt = t1 - t0;
-#pragma unroll 1
-    for (int dir = 0; dir < 2; ++dir) {
-        const int64_t base = ((int64_t)dir * A.G + pl) * A.ntile;
-        const double *anc = A.anc + base;
-        const double *dec = A.dec + base;
-        auto off = [&](int64_t t) -> int64_t { return agg_index<C>(A, dir, pl, t, col, hh) + (int64_t)ch * C::P; };
-        double ex[C::P];
-#pragma unroll
-        for (int m = 0; m < C::P; ++m) ex[m] = 0.0;
-        double xw = 0.0;
-#pragma unroll 1
-        for (int64_t b = 0; b < nt; b += 8) {
-            double xb[8], db[8], gb[8][C::P];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const bool in = b + k < nt;
-                const int64_t t = dir == 0 ? t0 + (in ? b + k : 0) : t1 - 1 - (in ? b + k : 0);
-                xb[k] = anc[t];
-                db[k] = dec[t];
-#pragma unroll
-                for (int m = 0; m < C::P; ++m) gb[k][m] = in ? A.agg[off(t) + m] : 0.0;
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (b + k >= nt) break;
-                const int64_t t = dir == 0 ? t0 + b + k : t1 - 1 - b - k;
-                if (b + k > 0) {
-#pragma unroll
-                    for (int m = 0; m < C::P; ++m) A.car[off(t) + m] = ex[m];
-                    const double tt = a * (dir == 0 ? xb[k] - xw : xw - xb[k]);
-                    const double E = db[k];
-                    if constexpr (C::P == 3) ex[2] = E * fma(0.5 * tt * tt, ex[0], fma(tt, ex[1], ex[2]));
-                    if constexpr (C::P >= 2) ex[1] = E * fma(tt, ex[0], ex[1]);
-                    ex[0] = E * ex[0];
-                }
-#pragma unroll
-                for (int m = 0; m < C::P; ++m) ex[m] += gb[k][m];
-                xw = xb[k];
-            }
-        }
-    }
-}
-
-template <class C>
-__device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int by) {
-    const int4 sg = A.segs[bx];
-    const int nslice = A.nslice;
-    const int pass = sg.x;
-    const int64_t t0 = sg.y, t1 = sg.z;
-    if (t1 - t0 <= CARRY_SMALL) {
-        carry_small<C>(A, pass, t0, t1, by);
-        return;
-    }
-    const int pl = pass - A.g0;
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int sl = by * 4 + threadIdx.x / WAVE;
-    if (sl >= nslice) return;
-    const int colw = sl % C::WCOL;
-    const int rowcb = sl / C::WCOL;  // (column block, row)
-    constexpr int ROWS = C::NSUB * C::NCLS * C::NTH;
-    const int row = rowcb % ROWS;
-    const int cb = rowcb / ROWS;
-    const int hh = row / (C::NCLS * C::NTH);
-    const int ch = row % (C::NCLS * C::NTH);
-    const int col = cb * C::WCOL + colw;
-    const double a = A.a;
-    const int64_t nt = t1 - t0;
-    const int64_t chunk = (nt + WAVE - 1) / WAVE;
-    const int64_t lo = t0 + lane * chunk;
-    const int64_t hi = lo + chunk < t1 ? lo + chunk : t1;
-    const int nact = (int)((nt + chunk - 1) / chunk);  // lanes holding tiles
-    const bool active = lane < nact;
-    const int64_t cnt = active ? hi - lo : 0;
-#pragma unroll 1
-    for (int dir = 0; dir < 2; ++dir) {
-        const int64_t base = ((int64_t)dir * A.G + pl) * A.ntile;
-        const double *anc = A.anc + base;
-        const double *dec = A.dec + base;
-        auto off = [&](int64_t t) -> int64_t { return agg_index<C>(A, dir, pl, t, col, hh) + (int64_t)ch * C::P; };
-        // the chunk's tiles in the scan direction: cb0, cb0 + step, ...
-        const int64_t cb0 = dir == 0 ? lo : hi - 1;
-        const int64_t step = dir == 0 ? 1 : -1;
-        // the segment's first tile in the scan direction: in lane 0 (forward) or in the
-        // last active lane (backward), always as the chunk's first tile
-        const bool seg_first = dir == 0 ? lane == 0 : lane == nact - 1;
-        // ---- chunk aggregate, anchored at the chunk's last tile, and the chunk's
-        // transfer (distance x a and decay) from the previous chunk's last anchor.
-        // The first block's anchors, aggregates and decays stay in registers.
-        double acc[C::P];
-#pragma unroll
-        for (int m = 0; m < C::P; ++m) acc[m] = 0.0;
-        double xs8[8], g8[8][C::P], e8[8], tt8[8];
-        double Ech = 1.0;
-        double xprev = active ? anc[cb0] : anc[t1 - 1];
-        const double xfirst = xprev;
-        for (int64_t b = 0; b < cnt; b += 8) {
-            double xb[8], db[8], gb[8][C::P];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {  // loads first, then the dependent updates
-                const bool in = b + k < cnt;
-                const int64_t t = in ? cb0 + step * (b + k) : cb0;
-                xb[k] = anc[t];
-                db[k] = dec[t];
-#pragma unroll
-                for (int m = 0; m < C::P; ++m) gb[k][m] = in ? A.agg[off(t) + m] : 0.0;
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (b + k >= cnt) break;
-                const double x = xb[k];
-                const double tt = a * (dir == 0 ? x - xprev : xprev - x);
-                const double E = (b + k == 0) ? 1.0 : db[k];  // exp(-tt), stored per tile
-                Ech *= db[k];
-                if constexpr (C::P == 3) acc[2] = E * fma(0.5 * tt * tt, acc[0], fma(tt, acc[1], acc[2]));
-                if constexpr (C::P >= 2) acc[1] = E * fma(tt, acc[0], acc[1]);
-                acc[0] = E * acc[0];
-#pragma unroll
-                for (int m = 0; m < C::P; ++m) acc[m] += gb[k][m];
-                xprev = x;
-                if (b == 0) {
-                    xs8[k] = x;
-                    e8[k] = db[k];
-                    tt8[k] = tt;
-#pragma unroll
-                    for (int m = 0; m < C::P; ++m) g8[k][m] = gb[k][m];
-                }
-            }
-        }
-        // inactive lanes hold a zero state and an identity transfer
-        const double xa = xprev;
-        const double xbefore = dir == 0 ? __shfl_up(xa, 1, WAVE) : __shfl_down(xa, 1, WAVE);
-        double tr = 0.0, Er = 1.0;
-        if (active && !seg_first) {
-            tr = a * (dir == 0 ? xa - xbefore : xbefore - xa);
-            Er = Ech;
-        }
-        (void)xfirst;
-        // ---- inclusive lane scan toward the direction, transfers carried along
-        for (int o = 1; o < WAVE; o <<= 1) {
-            const double tp = dir == 0 ? __shfl_up(tr, o, WAVE) : __shfl_down(tr, o, WAVE);
-            const double Ep = dir == 0 ? __shfl_up(Er, o, WAVE) : __shfl_down(Er, o, WAVE);
-            double q[C::P];
-#pragma unroll
-            for (int m = 0; m < C::P; ++m) q[m] = dir == 0 ? __shfl_up(acc[m], o, WAVE) : __shfl_down(acc[m], o, WAVE);
-            const bool ok = dir == 0 ? (lane >= o) : (lane + o < WAVE);
-            if (ok) {
-                if constexpr (C::P == 3) acc[2] = fma(Er, fma(0.5 * tr * tr, q[0], fma(tr, q[1], q[2])), acc[2]);
-                if constexpr (C::P >= 2) acc[1] = fma(Er, fma(tr, q[0], q[1]), acc[1]);
-                acc[0] = fma(Er, q[0], acc[0]);
-                tr += tp;
-                Er *= Ep;
-            }
-        }
-        // ---- exclusive value entering the chunk, anchored at the previous chunk's last tile
-        double ex[C::P];
-        {
-            const bool has = dir == 0 ? (lane > 0) : (lane < WAVE - 1);
-#pragma unroll
-            for (int m = 0; m < C::P; ++m) {
-                const double q = dir == 0 ? __shfl_up(acc[m], 1, WAVE) : __shfl_down(acc[m], 1, WAVE);
-                ex[m] = has ? q : 0.0;
-            }
-        }
-        if (!active) continue;
-        // ---- walk the chunk: each tile's carry is the running value anchored at the
-        // previous tile's anchor; then the tile is included
-        auto include = [&](double E, double tt, const double *g) {
-            if constexpr (C::P == 3) ex[2] = E * fma(0.5 * tt * tt, ex[0], fma(tt, ex[1], ex[2]));
-            if constexpr (C::P >= 2) ex[1] = E * fma(tt, ex[0], ex[1]);
-            ex[0] = E * ex[0];
-#pragma unroll
-            for (int m = 0; m < C::P; ++m) ex[m] += g[m];
-        };
-        if (cnt <= 8) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (k >= cnt) break;
-                const int64_t t = cb0 + step * k;
-                if (k == 0 && seg_first) {
-#pragma unroll
-                    for (int m = 0; m < C::P; ++m) ex[m] += g8[0][m];
-                } else {
-#pragma unroll
-                    for (int m = 0; m < C::P; ++m) A.car[off(t) + m] = ex[m];
-                    const double tt = k == 0 ? a * (dir == 0 ? xs8[0] - xbefore : xbefore - xs8[0]) : tt8[k];
-                    include(e8[k], tt, g8[k]);
-                }
-            }
-        } else {
-            double xw = xbefore;
-            for (int64_t b = 0; b < cnt; b += 8) {
-                double xb[8], db[8], gb[8][C::P];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const bool in = b + k < cnt;
-                    const int64_t t = in ? cb0 + step * (b + k) : cb0;
-                    xb[k] = anc[t];
-                    db[k] = dec[t];
-#pragma unroll
-                    for (int m = 0; m < C::P; ++m) gb[k][m] = in ? A.agg[off(t) + m] : 0.0;
-                }
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    if (b + k >= cnt) break;
-                    const int64_t t = cb0 + step * (b + k);
-                    if (b + k == 0 && seg_first) {
-#pragma unroll
-                        for (int m = 0; m < C::P; ++m) ex[m] += gb[k][m];
-                    } else {
-#pragma unroll
-                        for (int m = 0; m < C::P; ++m) A.car[off(t) + m] = ex[m];
-                        const double tt = a * (dir == 0 ? xb[k] - xw : xw - xb[k]);
-                        include(db[k], tt, gb[k]);
-                    }
-                    xw = xb[k];
-                }
-            }
-        }
-    }
-}
-
-template <class C>
-__global__ __launch_bounds__(256) void carry_kernel(SweepArgs A) {
-    carry_body<C>(A, blockIdx.x, blockIdx.y);
-}
-
-// Batched carry scans: items (problem, segment, slice group).
-template <class C>
-__global__ __launch_bounds__(256) void carry_batch_kernel(const SweepArgs *descs, const int4 *items, int nitems) {
-    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
-        const int4 it = items[i];
-        const SweepArgs A = descs[it.x];
-        carry_body<C>(A, it.y, it.z);
-    }
-}
-
-// yacc = [yacc +] sum of the group's slabs, in pass order.
-__global__ void accum_kernel(const double *ypart, int G, int64_t len, double *yacc, int first) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        double s = first ? 0.0 : yacc[e];
-        for (int g = 0; g < G; ++g) s += ypart[(int64_t)g * len + e];
-        yacc[e] = s;
-    }
-}
-
-__global__ void zero_kernel(double *p, int64_t len) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
-         e += (int64_t)gridDim.x * blockDim.x)
-        p[e] = 0.0;
-}
-
-// ---------------------------------------------------------------------------
-// Host-side dispatch.
-// ---------------------------------------------------------------------------
-constexpr int BS1 = 256;
-
-inline unsigned grid_1d(int64_t n) {
-    int64_t g = (n + BS1 - 1) / BS1;
-    if (g > 65535 * 8) g = 65535 * 8;
-    return (unsigned)(g < 1 ? 1 : g);
-}
-
-inline int tile_index(int T) { return T >= 1024 ? 3 : (T >= 512 ? 2 : (T >= 256 ? 1 : 0)); }
-
-// When the plan's profiling is on, record an event before the main sweep
-// launch on its stream and return the closing event to record after it.
-mm_status profile_begin(mm_plan p, int passes_covered, hipStream_t s, hipEvent_t *ev1) {
-    *ev1 = nullptr;
-    if (!p->profile) return MM_OK;
-    if (p->prof_used >= 4096) {
-        double ms = 0.0;
-        int64_t cnt = 0;
-        MM_TRY(profile_flush(p, &ms, &cnt));
-    }
-    if (p->prof_used >= p->prof_events.size()) {
-        hipEvent_t e0, e1;
-        MM_HIP_TRY(hipEventCreate(&e0));
-        MM_HIP_TRY(hipEventCreate(&e1));
-        p->prof_events.push_back({e0, e1});
-    }
-    MM_HIP_TRY(hipEventRecord(p->prof_events[p->prof_used].first, s));
-    *ev1 = p->prof_events[p->prof_used].second;
-    p->prof_used++;
-    p->prof_units += (int64_t)passes_covered;
-    return MM_OK;
-}
-
-template <class C>
-mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStream_t s) {
-    static_assert(C::T == 128 || C::T == 256 || C::T == 512 || C::T == 1024, "tile sizes with a cross-tile pass list");
-    const KParams kp = kparams(p->kernel, p->d);
-    const int64_t n = p->n;
-    const int ncb = W / C::WCOL;
-    const int64_t ntile = (n + C::T - 1) / C::T;
-    const int npass = (int)p->passes.size();
-    const int64_t len = n * W;
-    if (npass == 0) {
-        hipLaunchKernelGGL(zero_kernel, dim3(grid_1d(len)), dim3(BS1), 0, s, yacc, len);
-        MM_HIP_TRY(hipGetLastError());
-        return MM_OK;
-    }
-    const int ti = tile_index(C::T);
-    const std::vector<int> &xt = p->xt_host[ti];
-    const int gmax = group_passes(p, W);
-    SweepArgs A{};
-    A.xc = static_cast<const double *>(p->xc.ptr);
-    A.passes = static_cast<const PassDev *>(p->pass_dev.ptr);
-    A.xt = static_cast<const int32_t *>(p->pass_xt[ti].ptr);
-    A.vin = vin;
-    A.ypart = static_cast<double *>(p->part.ptr);
-    A.n = n;
-    A.ntile = ntile;
-    A.W = W;
-    A.a = kp.a;
-    const size_t aggslab = (size_t)2 * gmax * ntile * W * C::NSUB * C::NSLOT;
-    A.agg = static_cast<double *>(p->agg.ptr);
-    A.car = A.agg + aggslab;
-    A.anc = A.car + aggslab;
-    A.dec = A.anc + (size_t)2 * gmax * ntile;
-    for (int g0 = 0; g0 < npass; g0 += gmax) {
-        const int G = npass - g0 < gmax ? npass - g0 : gmax;
-        A.g0 = g0;
-        A.G = G;
-        // passes of the group whose segments span tiles: a contiguous range of xt
-        int k0 = 0;
-        while (k0 < (int)xt.size() && xt[k0] < g0) ++k0;
-        int k1 = k0;
-        while (k1 < (int)xt.size() && xt[k1] < g0 + G) ++k1;
-        A.k0 = k0;
-        if (k1 > k0 && ntile > 1) {
-            const dim3 gx((unsigned)((k1 - k0) * ntile), (unsigned)ncb);
-            hipLaunchKernelGGL((sweep_kernel<C, 1>), gx, dim3(WAVE), 0, s, A);
-            // segments of the group's cross-tile passes: a contiguous range of the plan's table
-            const std::vector<int> &so = p->seg_off[ti];
-            const int s0 = so[k0], s1 = so[k1];
-            const int nslice = C::NSUB * C::NCLS * C::NTH * W;
-            A.nslice = nslice;
-            A.segs = static_cast<const int4 *>(p->seg_tab[ti].ptr) + s0;
-            if (s1 > s0)
-                hipLaunchKernelGGL((carry_kernel<C>), dim3((unsigned)(s1 - s0), (unsigned)((nslice + 3) / 4)),
-                                   dim3(256), 0, s, A);
-        }
-        hipEvent_t ev1 = nullptr;
-        MM_TRY(profile_begin(p, G, s, &ev1));
-        hipLaunchKernelGGL((sweep_kernel<C, 0>), dim3((unsigned)(G * ntile), (unsigned)ncb), dim3(WAVE), 0, s, A);
-        if (ev1) MM_HIP_TRY(hipEventRecord(ev1, s));
-        hipLaunchKernelGGL(accum_kernel, dim3(grid_1d(len)), dim3(BS1), 0, s,
-                           static_cast<const double *>(p->part.ptr), G, len, yacc, g0 == 0 ? 1 : 0);
-    }
-    MM_HIP_TRY(hipGetLastError());
-    return MM_OK;
-}
-
-// Lane layout by the padded width W (a multiple of the block WB returned by
-// rhs_block): WCOL = WB columns per wave and runs of E = 256*WCOL/64
-// positions (tiles of 256 positions).  with_cfg calls f(Tag<Cfg<...>>) for the
-// configuration of (d, nu, form, WB).
-template <class C>
-struct Tag {
-    using type = C;
-};
-
-template <int D, int P, bool PROD, class F>
-mm_status with_wb(int WB, F &&f) {
-    if (WB == 32) return f(Tag<Cfg<D, P, PROD, 32, 128>>{});
-    if (WB == 4) return f(Tag<Cfg<D, P, PROD, 4, 16>>{});
-    if (WB == 2) return f(Tag<Cfg<D, P, PROD, 2, 8>>{});
-    return f(Tag<Cfg<D, P, PROD, 1, 4>>{});
-}
-
-template <int D, class F>
-mm_status with_p(const KParams &kp, int WB, F &&f) {
-    if (kp.P == 1) return with_wb<D, 1, true>(WB, f);
-    if constexpr (D == 1) {
-        if (kp.P == 2) return with_wb<D, 2, true>(WB, f);
-        return with_wb<D, 3, true>(WB, f);
-    } else {
-        if (kp.P == 2) return kp.prod ? with_wb<D, 2, true>(WB, f) : with_wb<D, 2, false>(WB, f);
-        return kp.prod ? with_wb<D, 3, true>(WB, f) : with_wb<D, 3, false>(WB, f);
-    }
-}
-
-template <class F>
-mm_status with_cfg(int d, const KParams &kp, int WB, F &&f) {
-    if (d == 1) return with_p<1>(kp, WB, f);
-    if (d == 2) return with_p<2>(kp, WB, f);
-    return with_p<3>(kp, WB, f);
-}
-
-// Arguments of a problem's single pass group (all passes) for configuration C,
-// with caller-owned aggregate and partial-slab workspaces.
-template <class C>
-SweepArgs make_args(mm_plan p, const double *vin, double *agg, double *part, int W, int gmax) {
-    const KParams kp = kparams(p->kernel, p->d);
-    const int ti = tile_index(C::T);
-    const int64_t ntile = (p->n + C::T - 1) / C::T;
-    SweepArgs A{};
-    A.xc = static_cast<const double *>(p->xc.ptr);
-    A.passes = static_cast<const PassDev *>(p->pass_dev.ptr);
-    A.xt = static_cast<const int32_t *>(p->pass_xt[ti].ptr);
-    A.vin = vin;
-    A.ypart = part;
-    A.n = p->n;
-    A.ntile = ntile;
-    A.W = W;
-    A.a = kp.a;
-    const size_t aggslab = (size_t)2 * gmax * ntile * W * C::NSUB * C::NSLOT;
-    A.agg = agg;
-    A.car = A.agg + aggslab;
-    A.anc = A.car + aggslab;
-    A.dec = A.anc + (size_t)2 * gmax * ntile;
-    A.nslice = C::NSUB * C::NCLS * C::NTH * W;
-    A.segs = static_cast<const int4 *>(p->seg_tab[ti].ptr);
-    A.g0 = 0;
-    A.k0 = 0;
-    A.G = (int)p->passes.size();
-    return A;
-}
-
-}  // namespace
 
 // Columns per wave (the padding unit of the number of right-hand sides):
 // 32 from 32 columns up, 4 from 4, else 2 or 1.
@@ -1215,40 +34,58 @@ size_t sweep_part_bytes(int64_t n, int npass, int W) {
     return (size_t)group_size(n, npass, W) * n * W * sizeof(double);
 }
 
-// Aggregates and carries: per tile and right-hand side at most
-// NSUB*NSLOT = 4*NTH*P <= 108 doubles (d = 3, product form, nu = 5/2), two
-// directions, per pass of a group; anchors and decays 2 each per tile and
+// Doubles of one tile aggregate per right-hand side: classes x channel rows
+// x scan channels (the configuration's FULLSLOT), for the kernel and, with
+// der, also for its lengthscale-derivative sweeps (one more channel in one
+// factor).  At most 4 x 9 x 3 = 108 for the kernel and 144 with der (d = 3,
+// product form, nu = 5/2).
+int agg_per_rhs(int d, const mm_kernel &k, bool der) {
+    const KParams kp = kparams(k, d);
+    const int ncls = d == 1 ? 1 : (d == 2 ? 2 : 4);
+    int best = 0;
+    for (int gj = -1; gj < (der ? d : 0); ++gj) {
+        if (!kp.prod && gj >= 0 && gj != d - 1) continue;
+        int nth = 1;
+        if (kp.prod)
+            for (int c = 0; c < d - 1; ++c) nth *= kp.P + (gj == c ? 1 : 0);
+        const int ps = kp.P + (gj == d - 1 ? 1 : 0);
+        best = std::max(best, ncls * nth * ps);
+    }
+    return best;
+}
+
+// Aggregates and carries: agg_per_rhs doubles per tile and right-hand side,
+// two directions, per pass of a group; anchors and decays 2 each per tile and
 // pass.  The smallest tile (128 positions) gives the most tiles.
-static size_t agg_bytes_for(int64_t n, int W, int64_t G) {
+static size_t agg_bytes_for(int64_t n, int W, int64_t G, int per_rhs) {
     const int64_t ntile = (n + 127) / 128;
-    const int64_t per_rhs = 108;
     return (size_t)(2 * (2 * G * ntile * (int64_t)W * per_rhs) + 4 * G * ntile + 16) * sizeof(double);
 }
 
-size_t sweep_agg_bytes(int64_t n, int d, int W, const mm_kernel &k) {
-    (void)k;
+size_t sweep_agg_bytes(int64_t n, int d, int W, const mm_kernel &k, bool der) {
     int L = 0;
     while ((int64_t(1) << L) < n) ++L;
     const int npass = n < 2 ? 0 : (d == 1 ? 1 : (d == 2 ? L : L * (L + 1) / 2));
     const int64_t G = npass == 0 ? 1 : group_size(n, npass, W);
-    return agg_bytes_for(n, W, G);
+    return agg_bytes_for(n, W, G, agg_per_rhs(d, k, der));
 }
 
 // A batched problem runs all its passes as one group, its partial slabs in a
 // workspace of its own; up to 16 GiB of them per problem.
 constexpr size_t BATCH_PART_BUDGET = size_t(16) << 30;
 
-bool sweep_batch_bytes_n(int64_t n, int npass, int W, size_t *agg_bytes, size_t *part_bytes) {
+bool sweep_batch_bytes_n(int64_t n, int d, const mm_kernel &k, int npass, int W, size_t *agg_bytes,
+                         size_t *part_bytes) {
     const size_t slab = (size_t)n * W * sizeof(double);
     if (npass > 0 && (size_t)npass * slab > BATCH_PART_BUDGET) return false;
     const int64_t G = npass > 0 ? npass : 1;
     *part_bytes = (size_t)G * slab;
-    *agg_bytes = agg_bytes_for(n, W, G);
+    *agg_bytes = agg_bytes_for(n, W, G, agg_per_rhs(d, k, false));
     return true;
 }
 
 bool sweep_batch_bytes(mm_plan p, int W, size_t *agg_bytes, size_t *part_bytes) {
-    return sweep_batch_bytes_n(p->n, (int)p->passes.size(), W, agg_bytes, part_bytes);
+    return sweep_batch_bytes_n(p->n, p->d, p->kernel, (int)p->passes.size(), W, agg_bytes, part_bytes);
 }
 
 mm_status upload_pass_tables(mm_plan p) {

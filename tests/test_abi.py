@@ -85,6 +85,8 @@ def test_null_pointers_rejected_on_host():
     assert L.matern_mvm(None, None, 1, None, 1, 1, 0.0, None) == mm.MM_ERR_ARG
     assert L.gp_cg_solve(None, None, 0.1, 0, 1e-8, 10, None, None, None, None) == mm.MM_ERR_ARG
     assert L.gp_predict(None, None, None, None, 1, 1, None, None) == mm.MM_ERR_ARG
+    assert L.matern_mvm_dlengthscale(None, None, 1, None, 1, 1, None) == mm.MM_ERR_ARG
+    assert L.gp_lml(None, None, 0.1, None, 1, 1, 10, 1e-8, None, None, None) == mm.MM_ERR_ARG
     assert L.mm_plan_destroy(None) == mm.MM_OK
     assert L.mm_plan_profile_enable(None, 1) == mm.MM_ERR_ARG
 
