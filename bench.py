@@ -158,6 +158,40 @@ def bench_pcg(mm, x, y, kern, rank, reps=2):
     return out
 
 
+def bench_gradient(mm, x, y, kern, probes, reps):
+    """The headline configuration's lengthscale-derivative products (nrhs 1, 4
+    and 32, against the plain product) and one evaluation of the log marginal
+    likelihood with its gradient from `probes` Rademacher probes (CG to 1e-8,
+    zero mean: the targets centred by their mean)."""
+    import torch
+    out = {"dlengthscale_mvm": {}}
+    plan = mm.Plan(x, kern)
+    for nrhs in (1, 4, 32):
+        vv = torch.as_tensor(np.random.default_rng(70 + nrhs).standard_normal((nrhs, N)), device=x.device)
+        yy = torch.empty_like(vv)
+        for _ in range(2):
+            plan.mvm_dlengthscale_raw(vv, yy, nrhs)
+            plan.mvm_raw(vv, yy, nrhs)
+        ms_d = _events_ms(lambda: plan.mvm_dlengthscale_raw(vv, yy, nrhs), reps)
+        ms_k = _events_ms(lambda: plan.mvm_raw(vv, yy, nrhs), reps)
+        out["dlengthscale_mvm"][str(nrhs)] = {"ms": round(ms_d, 4), "points_per_s": N * nrhs / (ms_d * 1e-3),
+                                              "plain_ms": round(ms_k, 4)}
+        log("dK/dl product nrhs=%d: %.3f ms (plain %.3f ms)" % (nrhs, ms_d, ms_k))
+    Z = torch.as_tensor(np.random.default_rng(71).choice([-1.0, 1.0], size=(N, probes)), device=x.device)
+    yc = y - y.mean()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = plan.lml(yc, SIGMA2, Z, maxit=20000, rtol=RTOL, raise_on_error=False)
+    torch.cuda.synchronize()
+    res["seconds"] = time.perf_counter() - t0
+    res["probes"] = probes
+    out["lml"] = res
+    log("lml with %d probes: %d iterations, %.2f s, L = %.6e, dL/dl = %.4e" %
+        (probes, res["iters"], res["seconds"], res["lml"], res["dlml_dlengthscale"]))
+    plan.close()
+    return out
+
+
 def bench_config3(dev, steps, rank):
     """d=3, N=500k, nu=5/2, lengthscale 0.3, x ~ N(0, I): one product with the 32
     Rademacher probes (product and L1 forms), the stochastic log-determinant from
@@ -339,6 +373,8 @@ def main():
                     help="also run the d=3 N=500k nu=5/2 section: one 32-probe product, the "
                          "stochastic log-determinant from those probes and one preconditioned solve")
     ap.add_argument("--logdet-steps", type=int, default=30)
+    ap.add_argument("--lml-probes", type=int, default=31,
+                    help="probes of the likelihood-gradient section (0: skip the section)")
     ap.add_argument("--pcg-rank", type=int, default=100,
                     help="rank of the pivoted Cholesky preconditioner of the extra PCG section (0: skip)")
     ap.add_argument("--maxit", type=int, default=20000,
@@ -466,6 +502,11 @@ def main():
         log("preconditioned solve: rank %d" % args.pcg_rank)
         pcg_out = bench_pcg(mm, x, y, kern, args.pcg_rank)
 
+    grad_out = None
+    if args.lml_probes > 0:
+        log("gradient: dK/dl products and the likelihood with %d probes" % args.lml_probes)
+        grad_out = bench_gradient(mm, x, y, kern, args.lml_probes, args.mvm_reps)
+
     c3_out = None
     if args.config3:
         log("config 3: d=3 N=500k nu=5/2, 32 probes")
@@ -513,6 +554,7 @@ def main():
         "true_relres": true_res,
         "mvm": mvm_rows,
         "pcg": pcg_out,
+        "gradient": grad_out,
         "config3": c3_out,
         "batched": batched_out,
         "served": served_out,

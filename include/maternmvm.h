@@ -205,6 +205,24 @@ mm_status gp_predict(mm_plan plan, const double *alpha, const double *beta, cons
                      int64_t m, int64_t ldz, double *mean, void *stream);
 
 /*
+ * Posterior variance at m new points (eq. gp_variance):
+ *     var(z) = K(z, z) - k_z^T (K + sigma2 I)^{-1} k_z,   K(z, z) = outputscale2,
+ * the variance of the latent function (add sigma2 for a new observation).
+ * k_z = K(X, z) comes from exact products on the union of the training and
+ * prediction points with unit weights on the latter; the solves run by
+ * multi-column conjugate gradients, 32 points at a time, each column to
+ * ||r|| <= rtol ||k_z||.
+ *   z      device, m x d column-major, leading dimension ldz >= m
+ *   rtol   > 0; maxit >= 1 per block of points
+ *   var    device, m outputs
+ *   info   host (may be NULL): the largest iteration count and residual over
+ *          the blocks, and the number of converged columns
+ * Same status rules as gp_cg_solve (outputs written).  Synchronises.
+ */
+mm_status gp_variance(mm_plan plan, double sigma2, const double *z, int64_t m, int64_t ldz, double rtol,
+                      int32_t maxit, double *var, mm_solve_info *info, void *stream);
+
+/*
  * Rank-k pivoted Cholesky preconditioner (Appendix A, "Preconditioning"):
  * P = L L^T + sigma2 I with L L^T the pivoted Cholesky decomposition of K,
  * applied in conjugate gradients through the Woodbury identity

@@ -31,6 +31,7 @@ Contents (each function cites the passage it follows):
                      likelihood and its gradient (eq. gp_log_likelihood, eq.
                      gp_log_likelihood_derivative) by dense algebra, and the
                      terms of the stochastic trace estimator (Appendix A).
+* ``posterior_variance``  the posterior variance of eq. gp_variance by Cholesky.
 * ``decomposition``  (sub-module) the paper's weighted-ECDF decomposition
                      evaluated by brute-force masked sums (Props. 1-2 and the
                      Matern examples of Section 2.3); used only to pin the
@@ -252,6 +253,15 @@ def predict(x, alpha, z, two_nu: int, form, ell: float, s2: float, beta=None) ->
     if beta is not None:
         mean = mean + design_matrix(z) @ np.asarray(beta, dtype=np.float64)
     return mean
+
+
+def posterior_variance(x, z, two_nu: int, form, ell: float, s2: float, sigma2: float) -> np.ndarray:
+    """Posterior variance of the latent function (eq. gp_variance):
+    K(z, z) - k_z^T (K + sigma^2 I)^{-1} k_z with K(z, z) = s2, by Cholesky."""
+    A = kernel_matrix(x, two_nu, form, ell, s2, sigma2=sigma2)
+    Kxz = kernel_matrix(z, two_nu, form, ell, s2, z=x)      # K(X, Z): n x m
+    U = cholesky_solve(cholesky(A), Kxz)
+    return s2 - np.einsum("ij,ij->j", Kxz, U)
 
 
 def pivoted_cholesky(x, two_nu: int, form, ell: float, s2: float, max_rank: int, tol: float = 0.0):

@@ -83,6 +83,8 @@ _SIGS = {
     "matern_mvm_dlengthscale": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int32, _P]),
     "gp_lml": (ctypes.c_int, [_P, _P, ctypes.c_double, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                               ctypes.c_double, ctypes.POINTER(_MMLmlInfo), _P, _P]),
+    "gp_variance": (ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                                   ctypes.c_int32, _P, ctypes.POINTER(_MMSolveInfo), _P]),
     "gp_cg_solve": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                    ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(_MMSolveInfo), _P]),
@@ -393,6 +395,24 @@ class Plan:
                                 ctypes.c_void_p(zc.data_ptr()), m, m,
                                 ctypes.c_void_p(mean.data_ptr()), _stream_ptr(self._stream)))
         return mean
+
+    def variance(self, z, sigma2: float, rtol: float = 1e-10, maxit: int = 20000, raise_on_error: bool = True):
+        """Posterior variance of the latent function at z of shape (m, d)
+        (eq. gp_variance).  Returns (var, info dict)."""
+        torch = _torch()
+        if z.dim() == 1:
+            z = z.view(-1, 1)
+        m = int(z.shape[0])
+        zc = z.t().contiguous()
+        var = torch.empty(m, dtype=torch.float64, device=z.device)
+        info = _MMSolveInfo()
+        st = lib().gp_variance(self._h, float(sigma2), ctypes.c_void_p(zc.data_ptr()), m, m, float(rtol), int(maxit),
+                               ctypes.c_void_p(var.data_ptr()), ctypes.byref(info), _stream_ptr(self._stream))
+        msg = last_error()
+        if st != MM_OK and raise_on_error:
+            raise MaternError(st, msg)
+        return var, {"iters": info.iters, "converged_cols": info.converged_cols,
+                     "relres_max": info.relres_max, "status": STATUS_NAMES[st]}
 
     def logdet(self, sigma2: float, probes, steps: int = 200, rtol: float = 0.0):
         """Stochastic log det(K + sigma2 I) from CG-Lanczos quadratures of the probe

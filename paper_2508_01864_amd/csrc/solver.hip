@@ -528,6 +528,37 @@ __global__ void lml_mix_kernel(const double *X, const double *B, int64_t n, int 
         V[e] = (e % W) == 0 ? X[e] : B[e];
 }
 
+// Coordinates of the union of the training points (canonical order) and the
+// prediction points, column-major with leading dimension n + m.
+__global__ void union_coords_kernel(const double *xc, int64_t n, const double *z, int64_t m, int64_t ldz, int d,
+                                    double *U) {
+    const int64_t nm = n + m;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nm; i += (int64_t)gridDim.x * blockDim.x)
+        for (int k = 0; k < d; ++k) U[k * nm + i] = i < n ? xc[k * n + i] : z[k * ldz + (i - n)];
+}
+
+// Unit weights on prediction points j0 .. j0 + b - 1: column r of V (leading
+// dimension nm) is the indicator of union point n + j0 + r.
+__global__ void unit_cols_kernel(double *V, int64_t nm, int64_t n, int64_t j0, int b) {
+    const int64_t total = nm * b;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / nm, i = e - r * nm;
+        V[e] = i == n + j0 + r ? 1.0 : 0.0;
+    }
+}
+
+// Right-hand sides k_z of the variance solves: the first n rows of the union
+// products (the union's first n points are the training points in canonical
+// order), point-major with W columns, the padding zero.
+__global__ void kz_rhs_kernel(const double *KV, int64_t nm, int64_t n, int b, double *B, int W) {
+    const int64_t total = n * W;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / W;
+        const int r = (int)(e - c * W);
+        B[e] = r < b ? KV[(int64_t)r * nm + c] : 0.0;
+    }
+}
+
 // Per row block and column: partial sums of X.B, X.D and X.X (three NRED x W
 // slabs of part).
 __global__ void lml_dots_kernel(const double *X, const double *B, const double *D, int64_t n, int W, double *part) {
@@ -1575,6 +1606,107 @@ mm_status gp_lml(mm_plan plan, const double *y, double sigma2, const double *Zc,
     mm_solver_destroy(sv);
     if (st != MM_OK) set_error("%s", msg.c_str());
     return st;
+}
+
+mm_status gp_variance(mm_plan plan, double sigma2, const double *z, int64_t m, int64_t ldz, double rtol,
+                      int32_t maxit, double *var, mm_solve_info *info, void *stream) {
+    clear_error();
+    MM_TRY(check_solve_args(plan, sigma2, rtol));
+    if (!z || !var) {
+        set_error("z and var must be non-NULL");
+        return MM_ERR_ARG;
+    }
+    if (m < 1 || ldz < m || maxit < 1) {
+        set_error("m >= 1, ldz >= m and maxit >= 1 are required");
+        return MM_ERR_ARG;
+    }
+    const int64_t n = plan->n;
+    const int d = plan->d;
+    if (n + m > (int64_t(1) << 30)) {
+        set_error("n + m exceeds 2^30");
+        return MM_ERR_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t nm = n + m;
+    constexpr int BLK = 32;  // prediction points per block of solves
+    DevBuf wb;
+    MM_TRY(dev_alloc(wb, ((size_t)d * nm + (size_t)2 * nm * BLK) * sizeof(double)));
+    double *U = static_cast<double *>(wb.ptr);
+    double *V = U + (size_t)d * nm;
+    double *KV = V + (size_t)nm * BLK;
+    hipLaunchKernelGGL(union_coords_kernel, dim3(grid1(nm)), dim3(BS), 0, s, static_cast<const double *>(plan->xc.ptr),
+                       n, z, m, ldz, d, U);
+    mm_plan up = nullptr;
+    mm_status st = mm_plan_create(U, nm, d, nm, &plan->kernel, stream, &up);
+    const double s2 = plan->kernel.outputscale2;
+    mm_solve_info worst{};
+    int conv_all = 1, brk_any = 0;
+    double rel_all = 0.0;
+    std::vector<double> hv(BLK), hp((size_t)3 * NRED * BLK);
+    for (int64_t j0 = 0; j0 < m && st == MM_OK; j0 += BLK) {
+        const int b = (int)(m - j0 < BLK ? m - j0 : BLK);
+        // k_z for the block: exact products of the union with unit weights
+        hipLaunchKernelGGL(unit_cols_kernel, dim3(grid1(nm * b)), dim3(BS), 0, s, V, nm, n, j0, b);
+        st = matern_mvm(up, V, nm, KV, nm, b, 0.0, stream);
+        if (st != MM_OK) break;
+        mm_solver sv = nullptr;
+        st = solver_new(plan, b, 0, sigma2, rtol, nullptr, s,
+                        [&](double *B, int W) {
+                            hipLaunchKernelGGL(kz_rhs_kernel, dim3(grid1(n * W)), dim3(BS), 0, s, KV, nm, n, b, B, W);
+                        },
+                        &sv);
+        if (st != MM_OK) break;
+        st = solver_run(sv, maxit, s);
+        int conv = 0, brk = 0;
+        double rel = 0.0;
+        mm_solve_info inf{};
+        if (st == MM_OK) st = solver_summary(sv, s, &conv, &brk, &rel, &inf);
+        if (st == MM_OK) {
+            const int W = sv->W;
+            // k_z^T A^-1 k_z per column (the X.B sums)
+            hipLaunchKernelGGL(lml_dots_kernel, dim3(NRED), dim3(BS), 0, s, sv->desc.X, sv->desc.B, sv->desc.B, n, W,
+                               sv->desc.part);
+            if (hipMemcpyAsync(hp.data(), sv->desc.part, (size_t)NRED * W * sizeof(double), hipMemcpyDeviceToHost,
+                               s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                set_error("HIP error in the variance products");
+                st = MM_ERR_HIP;
+            } else {
+                for (int r = 0; r < b; ++r) {
+                    double q = 0.0;
+                    for (int blk = 0; blk < NRED; ++blk) q += hp[(size_t)blk * W + r];
+                    hv[r] = s2 - q;
+                }
+                if (hipMemcpyAsync(var + j0, hv.data(), b * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess) {
+                    set_error("HIP error writing the variances");
+                    st = MM_ERR_HIP;
+                }
+            }
+            if (inf.iters > worst.iters) worst.iters = inf.iters;
+            if (inf.relres_max > worst.relres_max) worst.relres_max = inf.relres_max;
+            worst.converged_cols += inf.converged_cols;
+            if (conv < b) conv_all = 0;
+            if (brk) brk_any = 1;
+            if (rel > rel_all) rel_all = rel;
+        }
+        std::string msg = last_error_str();
+        mm_solver_destroy(sv);
+        if (st != MM_OK) set_error("%s", msg.c_str());
+    }
+    if (up) mm_plan_destroy(up);
+    dev_free(wb);
+    if (st != MM_OK) return st;
+    if (info) *info = worst;
+    if (brk_any) {
+        set_error("conjugate gradients broke down (p^T A p <= 0)");
+        return MM_ERR_BREAKDOWN;
+    }
+    if (!conv_all) {
+        set_error("conjugate gradients did not reach rtol in %d iterations (relres %.3e)", worst.iters, rel_all);
+        return MM_ERR_NOCONV;
+    }
+    return MM_OK;
 }
 
 mm_status gp_cg_solve_multi(mm_plan plan, const double *Bc, int64_t ldb, int32_t nrhs, double sigma2, double rtol,

@@ -142,3 +142,24 @@ def test_lml_reports_nonconvergence_and_refuses_l1(oracle_lib):
         plan.lml(to_gpu(y), 0.01, to_gpu(Z))
     assert e.value.status == mm.MM_ERR_NOTPD
     plan.close()
+
+
+@pytest.mark.parametrize("d,two_nu,m", [(1, 1, 5), (2, 3, 40), (3, 5, 33)])
+def test_posterior_variance_matches_oracle(oracle_lib, d, two_nu, m):
+    """eq. gp_variance at prediction points spread over the domain, on training
+    points and far away; 40 points take two blocks of solves."""
+    rng = np.random.default_rng(9500 + d)
+    n, ell, s2, sig = 900, 0.15, 1.3, 0.02
+    x = rng.uniform(0, 1, (n, d))
+    z = rng.uniform(0, 1, (m, d))
+    z[0] = x[3]                       # on a training point
+    z[-1] = 40.0                      # far from all of them
+    plan = mm.Plan(to_gpu(x), mm.Kernel(two_nu, "product", ell, s2))
+    var, info = plan.variance(to_gpu(z), sig, rtol=1e-12, maxit=n)
+    plan.close()
+    ref = oracle.posterior_variance(x, z, two_nu, "product", ell, s2, sig)
+    err = np.max(np.abs(to_np(var) - ref))
+    say("variance d=%d m=%d: iters %d max err %.2e" % (d, m, info["iters"], err))
+    assert info["status"] == "MM_OK" and info["converged_cols"] == m
+    assert err <= 1e-9 * s2
+    assert abs(to_np(var)[-1] - s2) <= 1e-12

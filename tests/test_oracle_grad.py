@@ -1,11 +1,12 @@
-"""Pins of the oracle's lengthscale derivative and log marginal likelihood
-(Section 2.3 gradients, eq. gp_log_likelihood, eq.
-gp_log_likelihood_derivative, Appendix A trace estimator).
+"""Pins of the oracle's lengthscale derivative, log marginal likelihood and
+posterior variance (Section 2.3 gradients, eq. gp_log_likelihood, eq.
+gp_log_likelihood_derivative, Appendix A trace estimator, eq. gp_variance).
 
 The derivative is checked against central finite differences of the oracle's
 kernel matrix (its C code, an independent route to the same numbers); the
 likelihood gradient against finite differences of the likelihood; the trace
-estimator against the exact trace on a probe basis.
+estimator against the exact trace on a probe basis; the variance against its
+one-point closed form and its limits.
 """
 import numpy as np
 import pytest
@@ -98,3 +99,21 @@ def test_hutchinson_on_a_probe_basis_is_the_trace(oracle_lib):
     R = rng.choice([-1.0, 1.0], size=(n, 4000))
     t = oracle.hutchinson_terms(A, D, R)
     assert abs(np.mean(t) - exact) <= 5 * np.std(t) / np.sqrt(t.size)
+
+
+def test_posterior_variance_closed_forms(oracle_lib):
+    rng = np.random.default_rng(11)
+    s2, sig = 1.6, 0.03
+    # one training point: var = s2 - k^2 / (s2 + sigma2)
+    x1 = rng.uniform(0, 1, (1, 2))
+    z = rng.uniform(0, 1, (5, 2))
+    k = np.array([oracle.kernel(zz, x1[0], 3, "product", 0.3, s2) for zz in z])
+    v = oracle.posterior_variance(x1, z, 3, "product", 0.3, s2, sig)
+    assert np.allclose(v, s2 - k * k / (s2 + sig), rtol=1e-13, atol=0)
+    # far from every training point the prior variance remains
+    x = rng.uniform(0, 1, (30, 2))
+    far = np.array([[50.0, 50.0]])
+    assert abs(oracle.posterior_variance(x, far, 5, "product", 0.2, s2, sig)[0] - s2) <= 1e-15
+    # at a training point the variance is below the noise level, and never negative
+    vt = oracle.posterior_variance(x, x[:5], 1, "product", 0.2, s2, sig)
+    assert np.all(vt > 0) and np.all(vt < sig)
