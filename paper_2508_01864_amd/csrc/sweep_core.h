@@ -146,8 +146,6 @@ __device__ __forceinline__ void factor_vecs(double E, double t, double (&sv)[N],
 // Flags stored with each staged element.
 constexpr int F_SIDE1 = 1;     // x1 half (d >= 2)
 constexpr int F_SIDE2 = 2;     // x2 half (d = 3)
-constexpr int F_SEGSTART = 4;  // first position of a segment
-constexpr int F_SEGEND = 8;    // last position of a segment (or of the array)
 constexpr int F_VALID = 16;    // position < n
 
 // One divide-and-conquer pass as the kernels see it (device table).
@@ -227,8 +225,9 @@ struct Cfg {
     static constexpr bool REGOUT = E <= 4 && E * NSLOT <= 64;
     // elements per block of a run's loads.  Short runs take two blocks: with
     // one, the block loop disappears, every load of the run is hoisted and
-    // the state spills (d = 3).
-    static constexpr int BLK = E <= 8 ? E / 2 : 8;
+    // the state spills (d = 3).  Long runs take blocks of 4 in d <= 2 (8 lifts
+    // the d = 2 kernels past 128 registers) and of 8 in d = 3.
+    static constexpr int BLK = E <= 8 ? E / 2 : (D <= 2 ? 4 : 8);
 };
 
 template <class C>
@@ -398,9 +397,13 @@ template <class C>
 struct Smem {
     int32_t c[C::T];
     int32_t flags[C::T];
-    double xs[C::T];
-    double est[C::T + 1];  // decay from the previous position; [T]: into the next tile's first
-    double xedge[2];       // scan coordinate before the tile (p0 - 1) and after it (p0 + T)
+    // decay exp(-t) and scaled distance t = a (x_j - x_{j-1}) from the previous
+    // position; both 0 at segment starts (the state restarts there) and past the
+    // end; [T]: into the next tile's first position
+    double est[C::T + 1];
+    double st[C::T + 1];
+    double xrun[2][C::RUNS];  // scan coordinate of each run's first and last position
+    double xedge[2];          // scan coordinate before the tile (p0 - 1) and after it (p0 + T)
     double geo[C::G > 0 ? C::G : 1][C::T];
 };
 
@@ -423,64 +426,50 @@ __device__ __forceinline__ void stage_tile(const SweepArgs &A, const PassDev &ps
                                            int64_t p0) {
     const int64_t n = A.n;
     const int64_t segmask = (int64_t(1) << ps.seg_log2) - 1;
-    for (int j = threadIdx.x; j < C::T; j += WAVE) {
-        const int64_t p = p0 + j;
-        const int64_t pc = p < n ? p : n - 1;
-        int flags = p < n ? F_VALID : 0;
-        if (p < n && (p & segmask) == 0) flags |= F_SEGSTART;
-        if (p >= n - 1 || ((p + 1) & segmask) == 0) flags |= F_SEGEND;
-        const int sj = slot<C>(j);
-        int64_t c;
-        if constexpr (C::D == 1) {
-            c = pc;
-            sm.xs[sj] = A.xc[c];
-        } else {
-            // sequential reads of the pass's stored geometry
-            const uint32_t cf = ps.cf[pc];
-            c = (int64_t)(cf & 0x3fffffffu);
-            flags |= (cf >> 30) & 1u ? F_SIDE1 : 0;
-            const double t1 = A.a * ps.w1[pc];
-            sm.geo[0][sj] = exp(-t1);
-            sm.geo[1][sj] = t1;
-            if constexpr (C::D == 3) {
-                flags |= (cf >> 31) ? F_SIDE2 : 0;
-                const double t2 = A.a * ps.w2[pc];
-                sm.geo[2][sj] = exp(-t2);
-                sm.geo[3][sj] = t2;
-            }
-            sm.xs[sj] = ps.xs[pc];
-        }
-        sm.c[sj] = (int32_t)c;
-        sm.flags[sj] = flags;
-    }
-    __syncthreads();
-    // decay exp(-a (x_j - x_{j-1})) into every position from its predecessor,
-    // including across the tile's edges (position p0 from p0 - 1, and the next
-    // tile's first position p0 + T from the tile's last); 1 at segment starts
     for (int j = threadIdx.x; j <= C::T; j += WAVE) {
         const int64_t p = p0 + j;
-        double e = 1.0;
-        if (p < n && p > 0 && (p & segmask) != 0) {
-            double xcur, xprev;
-            if (j > 0 && j < C::T) {
-                xcur = sm.xs[slot<C>(j)];
-                xprev = sm.xs[slot<C>(j - 1)];
-            } else if (j == 0) {
-                xcur = sm.xs[slot<C>(0)];
-                xprev = scan_coord<C>(A, ps, p - 1);
-                sm.xedge[0] = xprev;
+        const int64_t pc = p < n ? p : n - 1;
+        const double xcur = scan_coord<C>(A, ps, pc);
+        if (j < C::T) {
+            int flags = p < n ? F_VALID : 0;
+            const int sj = slot<C>(j);
+            int64_t c;
+            if constexpr (C::D == 1) {
+                c = pc;
             } else {
-                xcur = scan_coord<C>(A, ps, p);
-                xprev = sm.xs[slot<C>(C::T - 1)];
-                sm.xedge[1] = xcur;
+                // sequential reads of the pass's stored geometry
+                const uint32_t cf = ps.cf[pc];
+                c = (int64_t)(cf & 0x3fffffffu);
+                flags |= (cf >> 30) & 1u ? F_SIDE1 : 0;
+                const double t1 = A.a * ps.w1[pc];
+                sm.geo[0][sj] = exp(-t1);
+                sm.geo[1][sj] = t1;
+                if constexpr (C::D == 3) {
+                    flags |= (cf >> 31) ? F_SIDE2 : 0;
+                    const double t2 = A.a * ps.w2[pc];
+                    sm.geo[2][sj] = exp(-t2);
+                    sm.geo[3][sj] = t2;
+                }
             }
-            e = exp(-A.a * (xcur - xprev));
-        } else if (j == 0) {
-            sm.xedge[0] = sm.xs[slot<C>(0)];
-        } else if (j == C::T) {
-            sm.xedge[1] = sm.xs[slot<C>(C::T - 1)];
+            sm.c[sj] = (int32_t)c;
+            sm.flags[sj] = flags;
+            const int e = j % C::E;
+            if (e == 0) sm.xrun[0][j / C::E] = xcur;
+            if (e == C::E - 1) sm.xrun[1][j / C::E] = xcur;
         }
+        // from the predecessor, including across the tile's edges (position p0
+        // from p0 - 1, and the next tile's first position p0 + T from the last)
+        const bool has_prev = p < n && p > 0 && (p & segmask) != 0;
+        double e = 0.0, t = 0.0, xprev = xcur;
+        if (has_prev) {
+            xprev = scan_coord<C>(A, ps, p - 1);
+            t = A.a * (xcur - xprev);
+            e = exp(-t);
+        }
+        if (j == 0) sm.xedge[0] = xprev;
+        if (j == C::T) sm.xedge[1] = has_prev ? xcur : scan_coord<C>(A, ps, p0 + C::T - 1 < n ? p0 + C::T - 1 : n - 1);
         sm.est[j < C::T ? slot<C>(j) : C::T] = e;
+        sm.st[j < C::T ? slot<C>(j) : C::T] = t;
     }
     __syncthreads();
 }
@@ -529,28 +518,22 @@ __device__ __forceinline__ void scan_step(State<C> &F, double &t, double &E, int
 // source.  Returns the target value.
 template <class C, int DIR, bool TARGET>
 __device__ __forceinline__ double scan_elem(const Smem<C> &sm, State<C> &S, int e, int i, int run, int hh,
-                                            double &prevx, double v, double a) {
-    constexpr int BOUND = DIR == 0 ? F_SEGSTART : F_SEGEND;
+                                            double v) {
     const int sj = e * C::RUNS + run;
     const int fl = sm.flags[sj];
     int sc, tc;
     classes<C>(fl, hh, sc, tc);
-    const double xj = sm.xs[sj];
-    if (fl & BOUND) {
-        if constexpr (TARGET) S.zero();
+    // move the state from the previous position in the scan direction (the
+    // anchor of any carry) with the staged decay and distance; both are 0 at a
+    // segment start (forward) or past a segment end (backward), which restarts
+    // the state
+    int ej;
+    if constexpr (DIR == 0) {
+        ej = sj;
     } else {
-        const double t = a * (DIR == 0 ? xj - prevx : prevx - xj);
-        // the previous position in the scan direction is the anchor of any carry,
-        // so the decay is the staged one between neighbours
-        int ej;
-        if constexpr (DIR == 0) {
-            ej = sj;
-        } else {
-            ej = (e + 1 < C::E) ? sj + C::RUNS : (run + 1 < C::RUNS ? run + 1 : C::T);
-        }
-        S.shift(sm.est[ej], t);
+        ej = (e + 1 < C::E) ? sj + C::RUNS : (run + 1 < C::RUNS ? run + 1 : C::T);
     }
-    prevx = xj;
+    S.shift(sm.est[ej], sm.st[ej]);
     double geo[C::G > 0 ? C::G : 1];
     load_geo<C>(sm, sj, geo);
     ElemVec<C> ev;
@@ -578,10 +561,8 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
     const int Gr = seg <= C::E ? 1 : (seg >= C::T ? C::RUNS : seg / C::E);
     const int lig = run & (Gr - 1);
     const double a = A.a;
-    const int ebeg = DIR == 0 ? 0 : C::E - 1;
-    const int eend = DIR == 0 ? C::E - 1 : 0;
-    const double xbeg = sm.xs[ebeg * C::RUNS + run];
-    const double xend = sm.xs[eend * C::RUNS + run];
+    const double xbeg = sm.xrun[DIR == 0 ? 0 : 1][run];
+    const double xend = sm.xrun[DIR == 0 ? 1 : 0][run];
     const double *vcol = A.vin + col;
 
     State<C> Ex;  // carry entering the run, anchored at xex
@@ -592,12 +573,11 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
         // ---- run aggregate (anchored at xend)
         State<C> F;
         F.zero();
-        double px = xbeg;
         if constexpr (C::REGOUT) {
 #pragma unroll
             for (int i = 0; i < C::E; ++i) {
                 const int e = DIR == 0 ? i : C::E - 1 - i;
-                scan_elem<C, DIR, false>(sm, F, e, i, run, hh, px, vr[e], a);
+                scan_elem<C, DIR, false>(sm, F, e, i, run, hh, vr[e]);
             }
         } else {
 #pragma unroll 1
@@ -614,7 +594,7 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
 #pragma unroll
                 for (int k = 0; k < C::BLK; ++k) {
                     const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
-                    scan_elem<C, DIR, false>(sm, F, e, b + k, run, hh, px, vb[k], a);
+                    scan_elem<C, DIR, false>(sm, F, e, b + k, run, hh, vb[k]);
                 }
             }
         }
@@ -690,12 +670,11 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
     if constexpr (MODE == 0) {
         // ---- the scan proper: targets read the state, then sources enter it
         State<C> S = Ex;
-        double px = xex;
         if constexpr (C::REGOUT) {
 #pragma unroll
             for (int i = 0; i < C::E; ++i) {
                 const int e = DIR == 0 ? i : C::E - 1 - i;
-                outv[e] += scan_elem<C, DIR, true>(sm, S, e, i, run, hh, px, vr[e], a);
+                outv[e] += scan_elem<C, DIR, true>(sm, S, e, i, run, hh, vr[e]);
             }
         } else {
 #pragma unroll 1
@@ -723,7 +702,7 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
 #pragma unroll
                 for (int k = 0; k < C::BLK; ++k) {
                     const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
-                    const double val = scan_elem<C, DIR, true>(sm, S, e, b + k, run, hh, px, vb[k], a);
+                    const double val = scan_elem<C, DIR, true>(sm, S, e, b + k, run, hh, vb[k]);
                     if (addr[k] >= 0) slab[addr[k]] = ob[k] + val;
                 }
             }
