@@ -90,6 +90,22 @@ const char *mm_status_str(mm_status st);
 const char *mm_last_error(void);
 
 /*
+ * Device memory of the library.  Every device buffer the library allocates
+ * (plans, solvers, batches, preconditioners, temporaries) comes from
+ * alloc(bytes, stream, ctx), which returns device memory of the current device
+ * or NULL (the call then fails with MM_ERR_NOMEM), and goes back through
+ * free(ptr, stream, ctx) of the allocator that provided it.  stream is passed
+ * as NULL: the library synchronises the device before it releases a buffer,
+ * so a stream-ordered caching allocator (torch's) may reuse it at once.
+ * Both NULL restores hipMalloc / hipFree; exactly one NULL is MM_ERR_ARG.
+ * Process-wide: set it while no other library call is running.  Pinned host
+ * staging buffers are not affected.
+ */
+typedef void *(*mm_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*mm_free_fn)(void *ptr, void *stream, void *ctx);
+mm_status mm_set_allocator(mm_alloc_fn alloc, mm_free_fn free, void *ctx);
+
+/*
  * Upper bound of the device memory a plan for n points in dimension d needs,
  * including work buffers for products with up to nrhs right-hand sides.  Host
  * only; intended for admission control.  Returns 0 for invalid arguments.

@@ -68,6 +68,7 @@ class _MMLmlInfo(ctypes.Structure):
 _P = ctypes.c_void_p
 _SIGS = {
     "mm_version": (ctypes.c_char_p, []),
+    "mm_set_allocator": (ctypes.c_int, [_P, _P, _P]),
     "mm_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "mm_last_error": (ctypes.c_char_p, []),
     "mm_plan_footprint_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
@@ -625,6 +626,37 @@ class MvmBatch:
             self.close()
         except Exception:
             pass
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_refs = None
+
+
+def use_torch_allocator(on: bool = True):
+    """Route every device buffer of the library through torch's caching
+    allocator (mm_set_allocator), or back to hipMalloc with on=False.  Call
+    while no library objects are being created or destroyed."""
+    global _allocator_refs
+    if not on:
+        _check(lib().mm_set_allocator(None, None, None))
+        _allocator_refs = None
+        return
+    torch = _torch()
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes)))
+        except Exception:
+            return None
+
+    def _free(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    refs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _check(lib().mm_set_allocator(ctypes.cast(refs[0], ctypes.c_void_p), ctypes.cast(refs[1], ctypes.c_void_p),
+                                  None))
+    _allocator_refs = refs            # the callbacks must outlive their registration
 
 
 def lanczos_logquad(alpha, beta) -> float:

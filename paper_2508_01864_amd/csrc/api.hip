@@ -169,6 +169,16 @@ extern "C" {
 
 const char *mm_version(void) { return "maternmvm 0.1 (gfx950)"; }
 
+mm_status mm_set_allocator(mm_alloc_fn alloc, mm_free_fn free, void *ctx) {
+    clear_error();
+    if ((alloc == nullptr) != (free == nullptr)) {
+        set_error("alloc and free must both be set or both be NULL");
+        return MM_ERR_ARG;
+    }
+    set_allocator(alloc, free, ctx);
+    return MM_OK;
+}
+
 const char *mm_status_str(mm_status st) {
     switch (st) {
         case MM_OK: return "MM_OK";

@@ -41,9 +41,12 @@ const char *last_error_str();
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    mm_free_fn freefn = nullptr;  // the caller allocator that provided ptr (NULL: hipMalloc)
+    void *ctx = nullptr;
 };
 
 mm_status dev_alloc(DevBuf &b, size_t bytes);
+void set_allocator(mm_alloc_fn alloc, mm_free_fn free, void *ctx);
 mm_status dev_reserve(DevBuf &b, size_t bytes);  // grow-only
 void dev_free(DevBuf &b);
 

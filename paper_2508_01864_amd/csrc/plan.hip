@@ -39,15 +39,38 @@ void set_error(const char *fmt, ...) {
 void clear_error() { g_err.clear(); }
 const char *last_error_str() { return g_err.c_str(); }
 
+// Caller allocator (mm_set_allocator); NULL: hipMalloc / hipFree.
+static mm_alloc_fn g_alloc = nullptr;
+static mm_free_fn g_free = nullptr;
+static void *g_alloc_ctx = nullptr;
+
+void set_allocator(mm_alloc_fn alloc, mm_free_fn free, void *ctx) {
+    g_alloc = alloc;
+    g_free = free;
+    g_alloc_ctx = alloc ? ctx : nullptr;
+}
+
 mm_status dev_alloc(DevBuf &b, size_t bytes) {
     dev_free(b);
     if (bytes == 0) return MM_OK;
     void *ptr = nullptr;
-    hipError_t e = hipMalloc(&ptr, bytes);
-    if (e != hipSuccess) {
-        set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
-        (void)hipGetLastError();
-        return e == hipErrorOutOfMemory ? MM_ERR_NOMEM : MM_ERR_HIP;
+    if (g_alloc) {
+        ptr = g_alloc(bytes, nullptr, g_alloc_ctx);
+        if (!ptr) {
+            set_error("the caller allocator returned NULL for %zu bytes", bytes);
+            return MM_ERR_NOMEM;
+        }
+        b.freefn = g_free;
+        b.ctx = g_alloc_ctx;
+    } else {
+        hipError_t e = hipMalloc(&ptr, bytes);
+        if (e != hipSuccess) {
+            set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+            (void)hipGetLastError();
+            return e == hipErrorOutOfMemory ? MM_ERR_NOMEM : MM_ERR_HIP;
+        }
+        b.freefn = nullptr;
+        b.ctx = nullptr;
     }
     b.ptr = ptr;
     b.bytes = bytes;
@@ -60,9 +83,19 @@ mm_status dev_reserve(DevBuf &b, size_t bytes) {
 }
 
 void dev_free(DevBuf &b) {
-    if (b.ptr) (void)hipFree(b.ptr);
+    if (b.ptr) {
+        if (b.freefn) {
+            // hipFree waits for the device; keep that guarantee for the caller's allocator
+            (void)hipDeviceSynchronize();
+            b.freefn(b.ptr, nullptr, b.ctx);
+        } else {
+            (void)hipFree(b.ptr);
+        }
+    }
     b.ptr = nullptr;
     b.bytes = 0;
+    b.freefn = nullptr;
+    b.ctx = nullptr;
 }
 
 KParams kparams(const mm_kernel &k, int d) {

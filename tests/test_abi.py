@@ -18,6 +18,7 @@ HEADER = os.path.join(ROOT, "include", "maternmvm.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"typedef[^;]*;", "", text)          # function-pointer and struct typedefs
     names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
                        text, flags=re.M)
     return sorted(set(n for n in names if n not in ("if", "while", "return", "sizeof")))
@@ -105,3 +106,11 @@ def test_solver_entry_points_reject_null_handles_on_host():
     assert L.mm_solver_batch_set_schedule(None, 1, 1) == mm.MM_ERR_ARG
     assert L.mm_solver_batch_poll(None, None, None) == mm.MM_ERR_ARG
     assert L.mm_solver_batch_destroy(None) == mm.MM_OK
+
+
+def test_set_allocator_argument_rules_on_host():
+    L = mm.lib()
+    fn = ctypes.cast(mm._ALLOC_FN(lambda n, s, c: None), ctypes.c_void_p)
+    assert L.mm_set_allocator(fn, None, None) == mm.MM_ERR_ARG
+    assert "both" in mm.last_error()
+    assert L.mm_set_allocator(None, None, None) == mm.MM_OK
