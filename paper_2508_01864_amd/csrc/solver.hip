@@ -138,7 +138,64 @@ __global__ void cg_init_scalars_b(const CgDesc *ds, int nsol) {
     }
 }
 
-// Q = s2 (P + Y) + sigma2 P (Y = off-diagonal kernel sums of P), partial P.Q
+// alpha = r.z / p.Ap per active column from the p.Ap partials; non-positive
+// curvature = breakdown (one workgroup per solver)
+__device__ __forceinline__ void alpha_finish(const CgDesc &d, double *red, double *tot) {
+    reduce_cols(d.part, d.W, red, tot);
+    const int r = threadIdx.x;
+    if (r < d.W) {
+        const double s = tot[r];
+        double *c = d.sc + r * NS;
+        c[1] = s;
+        if (c[5] != 0.0) {
+            if (!(s > 0.0)) {
+                d.flags[1] = 1;
+                c[2] = 0.0;
+                c[5] = 0.0;
+            } else {
+                c[2] = c[0] / s;
+                const int it = (int)c[6];
+                if (d.tlog && it < d.tlog_cap) d.tlog[((int64_t)it * d.W + r) * 2] = c[2];
+                c[6] += 1.0;
+            }
+        } else {
+            c[2] = 0.0;
+        }
+    }
+    __syncthreads();
+}
+
+// beta = r.z(new) / r.z(old) from the r.r (and r.z) partials; columns reaching
+// the tolerance are frozen (one workgroup per solver)
+__device__ __forceinline__ void beta_finish(const CgDesc &d, double *red, double *tot, double *tz) {
+    reduce_cols(d.part, d.W, red, tot);
+    if (d.rank > 0) reduce_cols(d.part_rz, d.W, red, tz);
+    const int r = threadIdx.x;
+    if (r < d.W) {
+        const double s = tot[r];
+        const double rz = d.rank > 0 ? tz[r] : s;
+        double *c = d.sc + r * NS;
+        if (c[5] != 0.0) {
+            if (sqrt(s) <= d.rtol * c[4]) {
+                c[5] = 0.0;
+                c[3] = 0.0;
+            } else {
+                c[3] = rz / c[0];
+                const int it = (int)c[6] - 1;
+                if (d.tlog && it >= 0 && it < d.tlog_cap) d.tlog[((int64_t)it * d.W + r) * 2 + 1] = c[3];
+                atomicAdd(&d.flags[0], 1);  // integer count of still-active columns
+            }
+            c[7] = sqrt(s);
+            c[0] = rz;
+        } else {
+            c[3] = 0.0;
+        }
+    }
+    __syncthreads();
+}
+
+// Q = s2 (P + K~ P) + sigma2 P (K~ P: the product's off-diagonal sums) and
+// partial P.Q
 __global__ void cg_apply_b(const CgDesc *ds, const int2 *items, int nitems) {
     __shared__ double sm[BS];
     for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
@@ -154,8 +211,19 @@ __global__ void cg_apply_b(const CgDesc *ds, const int2 *items, int nitems) {
             if (d.nslab < 0) {
                 y = d.Y[e];
             } else {  // the product's per-pass partials, summed in pass order
+                // (loads issued four at a time, the additions stay in order)
                 y = 0.0;
-                for (int g = 0; g < d.nslab; ++g) y += d.slabs[(int64_t)g * len + e];
+                const double *sp = d.slabs + e;
+                int g = 0;
+                for (; g + 4 <= d.nslab; g += 4) {
+                    const double a0 = sp[(int64_t)g * len], a1 = sp[(int64_t)(g + 1) * len];
+                    const double a2 = sp[(int64_t)(g + 2) * len], a3 = sp[(int64_t)(g + 3) * len];
+                    y += a0;
+                    y += a1;
+                    y += a2;
+                    y += a3;
+                }
+                for (; g < d.nslab; ++g) y += sp[(int64_t)g * len];
             }
             const double q = fma(d.sigma2, p, d.s2 * (p + y));
             d.Q[e] = q;
@@ -165,35 +233,11 @@ __global__ void cg_apply_b(const CgDesc *ds, const int2 *items, int nitems) {
     }
 }
 
-// alpha = r.r / p.Ap per active column; non-positive curvature = breakdown
+// alpha for every solver
 __global__ void cg_alpha_b(const CgDesc *ds, int nsol) {
     __shared__ double red[BS];
     __shared__ double tot[64];
-    for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
-        const CgDesc d = ds[k];
-        reduce_cols(d.part, d.W, red, tot);
-        const int r = threadIdx.x;
-        if (r < d.W) {
-            const double s = tot[r];
-            double *c = d.sc + r * NS;
-            c[1] = s;
-            if (c[5] != 0.0) {
-                if (!(s > 0.0)) {
-                    d.flags[1] = 1;
-                    c[2] = 0.0;
-                    c[5] = 0.0;
-                } else {
-                    c[2] = c[0] / s;
-                    const int it = (int)c[6];
-                    if (d.tlog && it < d.tlog_cap) d.tlog[((int64_t)it * d.W + r) * 2] = c[2];
-                    c[6] += 1.0;
-                }
-            } else {
-                c[2] = 0.0;
-            }
-        }
-        __syncthreads();
-    }
+    for (int k = blockIdx.x; k < nsol; k += gridDim.x) alpha_finish(ds[k], red, tot);
 }
 
 // X += alpha P, R -= alpha Q, partial R.R
@@ -222,38 +266,12 @@ __global__ void cg_reset_active_b(const CgDesc *ds, int nsol) {
         ds[k].flags[0] = 0;
 }
 
-// beta = r.r(new) / r.r(old); columns reaching the tolerance are frozen
+// beta for every solver
 __global__ void cg_beta_b(const CgDesc *ds, int nsol) {
     __shared__ double red[BS];
     __shared__ double tot[64];
-    for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
-        const CgDesc d = ds[k];
-        reduce_cols(d.part, d.W, red, tot);
-        __shared__ double tz[64];
-        if (d.rank > 0) reduce_cols(d.part_rz, d.W, red, tz);
-        const int r = threadIdx.x;
-        if (r < d.W) {
-            const double s = tot[r];
-            const double rz = d.rank > 0 ? tz[r] : s;
-            double *c = d.sc + r * NS;
-            if (c[5] != 0.0) {
-                if (sqrt(s) <= d.rtol * c[4]) {
-                    c[5] = 0.0;
-                    c[3] = 0.0;
-                } else {
-                    c[3] = rz / c[0];
-                    const int it = (int)c[6] - 1;
-                    if (d.tlog && it >= 0 && it < d.tlog_cap) d.tlog[((int64_t)it * d.W + r) * 2 + 1] = c[3];
-                    atomicAdd(&d.flags[0], 1);  // integer count of still-active columns
-                }
-                c[7] = sqrt(s);
-                c[0] = rz;
-            } else {
-                c[3] = 0.0;
-            }
-        }
-        __syncthreads();
-    }
+    __shared__ double tz[64];
+    for (int k = blockIdx.x; k < nsol; k += gridDim.x) beta_finish(ds[k], red, tot, tz);
 }
 
 // P = R + beta P on active columns
@@ -264,10 +282,12 @@ __global__ void cg_dir_b(const CgDesc *ds, const int2 *items, int nitems) {
         const int64_t lo = (int64_t)it.y * CHUNK;
         const int64_t len = d.n * d.W;
         const int64_t hi = lo + CHUNK < len ? lo + CHUNK : len;
-        for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-            const int r = (int)(e % d.W);
-            if (d.sc[r * NS + 5] != 0.0) d.P[e] = fma(d.sc[r * NS + 3], d.P[e], d.rank > 0 ? d.Z[e] : d.R[e]);
-        }
+        // W divides CHUNK and the stride: the thread's column is fixed
+        const int r = (int)((lo + threadIdx.x) & (d.W - 1));
+        if (d.sc[r * NS + 5] == 0.0) continue;
+        const double be = d.sc[r * NS + 3];
+        const double *src = d.rank > 0 ? d.Z : d.R;
+        for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) d.P[e] = fma(be, d.P[e], src[e]);
     }
 }
 
