@@ -325,7 +325,11 @@ def bench_served(dev, count):
     reqs = [serve.Request(k, 0.0, p.x, p.y, mm.Kernel(p.two_nu, p.form, p.ell), p.sigma2, p.z,
                           rtol=1e-8, maxit=20000) for k, p in enumerate(probs)]
     # plain service times (all requests back to back) give the plain capacity
-    plain0 = serve.run_plain(reqs)
+    def done(tag):
+        return lambda r: log("%s: request %d (n=%d) done, %d iterations" % (tag, r.rid, len(reqs[r.rid].y),
+                                                                          r.info.get("iters", -1)))
+
+    plain0 = serve.run_plain(reqs, on_done=done("plain"))
     service = [r.done - r.admitted for r in plain0]
     cap = len(reqs) / sum(service)
     rate = 0.9 * cap
@@ -339,7 +343,7 @@ def bench_served(dev, count):
         free_at = start + sv
         plain.append(serve.Response(r.rid, r.arrival, start, free_at, None, None, None, {}))
     srv = serve.Server(chunk=16)
-    served = srv.run(reqs)
+    served = srv.run(reqs, on_done=done("served"))
     same = all(torch.equal(a.alpha, b.alpha) and torch.equal(a.mean, b.mean) for a, b in zip(served, plain0))
     sp, ss = serve.summary(plain), serve.summary(served)
     return {
@@ -366,7 +370,7 @@ def main():
     ap.add_argument("--no-mvm", action="store_true")
     ap.add_argument("--batched-count", type=int, default=256)
     ap.add_argument("--batched-iters", type=int, default=32)
-    ap.add_argument("--served-count", type=int, default=8)
+    ap.add_argument("--served-count", type=int, default=4)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--config3", action="store_true",

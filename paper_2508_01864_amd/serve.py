@@ -127,7 +127,8 @@ class Server:
         self.peak_bytes = 0
         self.peak_slots = 0
 
-    def run(self, requests: List[Request]) -> List[Response]:
+    def run(self, requests: List[Request], on_done=None) -> List[Response]:
+        """Serve the stream; on_done(response) is called as each request finishes."""
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         queue: collections.deque = collections.deque()
         live: Dict[int, _Live] = {}
@@ -198,6 +199,8 @@ class Server:
                         lv.plan.close()
                         out.append(Response(i, lv.req.arrival, lv.admitted, now(), alpha, beta, mean, info))
                         used -= lv.bytes
+                        if on_done is not None:
+                            on_done(out[-1])
         finally:
             if batch is not None:
                 batch.close()
@@ -207,7 +210,7 @@ class Server:
         return sorted(out, key=lambda r: r.rid)
 
 
-def run_plain(requests: List[Request], device=None) -> List[Response]:
+def run_plain(requests: List[Request], device=None, on_done=None) -> List[Response]:
     """Serve the stream one request at a time in arrival order (the plain
     path): plan, gp_cg_solve with fixed effects, gp_predict.  Service times are
     measured; a request starts when it has arrived and the previous one is
@@ -232,4 +235,6 @@ def run_plain(requests: List[Request], device=None) -> List[Response]:
         service = time.perf_counter() - t0
         free_at = start + service
         out.append(Response(r.rid, r.arrival, start, free_at, alpha, beta, mean, info))
+        if on_done is not None:
+            on_done(out[-1])
     return out
