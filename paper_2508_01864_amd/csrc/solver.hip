@@ -237,7 +237,10 @@ __global__ void cg_apply_b(const CgDesc *ds, const int2 *items, int nitems) {
 __global__ void cg_alpha_b(const CgDesc *ds, int nsol) {
     __shared__ double red[BS];
     __shared__ double tot[64];
-    for (int k = blockIdx.x; k < nsol; k += gridDim.x) alpha_finish(ds[k], red, tot);
+    for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
+        const CgDesc d = ds[k];
+        alpha_finish(d, red, tot);
+    }
 }
 
 // X += alpha P, R -= alpha Q, partial R.R
@@ -271,7 +274,10 @@ __global__ void cg_beta_b(const CgDesc *ds, int nsol) {
     __shared__ double red[BS];
     __shared__ double tot[64];
     __shared__ double tz[64];
-    for (int k = blockIdx.x; k < nsol; k += gridDim.x) beta_finish(ds[k], red, tot, tz);
+    for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
+        const CgDesc d = ds[k];
+        beta_finish(d, red, tot, tz);
+    }
 }
 
 // P = R + beta P on active columns
