@@ -137,7 +137,7 @@ mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int WB, h
         set_error("internal: width %d does not match the block %d", W, WB);
         return MM_ERR_ARG;
     }
-    return with_cfg(p->d, kp, WB, [&](auto t) {
+    return with_cfg(p->d, kp, WB, W, [&](auto t) {
         using C = typename decltype(t)::type;
         return run_passes<C>(p, vin, yacc, W, s);
     });
@@ -218,7 +218,7 @@ mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB,
     MM_TRY(upload(out.acc_items, ai));
     out.n_acc = (int)ai.size();
     for (auto &cl : out.classes) {
-        MM_TRY(with_cfg(cl.d, cl.kp, WB, [&](auto t) {
+        MM_TRY(with_cfg(cl.d, cl.kp, WB, W, [&](auto t) {
             using C = typename decltype(t)::type;
             const int ti = tile_index(C::T);
             std::vector<SweepArgs> descs;
@@ -260,7 +260,7 @@ mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB,
 
 mm_status sweep_batch_run(SweepBatch &b, hipStream_t s) {
     for (auto &cl : b.classes) {
-        MM_TRY(with_cfg(cl.d, cl.kp, b.WB, [&](auto t) {
+        MM_TRY(with_cfg(cl.d, cl.kp, b.WB, b.W, [&](auto t) {
             using C = typename decltype(t)::type;
             const SweepArgs *descs = static_cast<const SweepArgs *>(cl.descs.ptr);
             if (cl.n_agg > 0)

@@ -18,28 +18,28 @@ namespace mm {
 namespace {
 
 template <int D, int P, bool PROD, class F>
-mm_status with_gj(int gj, int WB, F &&f) {
+mm_status with_gj(int gj, int WB, int W, F &&f) {
     if constexpr (!PROD) {
         (void)gj;
-        return with_wb<D, P, false, D - 1>(WB, f);
+        return with_wb<D, P, false, D - 1>(WB, W, f);
     } else {
         if constexpr (D >= 3)
-            if (gj == 2) return with_wb<D, P, true, 2>(WB, f);
+            if (gj == 2) return with_wb<D, P, true, 2>(WB, W, f);
         if constexpr (D >= 2)
-            if (gj == 1) return with_wb<D, P, true, 1>(WB, f);
-        return with_wb<D, P, true, 0>(WB, f);
+            if (gj == 1) return with_wb<D, P, true, 1>(WB, W, f);
+        return with_wb<D, P, true, 0>(WB, W, f);
     }
 }
 
 template <int D, class F>
-mm_status with_p_gj(const KParams &kp, int gj, int WB, F &&f) {
-    if (kp.P == 1) return with_gj<D, 1, true>(gj, WB, f);
+mm_status with_p_gj(const KParams &kp, int gj, int WB, int W, F &&f) {
+    if (kp.P == 1) return with_gj<D, 1, true>(gj, WB, W, f);
     if constexpr (D == 1) {
-        if (kp.P == 2) return with_gj<D, 2, true>(gj, WB, f);
-        return with_gj<D, 3, true>(gj, WB, f);
+        if (kp.P == 2) return with_gj<D, 2, true>(gj, WB, W, f);
+        return with_gj<D, 3, true>(gj, WB, W, f);
     } else {
-        if (kp.P == 2) return kp.prod ? with_gj<D, 2, true>(gj, WB, f) : with_gj<D, 2, false>(gj, WB, f);
-        return kp.prod ? with_gj<D, 3, true>(gj, WB, f) : with_gj<D, 3, false>(gj, WB, f);
+        if (kp.P == 2) return kp.prod ? with_gj<D, 2, true>(gj, WB, W, f) : with_gj<D, 2, false>(gj, WB, W, f);
+        return kp.prod ? with_gj<D, 3, true>(gj, WB, W, f) : with_gj<D, 3, false>(gj, WB, W, f);
     }
 }
 
@@ -61,9 +61,9 @@ mm_status sweep_all_dl(mm_plan p, const double *vin, double *yacc, int W, int WB
             return run_passes<C>(p, vin, yacc, W, s, j > 0);
         };
         mm_status st;
-        if (d == 1) st = with_p_gj<1>(kp, gj, WB, run);
-        else if (d == 2) st = with_p_gj<2>(kp, gj, WB, run);
-        else st = with_p_gj<3>(kp, gj, WB, run);
+        if (d == 1) st = with_p_gj<1>(kp, gj, WB, W, run);
+        else if (d == 2) st = with_p_gj<2>(kp, gj, WB, W, run);
+        else st = with_p_gj<3>(kp, gj, WB, W, run);
         if (st != MM_OK) return st;
     }
     return MM_OK;
