@@ -223,6 +223,9 @@ struct Cfg {
     static constexpr int G = 2 * (D - 1);                    // staged geometry doubles
     // keep the targets' sums in registers over the sweep (runs of 4, small states)
     static constexpr bool REGOUT = E <= 4 && E * NSLOT <= 64;
+    // otherwise the targets' sums of the two directions (and sub-sweeps)
+    // gather in LDS and reach the pass's slab once, for up to 4 columns a wave
+    static constexpr bool LDSOUT = !REGOUT && WCOL <= 4;
     // elements per block of a run's loads.  Short runs take two blocks: with
     // one, the block loop disappears, every load of the run is hoisted and
     // the state spills (d = 3).  Long runs take blocks of 4 in d <= 2 (8 lifts
@@ -407,6 +410,12 @@ struct Smem {
     double geo[C::G > 0 ? C::G : 1][C::T];
 };
 
+// Targets' sums of the main launch gathered in LDS ([slot][column of the wave]).
+template <class C>
+struct Lout {
+    double v[C::LDSOUT ? C::T * C::WCOL : 1];
+};
+
 template <class C>
 __device__ __forceinline__ int slot(int j) {
     return (j % C::E) * C::RUNS + j / C::E;
@@ -555,7 +564,7 @@ template <class C, int MODE, int DIR>
 __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev &ps, const Smem<C> &sm,
                                               int hh, int64_t tile, int pl, int col, int run,
                                               const double (&vr)[C::REGOUT ? C::E : 1],
-                                              double (&outv)[C::REGOUT ? C::E : 1], double *slab) {
+                                              double (&outv)[C::REGOUT ? C::E : 1], double *slab, double *lout) {
     const int seg = 1 << (ps.seg_log2 < 30 ? ps.seg_log2 : 30);
     // runs per segment group (1 when segments fit in a run)
     const int Gr = seg <= C::E ? 1 : (seg >= C::T ? C::RUNS : seg / C::E);
@@ -692,18 +701,26 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                     vb[k] = valid ? lv : 0.0;
                     // the slab already holds this element's earlier values unless this is
                     // the first write of the pass (backward direction of sub-sweep 0)
-                    if (DIR == 0 || hh > 0) {
-                        const double lo = slab[ad];
-                        ob[k] = valid ? lo : 0.0;
-                    } else {
-                        ob[k] = 0.0;
+                    if constexpr (!C::LDSOUT) {
+                        if (DIR == 0 || hh > 0) {
+                            const double lo = slab[ad];
+                            ob[k] = valid ? lo : 0.0;
+                        } else {
+                            ob[k] = 0.0;
+                        }
                     }
                 }
 #pragma unroll
                 for (int k = 0; k < C::BLK; ++k) {
                     const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
                     const double val = scan_elem<C, DIR, true>(sm, S, e, b + k, run, hh, vb[k]);
-                    if (addr[k] >= 0) slab[addr[k]] = ob[k] + val;
+                    if constexpr (C::LDSOUT) {
+                        // this lane's own entry: no other lane touches it
+                        double &o = lout[(e * C::RUNS + run) * C::WCOL + threadIdx.x % C::WCOL];
+                        o = (DIR == 0 || hh > 0) ? o + val : val;
+                    } else {
+                        if (addr[k] >= 0) slab[addr[k]] = ob[k] + val;
+                    }
                 }
             }
         }
@@ -714,7 +731,7 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
 // the pass's slab.  MODE 1: tile aggregates of the passes whose segments span
 // several tiles.
 template <class C, int MODE>
-__device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, int64_t bx, int by) {
+__device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, double *lout, int64_t bx, int by) {
     int pass;
     int64_t tile;
     if constexpr (MODE == 0) {
@@ -746,8 +763,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, int6
 
 #pragma unroll 1
     for (int hh = 0; hh < C::NSUB; ++hh) {
-        run_direction<C, MODE, 1>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab);
-        run_direction<C, MODE, 0>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab);
+        run_direction<C, MODE, 1>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout);
+        run_direction<C, MODE, 0>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout);
     }
 
     if constexpr (MODE == 0 && C::REGOUT) {
@@ -757,12 +774,24 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, int6
             if (sm.flags[sj] & F_VALID) slab[(int64_t)sm.c[sj] * A.W + col] = outv[e];
         }
     }
+    if constexpr (MODE == 0 && C::LDSOUT) {
+        // one write of each target's sums to the pass's slab
+        for (int e = 0; e < C::E; ++e) {
+            const int sj = e * C::RUNS + run;
+            if (sm.flags[sj] & F_VALID) slab[(int64_t)sm.c[sj] * A.W + col] = lout[sj * C::WCOL + lane % C::WCOL];
+        }
+    }
 }
 
 template <class C, int MODE>
 __global__ __launch_bounds__(WAVE) void sweep_kernel(SweepArgs A) {
     __shared__ Smem<C> sm;
-    sweep_body<C, MODE>(A, sm, blockIdx.x, blockIdx.y);
+    if constexpr (MODE == 0 && C::LDSOUT) {
+        __shared__ Lout<C> lo;
+        sweep_body<C, MODE>(A, sm, lo.v, blockIdx.x, blockIdx.y);
+    } else {
+        sweep_body<C, MODE>(A, sm, nullptr, blockIdx.x, blockIdx.y);
+    }
 }
 
 // Batched: every item (problem, block x, block y) of a table runs the same body
@@ -770,10 +799,15 @@ __global__ __launch_bounds__(WAVE) void sweep_kernel(SweepArgs A) {
 template <class C, int MODE>
 __global__ __launch_bounds__(WAVE) void sweep_batch_kernel(const SweepArgs *descs, const int4 *items, int nitems) {
     __shared__ Smem<C> sm;
+    double *lout = nullptr;
+    if constexpr (MODE == 0 && C::LDSOUT) {
+        __shared__ Lout<C> lo;
+        lout = lo.v;
+    }
     for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
         const int4 it = items[i];
         const SweepArgs A = descs[it.x];
-        sweep_body<C, MODE>(A, sm, it.y, it.z);
+        sweep_body<C, MODE>(A, sm, lout, it.y, it.z);
         __syncthreads();
     }
 }
