@@ -148,6 +148,19 @@ constexpr int F_SIDE1 = 1;     // x1 half (d >= 2)
 constexpr int F_SIDE2 = 2;     // x2 half (d = 3)
 constexpr int F_VALID = 16;    // position < n
 
+// Accesses through the global address space.  The kernels read their pointers
+// from descriptors in memory, so the compiler cannot tell they are global and
+// would issue flat accesses, which also count against the LDS wait counter:
+// every wait for a staged LDS value would then wait for the gathers in flight.
+template <class T>
+__device__ __forceinline__ T gld(const T *p) {
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ __forceinline__ void gst(T *p, T v) {
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+
 // One divide-and-conquer pass as the kernels see it (device table).
 struct PassDev {
     const uint32_t *cf;   // canonical index | x1 half << 30 | x2 half << 31, in pass order
@@ -224,8 +237,12 @@ struct Cfg {
     // keep the targets' sums in registers over the sweep (runs of 4, small states)
     static constexpr bool REGOUT = E <= 4 && E * NSLOT <= 64;
     // otherwise the targets' sums of the two directions (and sub-sweeps)
-    // gather in LDS and reach the pass's slab once, for up to 4 columns a wave
-    static constexpr bool LDSOUT = !REGOUT && WCOL <= 4;
+    // gather per lane and reach the pass's slab once, for up to 4 columns a
+    // wave: in registers for d <= 2 (the run's block loop is unrolled so that
+    // every index is constant), in LDS for d = 3 (larger states)
+    static constexpr bool OUTREG = !REGOUT && WCOL <= 4 && D <= 2;
+    static constexpr bool LDSOUT = !REGOUT && !OUTREG && WCOL <= 4;
+    static constexpr bool SUMREG = REGOUT || OUTREG;   // outv holds the run's sums
     // elements per block of a run's loads.  Short runs take two blocks: with
     // one, the block loop disappears, every load of the run is hoisted and
     // the state spills (d = 3).  Long runs take blocks of 4 in d <= 2 (8 lifts
@@ -315,46 +332,56 @@ __device__ __forceinline__ void elem_vectors(const double *geo, ElemVec<C> &ev) 
     }
 }
 
+// S[c] += vc * source vector.
+template <class C>
+__device__ __forceinline__ void add_class(State<C> &S, int c, const ElemVec<C> &ev, double vc) {
+#pragma unroll
+    for (int h = 0; h < C::NTH; ++h) {
+        if constexpr (C::PROD) {
+            S.s[c][h][0] = fma(ev.f[h], vc, S.s[c][h][0]);
+        } else {
+#pragma unroll
+            for (int m = 0; m < C::P; ++m) S.s[c][h][m] = fma(ev.f[m], vc, S.s[c][h][m]);
+        }
+    }
+}
+
 // S[cls] += v * source vector.  The class is selected through the value
 // (v or 0) rather than a branch so the state stays in registers.
 template <class C>
 __device__ __forceinline__ void add_source(State<C> &S, int cls, const ElemVec<C> &ev, double v) {
 #pragma unroll
-    for (int c = 0; c < C::NCLS; ++c) {
-        const double vc = (c == cls) ? v : 0.0;
-#pragma unroll
-        for (int h = 0; h < C::NTH; ++h) {
-            if constexpr (C::PROD) {
-                S.s[c][h][0] = fma(ev.f[h], vc, S.s[c][h][0]);
-            } else {
-#pragma unroll
-                for (int m = 0; m < C::P; ++m) S.s[c][h][m] = fma(ev.f[m], vc, S.s[c][h][m]);
-            }
-        }
-    }
+    for (int c = 0; c < C::NCLS; ++c) add_class<C>(S, c, ev, (c == cls) ? v : 0.0);
 }
 
-// target vector . S[cls]
+// target vector . S[c]
+template <class C>
+__device__ __forceinline__ double target_dot(const State<C> &S, int c, const ElemVec<C> &ev) {
+    double acc = -0.0;  // -0 is the exact additive identity: the first term needs no addition
+#pragma unroll
+    for (int h = 0; h < C::NTH; ++h) {
+        if constexpr (C::PROD) {
+            // the kernel profile has c_0 = 1, the derivative profile e_0 = 0
+            double row = C::DSCAN ? 0.0 : S.s[c][h][0];
+#pragma unroll
+            for (int m = 1; m < C::P; ++m) row = fma(coef<C::PK, C::DSCAN>(m), S.s[c][h][m], row);
+            acc = fma(ev.g[h], row, acc);
+        } else {
+#pragma unroll
+            for (int m = 0; m < C::P; ++m) acc = fma(ev.g[m], S.s[c][h][m], acc);
+        }
+    }
+    return acc;
+}
+
+// target vector . S[cls] (0 for no class)
 template <class C>
 __device__ __forceinline__ double read_target(const State<C> &S, int cls, const ElemVec<C> &ev) {
     double out = 0.0;
 #pragma unroll
     for (int c = 0; c < C::NCLS; ++c) {
-        double acc = 0.0;
-#pragma unroll
-        for (int h = 0; h < C::NTH; ++h) {
-            if constexpr (C::PROD) {
-                // the kernel profile has c_0 = 1, the derivative profile e_0 = 0
-                double row = C::DSCAN ? 0.0 : S.s[c][h][0];
-#pragma unroll
-                for (int m = 1; m < C::P; ++m) row = fma(coef<C::PK, C::DSCAN>(m), S.s[c][h][m], row);
-                acc = fma(ev.g[h], row, acc);
-            } else {
-#pragma unroll
-                for (int m = 0; m < C::P; ++m) acc = fma(ev.g[m], S.s[c][h][m], acc);
-            }
-        }
-        out += (c == cls) ? acc : 0.0;
+        const double acc = target_dot<C>(S, c, ev);
+        out = (c == cls) ? acc : out;
     }
     return out;
 }
@@ -424,8 +451,8 @@ __device__ __forceinline__ int slot(int j) {
 // Scan coordinate of pass position p (0 <= p < n).
 template <class C>
 __device__ __forceinline__ double scan_coord(const SweepArgs &A, const PassDev &ps, int64_t p) {
-    if constexpr (C::D == 1) return A.xc[p];
-    else return ps.xs[p];
+    if constexpr (C::D == 1) return gld(A.xc + p);
+    else return gld(ps.xs + p);
 }
 
 // Stage the tile's positions: indices, flags, scan coordinate, offsets and
@@ -447,17 +474,19 @@ __device__ __forceinline__ void stage_tile(const SweepArgs &A, const PassDev &ps
                 c = pc;
             } else {
                 // sequential reads of the pass's stored geometry
-                const uint32_t cf = ps.cf[pc];
+                const uint32_t cf = gld(ps.cf + pc);
                 c = (int64_t)(cf & 0x3fffffffu);
                 flags |= (cf >> 30) & 1u ? F_SIDE1 : 0;
-                const double t1 = A.a * ps.w1[pc];
-                sm.geo[0][sj] = exp(-t1);
-                sm.geo[1][sj] = t1;
+                // past the end: zero geometry, i.e. zero source and target vectors
+                const bool in = p < n;
+                const double t1 = A.a * gld(ps.w1 + pc);
+                sm.geo[0][sj] = in ? exp(-t1) : 0.0;
+                sm.geo[1][sj] = in ? t1 : 0.0;
                 if constexpr (C::D == 3) {
                     flags |= (cf >> 31) ? F_SIDE2 : 0;
-                    const double t2 = A.a * ps.w2[pc];
-                    sm.geo[2][sj] = exp(-t2);
-                    sm.geo[3][sj] = t2;
+                    const double t2 = A.a * gld(ps.w2 + pc);
+                    sm.geo[2][sj] = in ? exp(-t2) : 0.0;
+                    sm.geo[3][sj] = in ? t2 : 0.0;
                 }
             }
             sm.c[sj] = (int32_t)c;
@@ -530,8 +559,6 @@ __device__ __forceinline__ double scan_elem(const Smem<C> &sm, State<C> &S, int 
                                             double v) {
     const int sj = e * C::RUNS + run;
     const int fl = sm.flags[sj];
-    int sc, tc;
-    classes<C>(fl, hh, sc, tc);
     // move the state from the previous position in the scan direction (the
     // anchor of any carry) with the staged decay and distance; both are 0 at a
     // segment start (forward) or past a segment end (backward), which restarts
@@ -548,8 +575,23 @@ __device__ __forceinline__ double scan_elem(const Smem<C> &sm, State<C> &S, int 
     ElemVec<C> ev;
     elem_vectors<C>(geo, ev);
     double out = 0.0;
-    if constexpr (TARGET) out = read_target<C>(S, tc, ev);
-    add_source<C>(S, sc, ev, v);
+    if constexpr (C::D == 2) {
+        // two classes, told apart by the x1 half alone: sources of half s
+        // feed the targets of half 1 - s.  A position past the end has zero
+        // staged geometry (a zero source vector), so it needs no class test.
+        const bool s1 = fl & F_SIDE1;
+        if constexpr (TARGET) {
+            const double t0 = target_dot<C>(S, 0, ev), t1 = target_dot<C>(S, 1, ev);
+            out = s1 ? t0 : t1;
+        }
+        add_class<C>(S, 0, ev, s1 ? 0.0 : v);
+        add_class<C>(S, 1, ev, s1 ? v : 0.0);
+    } else {
+        int sc, tc;
+        classes<C>(fl, hh, sc, tc);
+        if constexpr (TARGET) out = read_target<C>(S, tc, ev);
+        add_source<C>(S, sc, ev, v);
+    }
     return out;
 }
 
@@ -564,7 +606,7 @@ template <class C, int MODE, int DIR>
 __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev &ps, const Smem<C> &sm,
                                               int hh, int64_t tile, int pl, int col, int run,
                                               const double (&vr)[C::REGOUT ? C::E : 1],
-                                              double (&outv)[C::REGOUT ? C::E : 1], double *slab, double *lout) {
+                                              double (&outv)[C::SUMREG ? C::E : 1], double *slab, double *lout) {
     const int seg = 1 << (ps.seg_log2 < 30 ? ps.seg_log2 : 30);
     // runs per segment group (1 when segments fit in a run)
     const int Gr = seg <= C::E ? 1 : (seg >= C::T ? C::RUNS : seg / C::E);
@@ -595,10 +637,10 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
 #pragma unroll
                 for (int k = 0; k < C::BLK; ++k) {
                     // staged indices are clamped to valid points: load unconditionally
+                    // (a position past the end has no source class, so its value is unused)
                     const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
                     const int sj = e * C::RUNS + run;
-                    const double ld = vcol[(int64_t)sm.c[sj] * A.W];
-                    vb[k] = (sm.flags[sj] & F_VALID) ? ld : 0.0;
+                    vb[k] = gld(vcol + (int64_t)sm.c[sj] * A.W);
                 }
 #pragma unroll
                 for (int k = 0; k < C::BLK; ++k) {
@@ -646,16 +688,16 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                 tot.add_shifted(Frun, 1.0, 0.0);
                 double *dst = A.agg + agg_index<C>(A, DIR, pl, tile, col, hh);
 #pragma unroll
-                for (int k = 0; k < C::NSLOT; ++k) dst[k] = tot.flat()[k];
+                for (int k = 0; k < C::NSLOT; ++k) gst(dst + k, tot.flat()[k]);
                 if (col == 0 && hh == 0) {
                     const int64_t ai = ((int64_t)DIR * A.G + pl) * A.ntile + tile;
-                    A.anc[ai] = xend;
+                    gst(A.anc + ai, xend);
                     // decay across the tile from the previous tile's anchor; 1 for the
                     // segment's first tile in the scan direction (no predecessor)
                     const int64_t tps = seg / C::T;
                     const bool first = DIR == 0 ? (tile % tps) == 0 : (((tile + 1) % tps) == 0 || tile + 1 == A.ntile);
                     const double xo = sm.xedge[DIR == 0 ? 0 : 1];
-                    A.dec[ai] = first ? 1.0 : exp(-a * (DIR == 0 ? xend - xo : xo - xend));
+                    gst(A.dec + ai, first ? 1.0 : exp(-a * (DIR == 0 ? xend - xo : xo - xend)));
                 }
             }
             return;
@@ -668,8 +710,8 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                 State<C> cf;
                 const double *src = A.car + agg_index<C>(A, DIR, pl, tile, col, hh);
 #pragma unroll
-                for (int k = 0; k < C::NSLOT; ++k) cf.flat()[k] = src[k];
-                const double anc = A.anc[((int64_t)DIR * A.G + pl) * A.ntile + (DIR == 0 ? tile - 1 : tile + 1)];
+                for (int k = 0; k < C::NSLOT; ++k) cf.flat()[k] = gld(src + k);
+                const double anc = gld(A.anc + ((int64_t)DIR * A.G + pl) * A.ntile + (DIR == 0 ? tile - 1 : tile + 1));
                 if (run == (DIR == 0 ? 0 : C::RUNS - 1)) xex = anc;
                 const double t = a * (DIR == 0 ? xex - anc : anc - xex);
                 Ex.add_shifted(cf, exp(-t), t);
@@ -686,8 +728,7 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                 outv[e] += scan_elem<C, DIR, true>(sm, S, e, i, run, hh, vr[e]);
             }
         } else {
-#pragma unroll 1
-            for (int b = 0; b < C::E; b += C::BLK) {
+            auto block = [&](int b) {
                 double vb[C::BLK], ob[C::BLK];
                 int64_t addr[C::BLK];
 #pragma unroll
@@ -697,13 +738,12 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                     const bool valid = sm.flags[sj] & F_VALID;
                     const int64_t ad = (int64_t)sm.c[sj] * A.W + col;  // clamped: always in range
                     addr[k] = valid ? ad : -1;
-                    const double lv = A.vin[ad];
-                    vb[k] = valid ? lv : 0.0;
+                    vb[k] = gld(A.vin + ad);  // unused past the end (no source class)
                     // the slab already holds this element's earlier values unless this is
                     // the first write of the pass (backward direction of sub-sweep 0)
-                    if constexpr (!C::LDSOUT) {
+                    if constexpr (!C::LDSOUT && !C::OUTREG) {
                         if (DIR == 0 || hh > 0) {
-                            const double lo = slab[ad];
+                            const double lo = gld(slab + ad);
                             ob[k] = valid ? lo : 0.0;
                         } else {
                             ob[k] = 0.0;
@@ -714,15 +754,33 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                 for (int k = 0; k < C::BLK; ++k) {
                     const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
                     const double val = scan_elem<C, DIR, true>(sm, S, e, b + k, run, hh, vb[k]);
-                    if constexpr (C::LDSOUT) {
+                    if constexpr (C::OUTREG) {
+                        // ring slot of element e in this block (see the rotation below)
+                        const int q = DIR == 0 ? k : C::E - 1 - k;
+                        outv[q] = (DIR == 0 || hh > 0) ? outv[q] + val : val;
+                    } else if constexpr (C::LDSOUT) {
                         // this lane's own entry: no other lane touches it
                         double &o = lout[(e * C::RUNS + run) * C::WCOL + threadIdx.x % C::WCOL];
                         o = (DIR == 0 || hh > 0) ? o + val : val;
                     } else {
-                        if (addr[k] >= 0) slab[addr[k]] = ob[k] + val;
+                        if (addr[k] >= 0) gst(slab + addr[k], ob[k] + val);
                     }
                 }
-            }
+                if constexpr (C::OUTREG) {
+                    // The run's sums form a ring in registers, indexed by constants in
+                    // this rolled loop: a block works on the ring's first (forward) or
+                    // last (backward) BLK slots, then the ring turns by BLK toward
+                    // them.  After E / BLK blocks it has turned once, so slot e holds
+                    // element e again between directions.
+                    double r[C::E];
+#pragma unroll
+                    for (int i = 0; i < C::E; ++i) r[i] = outv[(i + (DIR == 0 ? C::BLK : C::E - C::BLK)) % C::E];
+#pragma unroll
+                    for (int i = 0; i < C::E; ++i) outv[i] = r[i];
+                }
+            };
+#pragma unroll 1
+            for (int b = 0; b < C::E; b += C::BLK) block(b);
         }
     }
 }
@@ -750,13 +808,16 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, doub
     stage_tile<C>(A, ps, sm, p0);
     double *slab = A.ypart + (int64_t)pl * A.n * A.W;
 
-    double vr[C::REGOUT ? C::E : 1], outv[C::REGOUT ? C::E : 1];
+    double vr[C::REGOUT ? C::E : 1], outv[C::SUMREG ? C::E : 1];
+    if constexpr (C::OUTREG) {
+#pragma unroll
+        for (int e = 0; e < C::E; ++e) outv[e] = 0.0;
+    }
     if constexpr (C::REGOUT) {
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
             const int sj = e * C::RUNS + run;
-            const double ld = A.vin[(int64_t)sm.c[sj] * A.W + col];  // clamped index
-            vr[e] = (sm.flags[sj] & F_VALID) ? ld : 0.0;
+            vr[e] = gld(A.vin + (int64_t)sm.c[sj] * A.W + col);  // clamped index; unused past the end
             outv[e] = 0.0;
         }
     }
@@ -767,18 +828,18 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, doub
         run_direction<C, MODE, 0>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout);
     }
 
-    if constexpr (MODE == 0 && C::REGOUT) {
+    if constexpr (MODE == 0 && C::SUMREG) {
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
             const int sj = e * C::RUNS + run;
-            if (sm.flags[sj] & F_VALID) slab[(int64_t)sm.c[sj] * A.W + col] = outv[e];
+            if (sm.flags[sj] & F_VALID) gst(slab + (int64_t)sm.c[sj] * A.W + col, outv[e]);
         }
     }
     if constexpr (MODE == 0 && C::LDSOUT) {
         // one write of each target's sums to the pass's slab
         for (int e = 0; e < C::E; ++e) {
             const int sj = e * C::RUNS + run;
-            if (sm.flags[sj] & F_VALID) slab[(int64_t)sm.c[sj] * A.W + col] = lout[sj * C::WCOL + lane % C::WCOL];
+            if (sm.flags[sj] & F_VALID) gst(slab + (int64_t)sm.c[sj] * A.W + col, lout[sj * C::WCOL + lane % C::WCOL]);
         }
     }
 }
@@ -856,10 +917,10 @@ __device__ __forceinline__ void carry_small(const SweepArgs &A, int pass, int64_
             for (int k = 0; k < 8; ++k) {
                 const bool in = b + k < nt;
                 const int64_t t = dir == 0 ? t0 + (in ? b + k : 0) : t1 - 1 - (in ? b + k : 0);
-                xb[k] = anc[t];
-                db[k] = dec[t];
+                xb[k] = gld(anc + t);
+                db[k] = gld(dec + t);
 #pragma unroll
-                for (int m = 0; m < C::P; ++m) gb[k][m] = in ? A.agg[off(t) + m] : 0.0;
+                for (int m = 0; m < C::P; ++m) gb[k][m] = in ? gld(A.agg + off(t) + m) : 0.0;
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
@@ -867,7 +928,7 @@ __device__ __forceinline__ void carry_small(const SweepArgs &A, int pass, int64_
                 const int64_t t = dir == 0 ? t0 + b + k : t1 - 1 - b - k;
                 if (b + k > 0) {
 #pragma unroll
-                    for (int m = 0; m < C::P; ++m) A.car[off(t) + m] = ex[m];
+                    for (int m = 0; m < C::P; ++m) gst(A.car + off(t) + m, ex[m]);
                     const double tt = a * (dir == 0 ? xb[k] - xw : xw - xb[k]);
                     mshift(ex, db[k], tt);
                 }
@@ -937,10 +998,10 @@ __device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int b
             for (int k = 0; k < 8; ++k) {  // loads first, then the dependent updates
                 const bool in = b + k < cnt;
                 const int64_t t = in ? cb0 + step * (b + k) : cb0;
-                xb[k] = anc[t];
-                db[k] = dec[t];
+                xb[k] = gld(anc + t);
+                db[k] = gld(dec + t);
 #pragma unroll
-                for (int m = 0; m < C::P; ++m) gb[k][m] = in ? A.agg[off(t) + m] : 0.0;
+                for (int m = 0; m < C::P; ++m) gb[k][m] = in ? gld(A.agg + off(t) + m) : 0.0;
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
@@ -1013,7 +1074,7 @@ __device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int b
                     for (int m = 0; m < C::P; ++m) ex[m] += g8[0][m];
                 } else {
 #pragma unroll
-                    for (int m = 0; m < C::P; ++m) A.car[off(t) + m] = ex[m];
+                    for (int m = 0; m < C::P; ++m) gst(A.car + off(t) + m, ex[m]);
                     const double tt = k == 0 ? a * (dir == 0 ? xs8[0] - xbefore : xbefore - xs8[0]) : tt8[k];
                     include(e8[k], tt, g8[k]);
                 }
@@ -1026,10 +1087,10 @@ __device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int b
                 for (int k = 0; k < 8; ++k) {
                     const bool in = b + k < cnt;
                     const int64_t t = in ? cb0 + step * (b + k) : cb0;
-                    xb[k] = anc[t];
-                    db[k] = dec[t];
+                    xb[k] = gld(anc + t);
+                    db[k] = gld(dec + t);
 #pragma unroll
-                    for (int m = 0; m < C::P; ++m) gb[k][m] = in ? A.agg[off(t) + m] : 0.0;
+                    for (int m = 0; m < C::P; ++m) gb[k][m] = in ? gld(A.agg + off(t) + m) : 0.0;
                 }
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
@@ -1040,7 +1101,7 @@ __device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int b
                         for (int m = 0; m < C::P; ++m) ex[m] += gb[k][m];
                     } else {
 #pragma unroll
-                        for (int m = 0; m < C::P; ++m) A.car[off(t) + m] = ex[m];
+                        for (int m = 0; m < C::P; ++m) gst(A.car + off(t) + m, ex[m]);
                         const double tt = a * (dir == 0 ? xb[k] - xw : xw - xb[k]);
                         include(db[k], tt, gb[k]);
                     }
@@ -1200,7 +1261,7 @@ template <int D, int P, bool PROD, int GJ = -1, class F>
 mm_status with_wb(int WB, int W, F &&f) {
     if (WB == 32) return f(Tag<Cfg<D, P, PROD, 32, 128, GJ>>{});
     if constexpr (D == 2)
-        if (WB == 4 && W >= 8) return f(Tag<Cfg<D, P, PROD, 4, 32, GJ>>{});
+        if (WB == 4 && W > 8) return f(Tag<Cfg<D, P, PROD, 4, 32, GJ>>{});
     if (WB == 4) return f(Tag<Cfg<D, P, PROD, 4, 16, GJ>>{});
     if (WB == 2) return f(Tag<Cfg<D, P, PROD, 2, 8, GJ>>{});
     return f(Tag<Cfg<D, P, PROD, 1, 4, GJ>>{});
