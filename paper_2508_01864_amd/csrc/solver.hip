@@ -18,9 +18,12 @@ namespace mm {
 namespace {
 
 constexpr int BS = 256;
+constexpr int WAVE = 64;   // lanes per wavefront
 constexpr int NRED = 1024;  // row blocks of the column dot products (fixed: deterministic sums)
-constexpr int NS = 8;      // scalars per column: [0] r.r [1] p.Ap [2] alpha [3] beta
+constexpr int NS = 10;     // scalars per column: [0] r.r [1] p.Ap [2] alpha [3] beta
                            // [4] |b| [5] active [6] iterations while active [7] |r|
+                           // [8] r.r and [9] active as the update left them (read by
+                           //     every workgroup of the direction step, which rewrites [0], [5])
 constexpr int CHUNK = 1024;
 constexpr int PUB = 1024;     // row blocks of the partial products L^T r (fixed: deterministic)
 constexpr int PC_MAXW = 8;    // columns of a preconditioned solver
@@ -29,7 +32,8 @@ static_assert(NRED % BS == 0, "whole row-block partials per thread in the scalar
 struct CgDesc {
     const double *B;
     double *X, *R, *P, *Q, *Y;
-    double *part;  // NRED x W partial column sums
+    double *part;  // NRED x W partial column sums (p.Ap of the apply step, |b|^2 at the start)
+    double *part2; // NRED x W partial r.r of the update step
     const double *slabs;  // per-pass partial products of P (nslab of n x W), or
     int nslab;            //   nslab < 0: the product is already summed in Y
     double *sc;    // W x NS
@@ -89,6 +93,34 @@ __device__ __forceinline__ void reduce_cols(const double *part, int W, double *r
     }
 }
 
+// The same sums for a workgroup that needs them for its own work: each thread
+// adds NRED/BS partials per column in a fixed order, each wave adds its lanes
+// by a fixed shuffle tree and the four wave sums are added in order.  Every
+// workgroup that calls it gets bitwise the same tot.  wred: 4 x 4 doubles.
+__device__ __forceinline__ void reduce_cols_w(const double *part, int W, double *wred, double *tot) {
+    const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
+    static_assert(BS == 4 * WAVE, "four waves per workgroup");
+    for (int r0 = 0; r0 < W; r0 += 4) {
+        double v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[q] = 0.0;
+            if (r0 + q < W)
+                for (int j = 0; j < NRED / BS; ++j) v[q] += part[(int64_t)(t + j * BS) * W + r0 + q];
+        }
+#pragma unroll
+        for (int o = WAVE / 2; o > 0; o >>= 1)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] += __shfl_down(v[q], o, WAVE);
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) wred[wv * 4 + q] = v[q];
+        __syncthreads();
+        if (t < 4 && r0 + t < W) tot[r0 + t] = ((wred[t] + wred[4 + t]) + wred[8 + t]) + wred[12 + t];
+        __syncthreads();
+    }
+}
+
 // x0 = 0, r0 = b, p0 = r0, partial |b|^2
 __global__ void cg_init_b(const CgDesc *ds, const int2 *items, int nitems) {
     __shared__ double sm[BS];
@@ -129,6 +161,8 @@ __global__ void cg_init_scalars_b(const CgDesc *ds, int nsol) {
             c[5] = (r < d.ncols && s > 0.0) ? 1.0 : 0.0;
             c[6] = 0.0;
             c[7] = sqrt(s);
+            c[8] = c[0];
+            c[9] = c[5];
         }
         if (r == 0) {
             d.flags[0] = 0;
@@ -138,60 +172,52 @@ __global__ void cg_init_scalars_b(const CgDesc *ds, int nsol) {
     }
 }
 
-// alpha = r.z / p.Ap per active column from the p.Ap partials; non-positive
-// curvature = breakdown (one workgroup per solver)
-__device__ __forceinline__ void alpha_finish(const CgDesc &d, double *red, double *tot) {
-    reduce_cols(d.part, d.W, red, tot);
-    const int r = threadIdx.x;
-    if (r < d.W) {
-        const double s = tot[r];
-        double *c = d.sc + r * NS;
-        c[1] = s;
-        if (c[5] != 0.0) {
-            if (!(s > 0.0)) {
-                d.flags[1] = 1;
-                c[2] = 0.0;
-                c[5] = 0.0;
-            } else {
-                c[2] = c[0] / s;
-                const int it = (int)c[6];
-                if (d.tlog && it < d.tlog_cap) d.tlog[((int64_t)it * d.W + r) * 2] = c[2];
-                c[6] += 1.0;
-            }
-        } else {
+// The scalars of column r after the alpha step (p.Ap = s); non-positive
+// curvature = breakdown.  Written by one workgroup per solver; the others
+// compute the same alpha from the same sums.  [8], [9] keep r.z and the active
+// flag for the direction step; the active-column count restarts.
+__device__ __forceinline__ void alpha_record(const CgDesc &d, int r, double s) {
+    double *c = d.sc + r * NS;
+    c[1] = s;
+    if (c[5] != 0.0) {
+        if (!(s > 0.0)) {
+            d.flags[1] = 1;
             c[2] = 0.0;
+            c[5] = 0.0;
+        } else {
+            c[2] = c[0] / s;
+            const int it = (int)c[6];
+            if (d.tlog && it < d.tlog_cap) d.tlog[((int64_t)it * d.W + r) * 2] = c[2];
+            c[6] += 1.0;
         }
+    } else {
+        c[2] = 0.0;
     }
-    __syncthreads();
+    c[8] = c[0];
+    c[9] = c[5];
+    if (r == 0) d.flags[0] = 0;
 }
 
-// beta = r.z(new) / r.z(old) from the r.r (and r.z) partials; columns reaching
-// the tolerance are frozen (one workgroup per solver)
-__device__ __forceinline__ void beta_finish(const CgDesc &d, double *red, double *tot, double *tz) {
-    reduce_cols(d.part, d.W, red, tot);
-    if (d.rank > 0) reduce_cols(d.part_rz, d.W, red, tz);
-    const int r = threadIdx.x;
-    if (r < d.W) {
-        const double s = tot[r];
-        const double rz = d.rank > 0 ? tz[r] : s;
-        double *c = d.sc + r * NS;
-        if (c[5] != 0.0) {
-            if (sqrt(s) <= d.rtol * c[4]) {
-                c[5] = 0.0;
-                c[3] = 0.0;
-            } else {
-                c[3] = rz / c[0];
-                const int it = (int)c[6] - 1;
-                if (d.tlog && it >= 0 && it < d.tlog_cap) d.tlog[((int64_t)it * d.W + r) * 2 + 1] = c[3];
-                atomicAdd(&d.flags[0], 1);  // integer count of still-active columns
-            }
-            c[7] = sqrt(s);
-            c[0] = rz;
-        } else {
+// The scalars of column r after the direction step (new r.r = s, r.z = rz):
+// beta = r.z(new) / r.z(old); columns reaching the tolerance are frozen.
+// Written by one workgroup per solver from the snapshots [8], [9].
+__device__ __forceinline__ void beta_record(const CgDesc &d, int r, double s, double rz) {
+    double *c = d.sc + r * NS;
+    if (c[9] != 0.0) {
+        if (sqrt(s) <= d.rtol * c[4]) {
+            c[5] = 0.0;
             c[3] = 0.0;
+        } else {
+            c[3] = rz / c[8];
+            const int it = (int)c[6] - 1;
+            if (d.tlog && it >= 0 && it < d.tlog_cap) d.tlog[((int64_t)it * d.W + r) * 2 + 1] = c[3];
+            atomicAdd(&d.flags[0], 1);  // integer count of still-active columns
         }
+        c[7] = sqrt(s);
+        c[0] = rz;
+    } else {
+        c[3] = 0.0;
     }
-    __syncthreads();
 }
 
 // Q = s2 (P + K~ P) + sigma2 P (K~ P: the product's off-diagonal sums) and
@@ -233,25 +259,25 @@ __global__ void cg_apply_b(const CgDesc *ds, const int2 *items, int nitems) {
     }
 }
 
-// alpha for every solver
-__global__ void cg_alpha_b(const CgDesc *ds, int nsol) {
-    __shared__ double red[BS];
-    __shared__ double tot[64];
-    for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
-        const CgDesc d = ds[k];
-        alpha_finish(d, red, tot);
-    }
-}
-
-// X += alpha P, R -= alpha Q, partial R.R
+// alpha = r.z / p.Ap per active column from the p.Ap partials (every
+// workgroup reduces them; the solver's first row block records the scalars),
+// then X += alpha P, R -= alpha Q and partial R.R
 __global__ void cg_update_b(const CgDesc *ds, const int2 *items, int nitems) {
     __shared__ double sm[BS];
+    __shared__ double wred[16];
+    __shared__ double tot[64];
     for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
         const int2 it = items[i];
         const CgDesc d = ds[it.x];
+        reduce_cols_w(d.part, d.W, wred, tot);
         int64_t lo, hi;
         row_range(d.n, it.y, lo, hi);
-        const double al = d.sc[(threadIdx.x % d.W) * NS + 2];
+        const int r = threadIdx.x % d.W;  // W divides BS: the thread's column is fixed
+        const double s = tot[r];
+        const double *c = d.sc + r * NS;
+        const double al = (c[5] != 0.0 && s > 0.0) ? c[0] / s : 0.0;
+        __syncthreads();  // every thread has read the scalars before they are recorded
+        if (it.y == 0 && (int)threadIdx.x < d.W) alpha_record(d, r, s);
         double acc = 0.0;
         for (int64_t e = lo * d.W + threadIdx.x; e < hi * d.W; e += BS) {
             const double xr = fma(al, d.P[e], d.X[e]);
@@ -260,38 +286,35 @@ __global__ void cg_update_b(const CgDesc *ds, const int2 *items, int nitems) {
             d.R[e] = rr;
             acc = fma(rr, rr, acc);
         }
-        block_col_sum(acc, d.W, sm, d.part, it.y);
+        block_col_sum(acc, d.W, sm, d.part2, it.y);
     }
 }
 
-__global__ void cg_reset_active_b(const CgDesc *ds, int nsol) {
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nsol; k += gridDim.x * blockDim.x)
-        ds[k].flags[0] = 0;
-}
-
-// beta for every solver
-__global__ void cg_beta_b(const CgDesc *ds, int nsol) {
-    __shared__ double red[BS];
+// beta = r.z(new) / r.z(old) from the r.r (and r.z) partials, columns reaching
+// the tolerance frozen (every workgroup reduces the partials; the solver's
+// first chunk records the scalars), then P = R + beta P (Z for R with a
+// preconditioner) on the still-active columns
+__global__ void cg_dir_b(const CgDesc *ds, const int2 *items, int nitems) {
+    __shared__ double wred[16];
     __shared__ double tot[64];
     __shared__ double tz[64];
-    for (int k = blockIdx.x; k < nsol; k += gridDim.x) {
-        const CgDesc d = ds[k];
-        beta_finish(d, red, tot, tz);
-    }
-}
-
-// P = R + beta P on active columns
-__global__ void cg_dir_b(const CgDesc *ds, const int2 *items, int nitems) {
     for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
         const int2 it = items[i];
         const CgDesc d = ds[it.x];
+        reduce_cols_w(d.part2, d.W, wred, tot);
+        if (d.rank > 0) reduce_cols_w(d.part_rz, d.W, wred, tz);
         const int64_t lo = (int64_t)it.y * CHUNK;
         const int64_t len = d.n * d.W;
         const int64_t hi = lo + CHUNK < len ? lo + CHUNK : len;
         // W divides CHUNK and the stride: the thread's column is fixed
         const int r = (int)((lo + threadIdx.x) & (d.W - 1));
-        if (d.sc[r * NS + 5] == 0.0) continue;
-        const double be = d.sc[r * NS + 3];
+        const double s = tot[r];
+        const double rz = d.rank > 0 ? tz[r] : s;
+        const double *c = d.sc + r * NS;
+        const bool on = c[9] != 0.0 && !(sqrt(s) <= d.rtol * c[4]);
+        const double be = on ? rz / c[8] : 0.0;
+        if (it.y == 0 && (int)threadIdx.x < d.W) beta_record(d, r, s, rz);
+        if (!on) continue;
         const double *src = d.rank > 0 ? d.Z : d.R;
         for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) d.P[e] = fma(be, d.P[e], src[e]);
     }
@@ -671,12 +694,8 @@ mm_status batch_enqueue(mm_solver_batch b, int iters, hipStream_t s) {
             for (SweepBatch &sb : b->sweeps) MM_TRY(sweep_batch_run(sb, s));
         }
         hipLaunchKernelGGL(cg_apply_b, dim3(pgrid(b->n_blk, b->grid_cap)), dim3(BS), 0, s, ds, ib, b->n_blk);
-        hipLaunchKernelGGL(cg_alpha_b, dim3(pgrid(nsol, 1024)), dim3(BS), 0, s, ds, nsol);
         hipLaunchKernelGGL(cg_update_b, dim3(pgrid(b->n_blk, b->grid_cap)), dim3(BS), 0, s, ds, ib, b->n_blk);
         if (b->n_pa > 0) MM_TRY(precond_enqueue(b, s, 0));
-        if (it == iters - 1)  // count the columns still active after the last iteration
-            hipLaunchKernelGGL(cg_reset_active_b, dim3(pgrid((nsol + BS - 1) / BS, 64)), dim3(BS), 0, s, ds, nsol);
-        hipLaunchKernelGGL(cg_beta_b, dim3(pgrid(nsol, 1024)), dim3(BS), 0, s, ds, nsol);
         hipLaunchKernelGGL(cg_dir_b, dim3(pgrid(b->n_chunk, b->grid_cap)), dim3(BS), 0, s, ds, ic, b->n_chunk);
     }
     hipLaunchKernelGGL(cg_collect_b, dim3(pgrid((nsol + BS - 1) / BS, 64)), dim3(BS), 0, s, ds, nsol,
@@ -1023,6 +1042,7 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
     d.Q = base + 4 * vec;
     d.Y = base + 5 * vec;
     d.part = base + 6 * vec;
+    d.part2 = d.part + (size_t)NRED * W;
     d.sc = d.part + (size_t)NRED * W * 8;
     d.flags = reinterpret_cast<int *>(d.sc + (size_t)W * NS);
     if (tlog_cap > 0) {
