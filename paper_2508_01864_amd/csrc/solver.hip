@@ -27,6 +27,11 @@ constexpr int NS = 10;     // scalars per column: [0] r.r [1] p.Ap [2] alpha [3]
 constexpr int CHUNK = 1024;
 constexpr int PUB = 1024;     // row blocks of the partial products L^T r (fixed: deterministic)
 constexpr int PC_MAXW = 8;    // columns of a preconditioned solver
+// Solvers of at most FUSE_W columns reduce the CG dot-product partials inside
+// every workgroup of the update and direction steps; wider ones have them
+// reduced once by a separate launch (a redundant reduction would read
+// NRED x W partials in each of the NRED workgroups).
+constexpr int FUSE_W = 8;
 static_assert(NRED % BS == 0, "whole row-block partials per thread in the scalar kernels");
 
 struct CgDesc {
@@ -34,6 +39,7 @@ struct CgDesc {
     double *X, *R, *P, *Q, *Y;
     double *part;  // NRED x W partial column sums (p.Ap of the apply step, |b|^2 at the start)
     double *part2; // NRED x W partial r.r of the update step
+    double *red;   // 3 x W reduced sums of wide solvers: p.Ap, r.r, r.z
     const double *slabs;  // per-pass partial products of P (nslab of n x W), or
     int nslab;            //   nslab < 0: the product is already summed in Y
     double *sc;    // W x NS
@@ -97,15 +103,17 @@ __device__ __forceinline__ void reduce_cols(const double *part, int W, double *r
 // adds NRED/BS partials per column in a fixed order, each wave adds its lanes
 // by a fixed shuffle tree and the four wave sums are added in order.  Every
 // workgroup that calls it gets bitwise the same tot.  wred: 4 x 4 doubles.
-__device__ __forceinline__ void reduce_cols_w(const double *part, int W, double *wred, double *tot) {
+__device__ __forceinline__ void reduce_cols_w(const double *part, int W, double *wred, double *tot, int c0 = 0,
+                                              int c1 = -1) {
     const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
     static_assert(BS == 4 * WAVE, "four waves per workgroup");
-    for (int r0 = 0; r0 < W; r0 += 4) {
+    if (c1 < 0) c1 = W;
+    for (int r0 = c0; r0 < c1; r0 += 4) {
         double v[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             v[q] = 0.0;
-            if (r0 + q < W)
+            if (r0 + q < c1)
                 for (int j = 0; j < NRED / BS; ++j) v[q] += part[(int64_t)(t + j * BS) * W + r0 + q];
         }
 #pragma unroll
@@ -116,7 +124,7 @@ __device__ __forceinline__ void reduce_cols_w(const double *part, int W, double 
 #pragma unroll
             for (int q = 0; q < 4; ++q) wred[wv * 4 + q] = v[q];
         __syncthreads();
-        if (t < 4 && r0 + t < W) tot[r0 + t] = ((wred[t] + wred[4 + t]) + wred[8 + t]) + wred[12 + t];
+        if (t < 4 && r0 + t < c1) tot[r0 + t] = ((wred[t] + wred[4 + t]) + wred[8 + t]) + wred[12 + t];
         __syncthreads();
     }
 }
@@ -259,6 +267,31 @@ __global__ void cg_apply_b(const CgDesc *ds, const int2 *items, int nitems) {
     }
 }
 
+// The CG sums of the solvers wider than FUSE_W, once per step: which = 0 the
+// p.Ap partials (before the update), 1 the r.r and r.z partials (before the
+// direction step).  Items: (solver, group of four columns).
+__global__ void cg_reduce_b(const CgDesc *ds, const int2 *items, int nitems, int which) {
+    __shared__ double wred[16];
+    __shared__ double tot[64];
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        const CgDesc d = ds[it.x];
+        const int c0 = 4 * it.y, c1 = c0 + 4 < d.W ? c0 + 4 : d.W;
+        if (which == 0) {
+            reduce_cols_w(d.part, d.W, wred, tot, c0, c1);
+            if ((int)threadIdx.x < c1 - c0) d.red[c0 + threadIdx.x] = tot[c0 + threadIdx.x];
+        } else {
+            reduce_cols_w(d.part2, d.W, wred, tot, c0, c1);
+            if ((int)threadIdx.x < c1 - c0) d.red[d.W + c0 + threadIdx.x] = tot[c0 + threadIdx.x];
+            if (d.rank > 0) {
+                reduce_cols_w(d.part_rz, d.W, wred, tot, c0, c1);
+                if ((int)threadIdx.x < c1 - c0) d.red[2 * d.W + c0 + threadIdx.x] = tot[c0 + threadIdx.x];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // alpha = r.z / p.Ap per active column from the p.Ap partials (every
 // workgroup reduces them; the solver's first row block records the scalars),
 // then X += alpha P, R -= alpha Q and partial R.R
@@ -269,11 +302,11 @@ __global__ void cg_update_b(const CgDesc *ds, const int2 *items, int nitems) {
     for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
         const int2 it = items[i];
         const CgDesc d = ds[it.x];
-        reduce_cols_w(d.part, d.W, wred, tot);
+        if (d.W <= FUSE_W) reduce_cols_w(d.part, d.W, wred, tot);
         int64_t lo, hi;
         row_range(d.n, it.y, lo, hi);
         const int r = threadIdx.x % d.W;  // W divides BS: the thread's column is fixed
-        const double s = tot[r];
+        const double s = d.W <= FUSE_W ? tot[r] : d.red[r];
         const double *c = d.sc + r * NS;
         const double al = (c[5] != 0.0 && s > 0.0) ? c[0] / s : 0.0;
         __syncthreads();  // every thread has read the scalars before they are recorded
@@ -301,15 +334,18 @@ __global__ void cg_dir_b(const CgDesc *ds, const int2 *items, int nitems) {
     for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
         const int2 it = items[i];
         const CgDesc d = ds[it.x];
-        reduce_cols_w(d.part2, d.W, wred, tot);
-        if (d.rank > 0) reduce_cols_w(d.part_rz, d.W, wred, tz);
+        const bool fused = d.W <= FUSE_W;
+        if (fused) {
+            reduce_cols_w(d.part2, d.W, wred, tot);
+            if (d.rank > 0) reduce_cols_w(d.part_rz, d.W, wred, tz);
+        }
         const int64_t lo = (int64_t)it.y * CHUNK;
         const int64_t len = d.n * d.W;
         const int64_t hi = lo + CHUNK < len ? lo + CHUNK : len;
         // W divides CHUNK and the stride: the thread's column is fixed
         const int r = (int)((lo + threadIdx.x) & (d.W - 1));
-        const double s = tot[r];
-        const double rz = d.rank > 0 ? tz[r] : s;
+        const double s = fused ? tot[r] : d.red[d.W + r];
+        const double rz = d.rank > 0 ? (fused ? tz[r] : d.red[2 * d.W + r]) : s;
         const double *c = d.sc + r * NS;
         const bool on = c[9] != 0.0 && !(sqrt(s) <= d.rtol * c[4]);
         const double be = on ? rz / c[8] : 0.0;
@@ -648,8 +684,8 @@ struct mm_solver_s {
 struct mm_solver_batch_s {
     std::vector<mm_solver> members;
     std::vector<SweepBatch> sweeps;      // one per distinct width among the members
-    DevBuf cg_desc, items_blk, items_chunk, status;
-    int n_blk = 0, n_chunk = 0;
+    DevBuf cg_desc, items_blk, items_chunk, items_red, status;
+    int n_blk = 0, n_chunk = 0, n_red = 0;  // n_red: (solver, column group) items of the wide members
     DevBuf items_pa, items_pu, items_pc;  // preconditioned members only
     int n_pa = 0, n_pu = 0, n_pc = 0;
     bool plain = false;                  // lone solver too large for a batch workspace
@@ -693,9 +729,12 @@ mm_status batch_enqueue(mm_solver_batch b, int iters, hipStream_t s) {
         } else {
             for (SweepBatch &sb : b->sweeps) MM_TRY(sweep_batch_run(sb, s));
         }
+        const int2 *ir = static_cast<const int2 *>(b->items_red.ptr);
         hipLaunchKernelGGL(cg_apply_b, dim3(pgrid(b->n_blk, b->grid_cap)), dim3(BS), 0, s, ds, ib, b->n_blk);
+        if (b->n_red > 0) hipLaunchKernelGGL(cg_reduce_b, dim3(pgrid(b->n_red, 1024)), dim3(BS), 0, s, ds, ir, b->n_red, 0);
         hipLaunchKernelGGL(cg_update_b, dim3(pgrid(b->n_blk, b->grid_cap)), dim3(BS), 0, s, ds, ib, b->n_blk);
         if (b->n_pa > 0) MM_TRY(precond_enqueue(b, s, 0));
+        if (b->n_red > 0) hipLaunchKernelGGL(cg_reduce_b, dim3(pgrid(b->n_red, 1024)), dim3(BS), 0, s, ds, ir, b->n_red, 1);
         hipLaunchKernelGGL(cg_dir_b, dim3(pgrid(b->n_chunk, b->grid_cap)), dim3(BS), 0, s, ds, ic, b->n_chunk);
     }
     hipLaunchKernelGGL(cg_collect_b, dim3(pgrid((nsol + BS - 1) / BS, 64)), dim3(BS), 0, s, ds, nsol,
@@ -706,7 +745,7 @@ mm_status batch_enqueue(mm_solver_batch b, int iters, hipStream_t s) {
 
 mm_status batch_build(mm_solver_batch b) {
     std::vector<CgDesc> descs;
-    std::vector<int2> ib, ic, ipa, ipu, ipc;
+    std::vector<int2> ib, ic, ir, ipa, ipu, ipc;
     std::vector<int> widths;
     for (size_t k = 0; k < b->members.size(); ++k) {
         mm_solver s = b->members[k];
@@ -722,6 +761,8 @@ mm_status batch_build(mm_solver_batch b) {
         if (w == widths.size()) widths.push_back(s->W);
         descs.push_back(s->desc);
         for (int blk = 0; blk < NRED; ++blk) ib.push_back(make_int2((int)k, blk));
+        if (s->W > FUSE_W)
+            for (int g = 0; 4 * g < s->W; ++g) ir.push_back(make_int2((int)k, g));
         if (s->desc.rank > 0) {
             for (int blk = 0; blk < PUB; ++blk) ipa.push_back(make_int2((int)k, blk));
             for (int e = 0; e < s->desc.rank * s->W; ++e) ipu.push_back(make_int2((int)k, e));
@@ -750,8 +791,10 @@ mm_status batch_build(mm_solver_batch b) {
     MM_TRY(upload_vec(b->cg_desc, descs));
     MM_TRY(upload_vec(b->items_blk, ib));
     MM_TRY(upload_vec(b->items_chunk, ic));
+    MM_TRY(upload_vec(b->items_red, ir));
     b->n_blk = (int)ib.size();
     b->n_chunk = (int)ic.size();
+    b->n_red = (int)ir.size();
     MM_TRY(upload_vec(b->items_pa, ipa));
     MM_TRY(upload_vec(b->items_pu, ipu));
     b->n_pu = (int)ipu.size();
@@ -770,6 +813,7 @@ void batch_free(mm_solver_batch b) {
     dev_free(b->cg_desc);
     dev_free(b->items_blk);
     dev_free(b->items_chunk);
+    dev_free(b->items_red);
     dev_free(b->items_pa);
     dev_free(b->items_pu);
     dev_free(b->items_pc);
@@ -1043,6 +1087,7 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
     d.Y = base + 5 * vec;
     d.part = base + 6 * vec;
     d.part2 = d.part + (size_t)NRED * W;
+    d.red = d.part + (size_t)2 * NRED * W;
     d.sc = d.part + (size_t)NRED * W * 8;
     d.flags = reinterpret_cast<int *>(d.sc + (size_t)W * NS);
     if (tlog_cap > 0) {
