@@ -239,7 +239,8 @@ mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB,
                 if (A.ntile > 1)
                     for (int sg = 0; sg < nseg; ++sg) {
                         const int4 g = p->seg_host[ti][sg];
-                        const int nby = (g.z - g.y <= CARRY_SMALL) ? (A.nslice + 255) / 256 : (A.nslice + 3) / 4;
+                        // (direction, slice) pairs: threads of one block, or one wave each
+                        const int nby = (g.z - g.y <= CARRY_SMALL) ? (2 * A.nslice + 255) / 256 : (2 * A.nslice + 3) / 4;
                         for (int by = 0; by < nby; ++by) ic.push_back(make_int4((int)m, sg, by, 0));
                     }
                 for (int64_t bx = 0; bx < (int64_t)npass * A.ntile; ++bx)

@@ -876,19 +876,23 @@ __global__ __launch_bounds__(WAVE) void sweep_batch_kernel(const SweepArgs *desc
 // Exclusive scans of the tile aggregates over the tiles of each segment, in
 // both directions: car[t] = the sum over the segment's tiles before t
 // (forward) or after t (backward) of their aggregates, moved to the anchor
-// next to t.  One wave per (segment, slice): a slice is one (sub-sweep,
-// class, channel row, column) P-vector.  Lanes take chunks of consecutive
-// tiles, scan them serially, join the chunks with a lane scan and write the
-// tiles' exclusive values.  `segs` lists (pass, first tile, end tile) of the
-// segments that span several tiles; blockIdx.x indexes them.
-// Segments of at most CARRY_SMALL tiles: one thread per slice scans the
-// segment's tiles serially (loads issued in blocks of 8 ahead of the updates).
+// next to t.  One wave per (segment, direction, slice): a slice is one
+// (sub-sweep, class, channel row, column) P-vector.  Lanes take chunks of
+// consecutive tiles, scan them serially, join the chunks with a lane scan and
+// write the tiles' exclusive values.  `segs` lists (pass, first tile, end
+// tile) of the segments that span several tiles; blockIdx.x indexes them.
+// Segments of at most CARRY_SMALL tiles: one thread per (direction, slice)
+// scans the segment's tiles serially (loads issued in blocks of 8 ahead of the
+// updates).
 constexpr int CARRY_SMALL = 16;
 
 template <class C>
 __device__ __forceinline__ void carry_small(const SweepArgs &A, int pass, int64_t t0, int64_t t1, int by) {
-    const int sl = by * 256 + (int)threadIdx.x;
-    if (sl >= A.nslice) return;
+    // one thread per (direction, slice): the two scan directions run side by side
+    const int sd = by * 256 + (int)threadIdx.x;
+    if (sd >= 2 * A.nslice) return;
+    const int dir = sd / A.nslice;
+    const int sl = sd - dir * A.nslice;
     const int pl = pass - A.g0;
     const int colw = sl % C::WCOL;
     const int rowcb = sl / C::WCOL;
@@ -900,8 +904,7 @@ __device__ __forceinline__ void carry_small(const SweepArgs &A, int pass, int64_
     const int col = cb * C::WCOL + colw;
     const double a = A.a;
     const int64_t nt = t1 - t0;
-#pragma unroll 1
-    for (int dir = 0; dir < 2; ++dir) {
+    {
         const int64_t base = ((int64_t)dir * A.G + pl) * A.ntile;
         const double *anc = A.anc + base;
         const double *dec = A.dec + base;
@@ -952,8 +955,11 @@ __device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int b
     }
     const int pl = pass - A.g0;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int sl = by * 4 + threadIdx.x / WAVE;
-    if (sl >= nslice) return;
+    // one wave per (direction, slice): the two scan directions run side by side
+    const int sd = by * 4 + threadIdx.x / WAVE;
+    if (sd >= 2 * nslice) return;
+    const int dir = sd / nslice;
+    const int sl = sd - dir * nslice;
     const int colw = sl % C::WCOL;
     const int rowcb = sl / C::WCOL;  // (column block, row)
     constexpr int ROWS = C::NSUB * C::NCLS * C::NTH;
@@ -970,8 +976,7 @@ __device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int b
     const int nact = (int)((nt + chunk - 1) / chunk);  // lanes holding tiles
     const bool active = lane < nact;
     const int64_t cnt = active ? hi - lo : 0;
-#pragma unroll 1
-    for (int dir = 0; dir < 2; ++dir) {
+    {
         const int64_t base = ((int64_t)dir * A.G + pl) * A.ntile;
         const double *anc = A.anc + base;
         const double *dec = A.dec + base;
@@ -1056,7 +1061,7 @@ __device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int b
                 ex[m] = has ? q : 0.0;
             }
         }
-        if (!active) continue;
+        if (!active) return;
         // ---- walk the chunk: each tile's carry is the running value anchored at the
         // previous tile's anchor; then the tile is included
         auto include = [&](double E, double tt, const double *g) {
@@ -1232,7 +1237,7 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
             A.nslice = nslice;
             A.segs = static_cast<const int4 *>(p->seg_tab[ti].ptr) + s0;
             if (s1 > s0)
-                hipLaunchKernelGGL((carry_kernel<C>), dim3((unsigned)(s1 - s0), (unsigned)((nslice + 3) / 4)),
+                hipLaunchKernelGGL((carry_kernel<C>), dim3((unsigned)(s1 - s0), (unsigned)((2 * nslice + 3) / 4)),
                                    dim3(256), 0, s, A);
         }
         hipEvent_t ev1 = nullptr;
