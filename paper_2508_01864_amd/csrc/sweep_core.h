@@ -354,6 +354,28 @@ __device__ __forceinline__ void add_source(State<C> &S, int cls, const ElemVec<C
     for (int c = 0; c < C::NCLS; ++c) add_class<C>(S, c, ev, (c == cls) ? v : 0.0);
 }
 
+// S[c] += M(E, t) (vc * source vector): a source entered at distance t
+// (decay E) from the state's anchor, in one step.  pw[m] = t^m / m!.
+template <class C>
+__device__ __forceinline__ void add_class_moved(State<C> &S, int c, const ElemVec<C> &ev, double vc, double E,
+                                                double t, const double (&pw)[C::P]) {
+    if constexpr (C::PROD) {
+        const double w = vc * E;
+#pragma unroll
+        for (int h = 0; h < C::NTH; ++h) {
+            const double g = ev.f[h] * w;
+            S.s[c][h][0] += g;
+#pragma unroll
+            for (int m = 1; m < C::P; ++m) S.s[c][h][m] = fma(g, pw[m], S.s[c][h][m]);
+        }
+    } else {
+        double q[C::P];
+#pragma unroll
+        for (int m = 0; m < C::P; ++m) q[m] = ev.f[m] * vc;
+        madd(S.s[c][0], q, E, t);
+    }
+}
+
 // target vector . S[c]
 template <class C>
 __device__ __forceinline__ double target_dot(const State<C> &S, int c, const ElemVec<C> &ev) {
@@ -595,6 +617,60 @@ __device__ __forceinline__ double scan_elem(const Smem<C> &sm, State<C> &S, int 
     return out;
 }
 
+// Both run aggregates of this lane's run in one walk over it (increasing
+// positions): Ff, anchored at the run's last position, by the state
+// recurrence of the forward direction; Fb, anchored at its first position,
+// adds each source moved by its distance and decay from that position, which
+// accumulate along the walk.  Only for runs inside one segment (segments
+// longer than a tile), so no staged decay inside the run is a restart.
+template <class C>
+__device__ __forceinline__ void run_aggregates(const SweepArgs &A, const Smem<C> &sm, int run, int col, int hh,
+                                               State<C> &Ff, State<C> &Fb) {
+    Ff.zero();
+    Fb.zero();
+    double D = 0.0, Ec = 1.0;  // a (x_e - x_first), exp(-D)
+    const double *vcol = A.vin + col;
+#pragma unroll 1
+    for (int b = 0; b < C::E; b += C::BLK) {
+        double vb[C::BLK];
+#pragma unroll
+        for (int k = 0; k < C::BLK; ++k) {
+            // clamped indices: a position past the end adds nothing
+            const int sj = (b + k) * C::RUNS + run;
+            vb[k] = gld(vcol + (int64_t)sm.c[sj] * A.W);
+        }
+#pragma unroll
+        for (int k = 0; k < C::BLK; ++k) {
+            const int e = b + k;
+            const int sj = e * C::RUNS + run;
+            scan_elem<C, 0, false>(sm, Ff, e, e, run, hh, vb[k]);
+            // the staged step into position e (from e - 1); none for the first
+            const double st = sm.st[sj], es = sm.est[sj];
+            D = e > 0 ? D + st : D;
+            Ec = e > 0 ? Ec * es : Ec;
+            double pw[C::P];
+            pw[0] = 1.0;
+#pragma unroll
+            for (int m = 1; m < C::P; ++m) pw[m] = pw[m - 1] * D * (1.0 / m);
+            double geo[C::G > 0 ? C::G : 1];
+            load_geo<C>(sm, sj, geo);
+            ElemVec<C> ev;
+            elem_vectors<C>(geo, ev);
+            const int fl = sm.flags[sj];
+            if constexpr (C::D == 2) {
+                const bool s1 = fl & F_SIDE1;
+                add_class_moved<C>(Fb, 0, ev, s1 ? 0.0 : vb[k], Ec, D, pw);
+                add_class_moved<C>(Fb, 1, ev, s1 ? vb[k] : 0.0, Ec, D, pw);
+            } else {
+                int sc, tc;
+                classes<C>(fl, hh, sc, tc);
+#pragma unroll
+                for (int c = 0; c < C::NCLS; ++c) add_class_moved<C>(Fb, c, ev, (c == sc) ? vb[k] : 0.0, Ec, D, pw);
+            }
+        }
+    }
+}
+
 // One scan direction over this lane's run, with every carry.
 // DIR 0: forward (increasing positions; sources at or before the target in
 //        the last coordinate: delta_last = +1);
@@ -606,7 +682,8 @@ template <class C, int MODE, int DIR>
 __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev &ps, const Smem<C> &sm,
                                               int hh, int64_t tile, int pl, int col, int run,
                                               const double (&vr)[C::REGOUT ? C::E : 1],
-                                              double (&outv)[C::SUMREG ? C::E : 1], double *slab, double *lout) {
+                                              double (&outv)[C::SUMREG ? C::E : 1], double *slab, double *lout,
+                                              const State<C> *Fpre = nullptr) {
     const int seg = 1 << (ps.seg_log2 < 30 ? ps.seg_log2 : 30);
     // runs per segment group (1 when segments fit in a run)
     const int Gr = seg <= C::E ? 1 : (seg >= C::T ? C::RUNS : seg / C::E);
@@ -621,10 +698,12 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
     double xex = xbeg;
 
     if (Gr > 1) {
-        // ---- run aggregate (anchored at xend)
+        // ---- run aggregate (anchored at xend); MODE 1 has both directions' already
         State<C> F;
         F.zero();
-        if constexpr (C::REGOUT) {
+        if constexpr (MODE == 1) {
+            F = *Fpre;
+        } else if constexpr (C::REGOUT) {
 #pragma unroll
             for (int i = 0; i < C::E; ++i) {
                 const int e = DIR == 0 ? i : C::E - 1 - i;
@@ -824,8 +903,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, doub
 
 #pragma unroll 1
     for (int hh = 0; hh < C::NSUB; ++hh) {
-        run_direction<C, MODE, 1>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout);
-        run_direction<C, MODE, 0>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout);
+        if constexpr (MODE == 1) {
+            State<C> Ff, Fb;
+            run_aggregates<C>(A, sm, run, col, hh, Ff, Fb);
+            run_direction<C, MODE, 1>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout, &Fb);
+            run_direction<C, MODE, 0>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout, &Ff);
+        } else {
+            run_direction<C, MODE, 1>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout);
+            run_direction<C, MODE, 0>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout);
+        }
     }
 
     if constexpr (MODE == 0 && C::SUMREG) {
