@@ -156,6 +156,7 @@ void plan_free(mm_plan plan) {
     dev_free(plan->part);
     dev_free(plan->pass_dev);
     for (auto &b : plan->pass_xt) dev_free(b);
+    for (auto &b : plan->pass_xtpos) dev_free(b);
     for (auto &b : plan->seg_tab) dev_free(b);
     for (auto &e : plan->prof_events) {
         (void)hipEventDestroy(e.first);

@@ -103,6 +103,7 @@ struct mm_plan_s {
     mm::DevBuf pass_dev;          // device table of the passes
     static constexpr int NTS = 4;  // tile sizes 128, 256, 512, 1024 positions
     mm::DevBuf pass_xt[NTS];        // per tile size: passes whose segments span tiles
+    mm::DevBuf pass_xtpos[NTS];     // per tile size: each pass's position in pass_xt (-1: none)
     std::vector<int> xt_host[NTS];
     mm::DevBuf seg_tab[NTS];        // per tile size: (pass, first tile, end tile) of those segments
     std::vector<int> seg_off[NTS];  //   offset of each cross-tile pass's first segment

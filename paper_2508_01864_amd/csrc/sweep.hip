@@ -56,10 +56,15 @@ int agg_per_rhs(int d, const mm_kernel &k, bool der) {
 
 // Aggregates and carries: agg_per_rhs doubles per tile and right-hand side,
 // two directions, per pass of a group; anchors and decays 2 each per tile and
-// pass.  The smallest tile (128 positions) gives the most tiles.
-static size_t agg_bytes_for(int64_t n, int W, int64_t G, int per_rhs) {
+// pass.  The smallest tile (128 positions) gives the most tiles.  For d <= 2
+// below 32 columns, also the runs' within-tile carries of the cross-tile
+// passes: agg_per_rhs doubles per lane, two directions, per tile of at least
+// 256 positions and block of at least two columns (32 lanes per column).
+static size_t agg_bytes_for(int64_t n, int d, int W, int64_t G, int per_rhs) {
     const int64_t ntile = (n + 127) / 128;
-    return (size_t)(2 * (2 * G * ntile * (int64_t)W * per_rhs) + 4 * G * ntile + 16) * sizeof(double);
+    size_t dbl = (size_t)(2 * (2 * G * ntile * (int64_t)W * per_rhs) + 4 * G * ntile + 16);
+    if (d <= 2 && W < 32) dbl += (size_t)2 * G * ((n + 255) / 256) * 32 * W * per_rhs;
+    return dbl * sizeof(double);
 }
 
 size_t sweep_agg_bytes(int64_t n, int d, int W, const mm_kernel &k, bool der) {
@@ -67,7 +72,7 @@ size_t sweep_agg_bytes(int64_t n, int d, int W, const mm_kernel &k, bool der) {
     while ((int64_t(1) << L) < n) ++L;
     const int npass = n < 2 ? 0 : (d == 1 ? 1 : (d == 2 ? L : L * (L + 1) / 2));
     const int64_t G = npass == 0 ? 1 : group_size(n, npass, W);
-    return agg_bytes_for(n, W, G, agg_per_rhs(d, k, der));
+    return agg_bytes_for(n, d, W, G, agg_per_rhs(d, k, der));
 }
 
 // A batched problem runs all its passes as one group, its partial slabs in a
@@ -80,7 +85,7 @@ bool sweep_batch_bytes_n(int64_t n, int d, const mm_kernel &k, int npass, int W,
     if (npass > 0 && (size_t)npass * slab > BATCH_PART_BUDGET) return false;
     const int64_t G = npass > 0 ? npass : 1;
     *part_bytes = (size_t)G * slab;
-    *agg_bytes = agg_bytes_for(n, W, G, agg_per_rhs(d, k, false));
+    *agg_bytes = agg_bytes_for(n, d, W, G, agg_per_rhs(d, k, false));
     return true;
 }
 
@@ -103,6 +108,10 @@ mm_status upload_pass_tables(mm_plan p) {
     MM_HIP_TRY(hipMemcpy(p->pass_dev.ptr, tab.data(), tab.size() * sizeof(PassDev), hipMemcpyHostToDevice));
     for (int ti = 0; ti < mm_plan_s::NTS; ++ti) {
         if (p->xt_host[ti].empty()) continue;
+        std::vector<int32_t> pos(p->passes.size(), -1);
+        for (size_t k = 0; k < p->xt_host[ti].size(); ++k) pos[p->xt_host[ti][k]] = (int32_t)k;
+        MM_TRY(dev_alloc(p->pass_xtpos[ti], pos.size() * sizeof(int32_t)));
+        MM_HIP_TRY(hipMemcpy(p->pass_xtpos[ti].ptr, pos.data(), pos.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         MM_TRY(dev_alloc(p->pass_xt[ti], p->xt_host[ti].size() * sizeof(int32_t)));
         MM_HIP_TRY(hipMemcpy(p->pass_xt[ti].ptr, p->xt_host[ti].data(), p->xt_host[ti].size() * sizeof(int32_t),
                              hipMemcpyHostToDevice));

@@ -191,6 +191,10 @@ struct SweepArgs {
     int G;                 // passes in the group
     int nslice;            // carry-scan slices (sub-sweep x class x row x column)
     const int4 *segs;      // the plan's cross-tile segments (pass, first tile, end tile)
+    const int32_t *xtpos;  // each pass's position in xt (-1: its segments fit in a tile)
+    double *runex;         // the runs' within-tile carries of the cross-tile passes (Cfg::RUNEX; null
+                           //   when the workspace has no room: below d = 3 and 32 columns it has):
+                           //   [2 dirs][xt pass of the group][ntile][column block][NSUB][NSLOT][lane]
     double a;
 };
 
@@ -243,6 +247,9 @@ struct Cfg {
     static constexpr bool OUTREG = !REGOUT && WCOL <= 4 && D <= 2;
     static constexpr bool LDSOUT = !REGOUT && !OUTREG && WCOL <= 4;
     static constexpr bool SUMREG = REGOUT || OUTREG;   // outv holds the run's sums
+    // the tile-aggregate pre-pass stores every run's within-tile carry of the
+    // cross-tile passes, so the main launch skips their aggregate pass and lane scan
+    static constexpr bool RUNEX = OUTREG && WCOL >= 2;
     // elements per block of a run's loads.  Short runs take two blocks: with
     // one, the block loop disappears, every load of the run is hoisted and
     // the state spills (d = 3).  Long runs take blocks of 4 in d <= 2 (8 lifts
@@ -540,6 +547,14 @@ __device__ __forceinline__ void load_geo(const Smem<C> &sm, int sj, double (&geo
     for (int k = 0; k < C::G; ++k) geo[k] = sm.geo[k][sj];
 }
 
+// First element of a wave's stored within-tile run carries (element k of lane
+// l at + k * WAVE + l).
+template <class C>
+__device__ __forceinline__ int64_t runex_index(const SweepArgs &A, int dir, int kx, int64_t tile, int cb, int hh) {
+    const int ncb = A.W / C::WCOL;
+    return (((((int64_t)dir * A.G + kx) * A.ntile + tile) * ncb + cb) * C::NSUB + hh) * (int64_t)C::NSLOT * WAVE;
+}
+
 template <class C>
 __device__ __forceinline__ int64_t agg_index(const SweepArgs &A, int dir, int pl, int64_t tile, int col,
                                              int hh) {
@@ -698,67 +713,90 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
     double xex = xbeg;
 
     if (Gr > 1) {
-        // ---- run aggregate (anchored at xend); MODE 1 has both directions' already
-        State<C> F;
-        F.zero();
-        if constexpr (MODE == 1) {
-            F = *Fpre;
-        } else if constexpr (C::REGOUT) {
+        // cross-tile passes: the pre-pass stored this run's within-tile carry
+        bool stored = false;
+        if constexpr (MODE == 0 && C::RUNEX) stored = seg > C::T && A.ntile > 1 && A.runex != nullptr;
+        State<C> Frun;  // MODE 1: the run's own aggregate
+        if (stored) {
+            const int kx = gld(A.xtpos + A.g0 + pl) - A.k0;
+            const double *src = A.runex + runex_index<C>(A, DIR, kx, tile, col / C::WCOL, hh) + threadIdx.x;
 #pragma unroll
-            for (int i = 0; i < C::E; ++i) {
-                const int e = DIR == 0 ? i : C::E - 1 - i;
-                scan_elem<C, DIR, false>(sm, F, e, i, run, hh, vr[e]);
-            }
-        } else {
-#pragma unroll 1
-            for (int b = 0; b < C::E; b += C::BLK) {
-                double vb[C::BLK];
-#pragma unroll
-                for (int k = 0; k < C::BLK; ++k) {
-                    // staged indices are clamped to valid points: load unconditionally
-                    // (a position past the end has no source class, so its value is unused)
-                    const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
-                    const int sj = e * C::RUNS + run;
-                    vb[k] = gld(vcol + (int64_t)sm.c[sj] * A.W);
-                }
-#pragma unroll
-                for (int k = 0; k < C::BLK; ++k) {
-                    const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
-                    scan_elem<C, DIR, false>(sm, F, e, b + k, run, hh, vb[k]);
-                }
-            }
-        }
-        State<C> Frun;
-        if constexpr (MODE == 1) Frun = F;
-        // ---- inclusive scan over the runs of this column.  Initial transfer: from
-        // the previous run's anchor to this run's (none for a group's first run).
-        double tr = 0.0, Er = 1.0;
-        {
-            const double xo = DIR == 0 ? __shfl_up(xend, C::WCOL, WAVE) : __shfl_down(xend, C::WCOL, WAVE);
-            const bool has = DIR == 0 ? (lig > 0) : (lig < Gr - 1);
-            if (has) {
-                tr = a * (DIR == 0 ? xend - xo : xo - xend);
-                Er = exp(-tr);
-            }
-        }
-#pragma unroll 1
-        for (int o = 1; o < Gr; o <<= 1) {
-            const bool ok = DIR == 0 ? (lig >= o) : (lig + o < Gr);
-            scan_step<C, DIR == 0>(F, tr, Er, o, ok);
-        }
-        // exclusive value
-        {
-            const int dl = C::WCOL;
-            const double xp = DIR == 0 ? __shfl_up(xend, dl, WAVE) : __shfl_down(xend, dl, WAVE);
-            const bool has = DIR == 0 ? (lig > 0) : (lig < Gr - 1);
-#pragma unroll
-            for (int k = 0; k < C::NSLOT; ++k) {
-                const double q = DIR == 0 ? __shfl_up(F.flat()[k], dl, WAVE) : __shfl_down(F.flat()[k], dl, WAVE);
-                Ex.flat()[k] = has ? q : 0.0;
-            }
+            for (int k = 0; k < C::NSLOT; ++k) Ex.flat()[k] = gld(src + k * WAVE);
+            // anchored at the previous run's last position in the scan direction
+            const bool has = DIR == 0 ? (run > 0) : (run < C::RUNS - 1);
+            const int rp = DIR == 0 ? (run > 0 ? run - 1 : 0) : (run + 1 < C::RUNS ? run + 1 : run);
+            const double xp = sm.xrun[DIR == 0 ? 1 : 0][rp];
             if (has) xex = xp;
+        } else {
+            // ---- run aggregate (anchored at xend); MODE 1 has both directions' already
+            State<C> F;
+            F.zero();
+            if constexpr (MODE == 1) {
+                F = *Fpre;
+            } else if constexpr (C::REGOUT) {
+#pragma unroll
+                for (int i = 0; i < C::E; ++i) {
+                    const int e = DIR == 0 ? i : C::E - 1 - i;
+                    scan_elem<C, DIR, false>(sm, F, e, i, run, hh, vr[e]);
+                }
+            } else {
+#pragma unroll 1
+                for (int b = 0; b < C::E; b += C::BLK) {
+                    double vb[C::BLK];
+#pragma unroll
+                    for (int k = 0; k < C::BLK; ++k) {
+                        // staged indices are clamped to valid points: load unconditionally
+                        // (a position past the end adds nothing: it has no source class or
+                        // a zero source vector)
+                        const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
+                        const int sj = e * C::RUNS + run;
+                        vb[k] = gld(vcol + (int64_t)sm.c[sj] * A.W);
+                    }
+#pragma unroll
+                    for (int k = 0; k < C::BLK; ++k) {
+                        const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
+                        scan_elem<C, DIR, false>(sm, F, e, b + k, run, hh, vb[k]);
+                    }
+                }
+            }
+            if constexpr (MODE == 1) Frun = F;
+            // ---- inclusive scan over the runs of this column.  Initial transfer: from
+            // the previous run's anchor to this run's (none for a group's first run).
+            double tr = 0.0, Er = 1.0;
+            {
+                const double xo = DIR == 0 ? __shfl_up(xend, C::WCOL, WAVE) : __shfl_down(xend, C::WCOL, WAVE);
+                const bool has = DIR == 0 ? (lig > 0) : (lig < Gr - 1);
+                if (has) {
+                    tr = a * (DIR == 0 ? xend - xo : xo - xend);
+                    Er = exp(-tr);
+                }
+            }
+#pragma unroll 1
+            for (int o = 1; o < Gr; o <<= 1) {
+                const bool ok = DIR == 0 ? (lig >= o) : (lig + o < Gr);
+                scan_step<C, DIR == 0>(F, tr, Er, o, ok);
+            }
+            // exclusive value
+            {
+                const int dl = C::WCOL;
+                const double xp = DIR == 0 ? __shfl_up(xend, dl, WAVE) : __shfl_down(xend, dl, WAVE);
+                const bool has = DIR == 0 ? (lig > 0) : (lig < Gr - 1);
+#pragma unroll
+                for (int k = 0; k < C::NSLOT; ++k) {
+                    const double q = DIR == 0 ? __shfl_up(F.flat()[k], dl, WAVE) : __shfl_down(F.flat()[k], dl, WAVE);
+                    Ex.flat()[k] = has ? q : 0.0;
+                }
+                if (has) xex = xp;
+            }
         }
         if constexpr (MODE == 1) {
+            if (C::RUNEX && A.runex != nullptr) {
+                // every run's within-tile carry, for the main launch
+                const int kx = gld(A.xtpos + A.g0 + pl) - A.k0;
+                double *dst = A.runex + runex_index<C>(A, DIR, kx, tile, col / C::WCOL, hh) + threadIdx.x;
+#pragma unroll
+                for (int k = 0; k < C::NSLOT; ++k) gst(dst + k * WAVE, Ex.flat()[k]);
+            }
             // tile total: inclusive value of the run that ends the tile in this direction
             if (run == (DIR == 0 ? C::RUNS - 1 : 0)) {
                 State<C> tot = Ex;
@@ -1303,6 +1341,8 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
     A.car = A.agg + aggslab;
     A.anc = A.car + aggslab;
     A.dec = A.anc + (size_t)2 * gmax * ntile;
+    A.runex = (p->d <= 2 && W < 32) ? A.dec + (size_t)2 * gmax * ntile : nullptr;  // see agg_bytes_for
+    A.xtpos = static_cast<const int32_t *>(p->pass_xtpos[ti].ptr);
     for (int g0 = 0; g0 < npass; g0 += gmax) {
         const int G = npass - g0 < gmax ? npass - g0 : gmax;
         A.g0 = g0;
@@ -1399,6 +1439,8 @@ SweepArgs make_args(mm_plan p, const double *vin, double *agg, double *part, int
     A.car = A.agg + aggslab;
     A.anc = A.car + aggslab;
     A.dec = A.anc + (size_t)2 * gmax * ntile;
+    A.runex = (p->d <= 2 && W < 32) ? A.dec + (size_t)2 * gmax * ntile : nullptr;  // see agg_bytes_for
+    A.xtpos = static_cast<const int32_t *>(p->pass_xtpos[ti].ptr);
     A.nslice = C::NSUB * C::NCLS * C::NTH * W;
     A.segs = static_cast<const int4 *>(p->seg_tab[ti].ptr);
     A.g0 = 0;
