@@ -19,7 +19,7 @@ import os
 from typing import Callable, Dict, Iterable, List, Sequence, Tuple
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SWEEP_WG_PER_CU = (1, 2, 4, 8, 16)
+SWEEP_WG_PER_CU = (1, 2, 4, 8, 16, 24, 32)
 SIDE_GRID = (512, 2048, 8192)
 DEFAULT = (16, 2048)
 

@@ -695,7 +695,8 @@ struct mm_solver_batch_s {
     int graph_iters = 0;
     int use_graph = 1;
     int grid_cap = 2048;                 // persistent grid of the CG step kernels
-    int wg_per_cu = 16;                  // persistent sweep grids: workgroups per compute unit
+    int wg_per_cu = 24;                  // persistent sweep grids: workgroups per compute unit
+                                         // (24 measured 1-2% faster than 16 for the d = 2 solves)
 };
 
 namespace mm {
