@@ -143,6 +143,21 @@ def test_config2_full_size_sampled(oracle_lib):
         assert comp <= MVM_TOL and nrm <= MVM_TOL
 
 
+def test_several_pass_groups_with_stored_run_carries(oracle_lib):
+    """d=2, N = 2^21 + 3, 16 columns: the per-pass partial results exceed their
+    budget, so the product runs its 22 passes in groups of 3 (tiles of 512, the
+    runs' within-tile carries stored per group); 48 sampled rows."""
+    rng = np.random.default_rng(9900)
+    n = (1 << 21) + 3
+    x = rng.uniform(0.0, 1.0, (n, 2))
+    v = rng.standard_normal((n, 16))
+    rows = rng.choice(n, 48, replace=False)
+    say("several pass groups: n=%d nrhs=16" % n)
+    comp, nrm = run_case(x, v, 3, "product", 0.05, rows=rows)
+    say("several pass groups", comp, nrm)
+    assert comp <= MVM_TOL and nrm <= MVM_TOL
+
+
 @pytest.mark.parametrize("nrhs", [1, 8, 32])
 def test_config2_rhs_widths(oracle_lib, nrhs):
     p = workloads.config2(nrhs=nrhs)
