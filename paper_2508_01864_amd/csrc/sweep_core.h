@@ -1379,10 +1379,10 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
 
 // Lane layout by the padded width W (a multiple of the block WB returned by
 // rhs_block): WCOL = WB columns per wave and runs of E = 256*WCOL/64
-// positions (tiles of 256 positions); in d = 2 with at least 8 columns the
-// 4-column blocks take runs of 32 (tiles of 512: measured 6-10% faster there,
-// slower in d = 1 and 3).  with_cfg calls f(Tag<Cfg<...>>) for the
-// configuration of (d, nu, form, WB, W).
+// positions (tiles of 256 positions); in d = 2 with more than 8 columns the
+// 4-column blocks take runs of 32 (tiles of 512: measured 5% faster at 16
+// columns, slower at 5 to 8 and in d = 1 and 3).  with_cfg calls
+// f(Tag<Cfg<...>>) for the configuration of (d, nu, form, WB, W).
 template <class C>
 struct Tag {
     using type = C;
