@@ -76,8 +76,13 @@ typedef struct {
 /* Outcome of a conjugate-gradient solve. */
 typedef struct {
     int32_t iters;           /* iterations performed (matrix-vector products of the loop) */
+    double relres_max;       /* max over columns of ||r_c|| / ||b_c|| at exit: the recurrence
+                                residual, or the recomputed one after a final check */
     int32_t converged_cols;  /* columns whose relative residual reached rtol */
-    double relres_max;       /* max over columns of ||r_c|| / ||b_c|| at exit (recurrence) */
+    double true_relres;      /* the residual recomputed with a fresh product at exit:
+                                ||y - H beta - (K + sigma2 I) alpha|| / ||y|| with fixed
+                                effects, else max_c ||b_c - (K + sigma2 I) x_c|| / ||b_c||;
+                                -1 when not computed (breakdown, calls without a check) */
 } mm_solve_info;
 
 /* Library version string. */
@@ -129,8 +134,11 @@ mm_status mm_plan_create(const double *x, int64_t n, int32_t d, int64_t ldx,
                          const mm_kernel *kernel, void *stream, mm_plan *out);
 
 /* Replace the kernel (nu, form, lengthscale, outputscale) of a plan; the
- * stored sorting outputs are kept. */
-mm_status mm_plan_set_kernel(mm_plan plan, const mm_kernel *kernel);
+ * stored sorting outputs are kept.  Later products on `stream` use the new
+ * kernel; the lengthscale factors are evaluated on chip by every product, so
+ * nothing is recomputed here and no work is enqueued.  MM_ERR_ARG while
+ * solvers or batches of the plan are alive. */
+mm_status mm_plan_set_kernel(mm_plan plan, const mm_kernel *kernel, void *stream);
 
 /* Point count and dimension of a plan (host). */
 mm_status mm_plan_info(mm_plan plan, int64_t *n, int32_t *d, mm_kernel *kernel);
@@ -178,16 +186,22 @@ mm_status matern_mvm_dlengthscale(mm_plan plan, const double *v, int64_t ldv, do
  * obtained from one multi-column CG over [y, H]; otherwise beta = 0.
  *   y        device, n targets (caller order)
  *   sigma2   noise variance > 0
- *   rtol     per-column stop test ||r_c|| <= rtol ||b_c|| on the recurrence residual
+ *   rtol     tolerance of the returned solution: the residual recomputed with
+ *            a fresh product, ||y - H beta - A alpha|| <= rtol ||y|| (with fixed
+ *            effects) or ||y - A alpha|| <= rtol ||y||.  Each column stops when its
+ *            recurrence residual reaches its tolerance (rtol at first); then the
+ *            residual is recomputed, and if it misses rtol the column tolerances
+ *            shrink and the iteration restarts from the recomputed residual
+ *            (residual replacement; at most 8 checks)
  *   maxit    iteration limit >= 1
  *   alpha    device, n outputs (caller order)
  *   beta     host, d+1 outputs, or NULL when fixed_effects == 0
- *   info     host, may be NULL
+ *   info     host, may be NULL (info->true_relres: the recomputed residual)
  * The L1 form with nu >= 3/2 and d >= 2 is not positive definite and is
  * refused with MM_ERR_NOTPD (the product form is; Appendix B).  Returns
- * MM_ERR_NOCONV after maxit iterations and MM_ERR_BREAKDOWN on a non-positive
- * curvature p^T A p; both still write the last iterate and info.
- * Synchronises.
+ * MM_ERR_NOCONV when maxit iterations end before the recomputed residual
+ * meets rtol, and MM_ERR_BREAKDOWN on a non-positive curvature p^T A p; both
+ * still write the last iterate and info.  Synchronises.
  */
 mm_status gp_cg_solve(mm_plan plan, const double *y, double sigma2, int32_t fixed_effects,
                       double rtol, int32_t maxit, double *alpha, double *beta,
@@ -199,8 +213,9 @@ mm_status gp_cg_solve(mm_plan plan, const double *y, double sigma2, int32_t fixe
  *   B     device, n x nrhs column-major, leading dimension ldb >= n
  *   X     device, n x nrhs column-major, leading dimension ldx >= n
  *   nrhs  1 <= nrhs <= 64
- * Columns are stopped independently (||r_c|| <= rtol ||b_c||).
- * Same status rules and synchronisation as gp_cg_solve.
+ * Columns are stopped independently; each must end with its recomputed
+ * residual ||b_c - A x_c|| <= rtol ||b_c|| (same checks and restarts, status
+ * rules and synchronisation as gp_cg_solve).
  */
 mm_status gp_cg_solve_multi(mm_plan plan, const double *B, int64_t ldb, int32_t nrhs,
                             double sigma2, double rtol, int32_t maxit, double *X, int64_t ldx,
@@ -318,9 +333,27 @@ mm_status mm_solver_iterate(mm_solver solver, int32_t iters, void *stream);
 mm_status mm_solver_poll(mm_solver solver, int32_t *active_cols, int32_t *breakdown,
                          mm_solve_info *info, void *stream);
 
+/* Residual check of gp_cg_solve on the current iterate (Appendix A,
+ * Algorithm 2; with fixed effects the Section 3.2 combination): the residual
+ * recomputed with one fresh product, ||y - H beta - A alpha|| / ||y|| (fixed
+ * effects) or max_c ||b_c - A x_c|| / ||b_c||, into *true_relres.  The solver
+ * restarts from it (R = B - A X; the next direction is the residual, or its
+ * preconditioned image).  *passed = 1 when it meets rtol: every column is
+ * then frozen and further iterations change nothing.  Otherwise, when tighten
+ * is nonzero and every column had converged by the recurrence, the column
+ * tolerances shrink by 0.5 rtol / true_relres (clamped to [0.05, 0.5]) and
+ * the missing columns (all columns with fixed effects) continue under
+ * mm_solver_iterate.  The iterate X itself is unchanged.  Outputs may be NULL.
+ * Synchronises. */
+mm_status mm_solver_check(mm_solver solver, int32_t tighten, int32_t *passed, double *true_relres,
+                          void *stream);
+
 /* Write alpha (device, n, caller order) and beta (host, d+1, fixed effects
  * only) from the current iterate, with the status rules of gp_cg_solve
- * (MM_ERR_NOCONV / MM_ERR_BREAKDOWN still write the outputs).  Synchronises. */
+ * (MM_ERR_NOCONV / MM_ERR_BREAKDOWN still write the outputs).  Unless the
+ * iterate was checked since its last iteration, the residual is recomputed
+ * first as by mm_solver_check without tightening (info->true_relres).
+ * Synchronises. */
 mm_status mm_solver_finish(mm_solver solver, double *alpha, double *beta, mm_solve_info *info,
                            void *stream);
 

@@ -52,8 +52,8 @@ class _MMKernel(ctypes.Structure):
 
 
 class _MMSolveInfo(ctypes.Structure):
-    _fields_ = [("iters", ctypes.c_int32), ("converged_cols", ctypes.c_int32),
-                ("relres_max", ctypes.c_double)]
+    _fields_ = [("iters", ctypes.c_int32), ("relres_max", ctypes.c_double),
+                ("converged_cols", ctypes.c_int32), ("true_relres", ctypes.c_double)]
 
 
 class _MMLmlInfo(ctypes.Structure):
@@ -75,7 +75,7 @@ _SIGS = {
                                                   ctypes.POINTER(_MMKernel)]),
     "mm_plan_create": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
                                       ctypes.POINTER(_MMKernel), _P, ctypes.POINTER(_P)]),
-    "mm_plan_set_kernel": (ctypes.c_int, [_P, ctypes.POINTER(_MMKernel)]),
+    "mm_plan_set_kernel": (ctypes.c_int, [_P, ctypes.POINTER(_MMKernel), _P]),
     "mm_plan_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(_MMKernel)]),
     "mm_plan_destroy": (ctypes.c_int, [_P]),
@@ -115,6 +115,8 @@ _SIGS = {
     "mm_solver_iterate": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "mm_solver_poll": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(_MMSolveInfo), _P]),
+    "mm_solver_check": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_double), _P]),
     "mm_solver_finish": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(_MMSolveInfo), _P]),
     "mm_solver_destroy": (ctypes.c_int, [_P]),
@@ -272,7 +274,7 @@ class Plan:
 
     def set_kernel(self, kernel: Kernel):
         k = kernel.c()
-        _check(lib().mm_plan_set_kernel(self._h, ctypes.byref(k)))
+        _check(lib().mm_plan_set_kernel(self._h, ctypes.byref(k), _stream_ptr(self._stream)))
         self.kernel = kernel
 
     def mvm(self, v, shift: float = 0.0, out=None):
@@ -356,8 +358,7 @@ class Plan:
         msg = last_error()
         if st != MM_OK and raise_on_error:
             raise MaternError(st, msg)
-        out = {"iters": info.iters, "converged_cols": info.converged_cols,
-               "relres_max": info.relres_max, "status": STATUS_NAMES[st]}
+        out = _info_dict(info, st)
         return alpha, (np.array(beta[:]) if fixed_effects else None), out
 
     def cg_solve_multi(self, B, sigma2: float, rtol: float = 1e-8, maxit: int = 20000,
@@ -375,8 +376,7 @@ class Plan:
         msg = last_error()
         if st != MM_OK and raise_on_error:
             raise MaternError(st, msg)
-        out = {"iters": info.iters, "converged_cols": info.converged_cols,
-               "relres_max": info.relres_max, "status": STATUS_NAMES[st]}
+        out = _info_dict(info, st)
         return (Xc.view(-1) if B.dim() == 1 else Xc.t()), out
 
     def predict(self, alpha, z, beta=None):
@@ -412,8 +412,7 @@ class Plan:
         msg = last_error()
         if st != MM_OK and raise_on_error:
             raise MaternError(st, msg)
-        return var, {"iters": info.iters, "converged_cols": info.converged_cols,
-                     "relres_max": info.relres_max, "status": STATUS_NAMES[st]}
+        return var, _info_dict(info, st)
 
     def logdet(self, sigma2: float, probes, steps: int = 200, rtol: float = 0.0):
         """Stochastic log det(K + sigma2 I) from CG-Lanczos quadratures of the probe
@@ -442,7 +441,7 @@ class Plan:
 
 def _info_dict(info: _MMSolveInfo, st: int) -> dict:
     return {"iters": info.iters, "converged_cols": info.converged_cols,
-            "relres_max": info.relres_max, "status": STATUS_NAMES[st]}
+            "relres_max": info.relres_max, "true_relres": info.true_relres, "status": STATUS_NAMES[st]}
 
 
 class Solver:
@@ -477,6 +476,17 @@ class Solver:
         _check(lib().mm_solver_poll(self._h, ctypes.byref(act), ctypes.byref(brk), ctypes.byref(info),
                                     _stream_ptr(self._stream)))
         return act.value, brk.value, _info_dict(info, MM_OK)
+
+    def check(self, tighten: bool = True):
+        """Recompute the residual of the current iterate with a fresh product and
+        restart from it (mm_solver_check).  Returns (passed, true relative
+        residual); when it misses rtol and tighten is set, the column tolerances
+        shrink and further iterations continue the solve."""
+        ok = ctypes.c_int32()
+        rel = ctypes.c_double()
+        _check(lib().mm_solver_check(self._h, 1 if tighten else 0, ctypes.byref(ok), ctypes.byref(rel),
+                                     _stream_ptr(self._stream)))
+        return bool(ok.value), rel.value
 
     def finish(self, raise_on_error: bool = True):
         """(alpha, beta or None, info) from the current iterate."""
@@ -630,17 +640,20 @@ class MvmBatch:
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
-_allocator_refs = None
+# Every callback pair ever registered, kept for the life of the process: a
+# buffer returns to the allocator that provided it, so a plan, solver or batch
+# created under one pair still calls that pair's free thunk after a switch.
+_allocator_refs = []
 
 
 def use_torch_allocator(on: bool = True):
     """Route every device buffer of the library through torch's caching
-    allocator (mm_set_allocator), or back to hipMalloc with on=False.  Call
-    while no library objects are being created or destroyed."""
-    global _allocator_refs
+    allocator (mm_set_allocator), or back to hipMalloc with on=False.  Objects
+    created before a switch keep freeing through the allocator that gave them
+    their buffers (its callbacks are never released).  Call while no library
+    objects are being created or destroyed."""
     if not on:
         _check(lib().mm_set_allocator(None, None, None))
-        _allocator_refs = None
         return
     torch = _torch()
 
@@ -654,9 +667,9 @@ def use_torch_allocator(on: bool = True):
         torch.cuda.caching_allocator_delete(int(ptr))
 
     refs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _allocator_refs.append(refs)
     _check(lib().mm_set_allocator(ctypes.cast(refs[0], ctypes.c_void_p), ctypes.cast(refs[1], ctypes.c_void_p),
                                   None))
-    _allocator_refs = refs            # the callbacks must outlive their registration
 
 
 def lanczos_logquad(alpha, beta) -> float:

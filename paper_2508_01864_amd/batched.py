@@ -7,7 +7,9 @@ kernel configuration and sweep phase, and every CG vector update in one launch
 per step, replayed from a HIP graph.  Solvers that converge are dropped from
 the batch once they make up a set fraction of its work, so finished problems
 stop costing launches.  A problem's iterates do not depend on its batch-mates:
-the result equals gp_cg_solve on that problem alone, bit for bit.
+the result equals gp_cg_solve on that problem alone, bit for bit (a solver
+that converges by its recurrence has its residual recomputed and, if that
+misses rtol, restarts with tighter tolerances, exactly as gp_cg_solve does).
 """
 from __future__ import annotations
 
@@ -86,7 +88,15 @@ def solve_many(plans: List[Plan], ys, sigma2s, fixed_effects: bool = False, rtol
             now = time.perf_counter() - t0
             for i, st in zip(members, status):
                 taken[i] += k
-                if not finished[i] and (st <= 0 or taken[i] >= maxit):
+                if finished[i]:
+                    continue
+                if st == 0 and taken[i] < maxit:
+                    # converged by the recurrence: recompute the residual; a miss
+                    # restarts the solver with tighter tolerances (it stays active)
+                    passed, _ = solvers[i].check(tighten=True)
+                    if not passed:
+                        continue
+                if st <= 0 or taken[i] >= maxit:
                     finished[i] = True
                     done_at[i] = now
             active = [i for i in members if not finished[i]]

@@ -25,39 +25,16 @@ inline unsigned grid1(int64_t n) {
 // layout conversion between the caller's column-major vectors and the
 // point-major canonical work layout (row c = canonical point, W columns)
 // ---------------------------------------------------------------------------
-__global__ void gather_in_kernel(const double *v, int64_t ldv, int nrhs, const int32_t *perm,
-                                 int64_t n, double *vin, int W) {
+// y[r * ldy + i] = scale * yacc[iperm[i], r]: the derivative product has no
+// diagonal term (threads take (caller point, column), column fastest)
+__global__ void scale_out_kernel(const double *yacc, int W, int nrhs, const int32_t *iperm, int64_t n,
+                                 double scale, double *y, int64_t ldy) {
     const int64_t total = n * W;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = e / W;
-        const int r = (int)(e - c * W);
-        vin[e] = r < nrhs ? v[(int64_t)r * ldv + perm[c]] : 0.0;
-    }
-}
-
-__global__ void scatter_out_kernel(const double *vin, const double *yacc, int W, int nrhs,
-                                   const int32_t *perm, int64_t n, double s2, double shift,
-                                   double *y, int64_t ldy) {
-    const int64_t total = n * nrhs;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int r = (int)(e / n);
-        const int64_t c = e - (int64_t)r * n;
-        const double vv = vin[c * W + r];
-        y[(int64_t)r * ldy + perm[c]] = fma(shift, vv, s2 * (vv + yacc[c * W + r]));
-    }
-}
-
-// y[perm[c], r] = scale * yacc[c, r]: the derivative product has no diagonal term
-__global__ void scale_out_kernel(const double *yacc, int W, int nrhs, const int32_t *perm, int64_t n,
-                                 double scale, double *y, int64_t ldy) {
-    const int64_t total = n * nrhs;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int r = (int)(e / n);
-        const int64_t c = e - (int64_t)r * n;
-        y[(int64_t)r * ldy + perm[c]] = scale * yacc[c * W + r];
+        const int64_t i = e / W;
+        const int r = (int)(e - i * W);
+        if (r < nrhs) y[(int64_t)r * ldy + i] = scale * yacc[(int64_t)iperm[i] * W + r];
     }
 }
 
@@ -89,17 +66,101 @@ __global__ void predict_out_kernel(const double *out, int64_t n, int64_t m, cons
 }
 
 
-}  // namespace
-
-void launch_gather_in(const double *v, int64_t ldv, int nrhs, const int32_t *perm, int64_t n,
-                      double *vin, int W, hipStream_t s) {
-    hipLaunchKernelGGL(gather_in_kernel, dim3(grid1(n * W)), dim3(BS), 0, s, v, ldv, nrhs, perm, n, vin, W);
+// vin[iperm[i] * W + r] = v[r * ldv + i] (0 for the padding columns r >= nrhs).
+// Threads take (caller point i, column r) with r fastest: each thread group
+// writes a whole canonical row, and the reads of a wave revisit the same few
+// lines of the W caller columns, which stay in cache between neighbouring waves.
+// I is the index type of the element counter (32 bits when n W fits).
+template <class I>
+__global__ void gather_caller_kernel(const double *v, int64_t ldv, int nrhs, const int32_t *iperm, int64_t n,
+                                     double *vin, int W) {
+    const I total = (I)(n * W);
+    const I w = (I)W;
+    for (I e = (I)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (I)gridDim.x * blockDim.x) {
+        const I i = e / w;
+        const int r = (int)(e - i * w);
+        vin[(int64_t)iperm[i] * W + r] = r < nrhs ? v[(int64_t)r * ldv + i] : 0.0;
+    }
 }
 
-void launch_scatter_out(const double *vin, const double *yacc, int W, int nrhs, const int32_t *perm,
-                        int64_t n, double s2, double shift, double *y, int64_t ldy, hipStream_t s) {
-    hipLaunchKernelGGL(scatter_out_kernel, dim3(grid1(n * nrhs)), dim3(BS), 0, s, vin, yacc, W, nrhs,
-                       perm, n, s2, shift, y, ldy);
+// y[r * ldy + i] = s2 (vin[c, r] + sum_g part_g[c, r]) + shift vin[c, r] with
+// c = iperm[i]; the pass slabs are added in pass order (after yacc when not
+// first).  Threads take (caller point i, column r) with r fastest: reads are
+// whole canonical rows, writes fill the W caller columns a few points at a time.
+template <class I>
+__global__ void finish_caller_kernel(const double *vin, const double *part, int G, int first, const double *yacc,
+                                     int W, int nrhs, const int32_t *iperm, int64_t n, double s2, double shift,
+                                     double *y, int64_t ldy) {
+    const I total = (I)(n * W);
+    const I w = (I)W;
+    const int64_t len = n * W;
+    for (I e = (I)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (I)gridDim.x * blockDim.x) {
+        const I i = e / w;
+        const int r = (int)(e - i * w);
+        if (r >= nrhs) continue;
+        const int64_t q = (int64_t)iperm[i] * W + r;
+        double acc = first ? 0.0 : yacc[q];
+        for (int g = 0; g < G; ++g) acc += part[(int64_t)g * len + q];
+        const double vv = vin[q];
+        y[(int64_t)r * ldy + i] = fma(shift, vv, s2 * (vv + acc));
+    }
+}
+
+// The same in canonical order for narrow widths (rows of 1 or 2 doubles): the
+// slab reads are sequential, the writes land at perm[c].
+template <class I>
+__global__ void finish_canon_kernel(const double *vin, const double *part, int G, int first, const double *yacc,
+                                    int W, int nrhs, const int32_t *perm, int64_t n, double s2, double shift,
+                                    double *y, int64_t ldy) {
+    const I total = (I)(n * W);
+    const I w = (I)W;
+    const int64_t len = n * W;
+    for (I q = (I)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (I)gridDim.x * blockDim.x) {
+        const I c = q / w;
+        const int r = (int)(q - c * w);
+        if (r >= nrhs) continue;
+        double acc = first ? 0.0 : yacc[q];
+        for (int g = 0; g < G; ++g) acc += part[(int64_t)g * len + q];
+        const double vv = vin[q];
+        y[(int64_t)r * ldy + perm[c]] = fma(shift, vv, s2 * (vv + acc));
+    }
+}
+
+inline bool fits32(int64_t n, int W) { return (uint64_t)n * (uint64_t)W + 65536u * 8u * BS < (uint64_t(1) << 32); }
+
+}  // namespace
+
+void launch_gather_caller(mm_plan p, const double *v, int64_t ldv, int nrhs, double *vin, int W, hipStream_t s) {
+    const int32_t *ip = static_cast<const int32_t *>(p->iperm.ptr);
+    if (fits32(p->n, W))
+        hipLaunchKernelGGL(gather_caller_kernel<uint32_t>, dim3(grid1(p->n * W)), dim3(BS), 0, s, v, ldv, nrhs, ip,
+                           p->n, vin, W);
+    else
+        hipLaunchKernelGGL(gather_caller_kernel<int64_t>, dim3(grid1(p->n * W)), dim3(BS), 0, s, v, ldv, nrhs, ip,
+                           p->n, vin, W);
+}
+
+void launch_finish_out(mm_plan p, const double *vin, const double *part, int G, int first, const double *yacc,
+                       int W, int nrhs, double s2, double shift, double *y, int64_t ldy, hipStream_t s) {
+    const bool small = fits32(p->n, W);
+    const dim3 g(grid1(p->n * W)), b(BS);
+    if (W >= 4) {
+        const int32_t *ip = static_cast<const int32_t *>(p->iperm.ptr);
+        if (small)
+            hipLaunchKernelGGL(finish_caller_kernel<uint32_t>, g, b, 0, s, vin, part, G, first, yacc, W, nrhs, ip,
+                               p->n, s2, shift, y, ldy);
+        else
+            hipLaunchKernelGGL(finish_caller_kernel<int64_t>, g, b, 0, s, vin, part, G, first, yacc, W, nrhs, ip,
+                               p->n, s2, shift, y, ldy);
+    } else {
+        const int32_t *pm = static_cast<const int32_t *>(p->perm.ptr);
+        if (small)
+            hipLaunchKernelGGL(finish_canon_kernel<uint32_t>, g, b, 0, s, vin, part, G, first, yacc, W, nrhs, pm,
+                               p->n, s2, shift, y, ldy);
+        else
+            hipLaunchKernelGGL(finish_canon_kernel<int64_t>, g, b, 0, s, vin, part, G, first, yacc, W, nrhs, pm,
+                               p->n, s2, shift, y, ldy);
+    }
 }
 
 // Fold the recorded event pairs into the running totals (waits for them).
@@ -148,6 +209,7 @@ void plan_free(mm_plan plan) {
     (void)hipDeviceSynchronize();
     dev_free(plan->xc);
     dev_free(plan->perm);
+    dev_free(plan->iperm);
     dev_free(plan->structure);
     dev_free(plan->geo);
     dev_free(plan->vin);
@@ -246,7 +308,7 @@ mm_status mm_plan_create(const double *x, int64_t n, int32_t d, int64_t ldx, con
     return MM_OK;
 }
 
-mm_status mm_plan_set_kernel(mm_plan plan, const mm_kernel *kernel) {
+mm_status mm_plan_set_kernel(mm_plan plan, const mm_kernel *kernel, void *stream) {
     clear_error();
     if (!plan) {
         set_error("plan is NULL");
@@ -258,6 +320,7 @@ mm_status mm_plan_set_kernel(mm_plan plan, const mm_kernel *kernel) {
         return MM_ERR_ARG;
     }
     plan->kernel = *kernel;
+    plan->last_stream = static_cast<hipStream_t>(stream);
     return MM_OK;
 }
 
@@ -311,9 +374,12 @@ mm_status matern_mvm(mm_plan plan, const double *v, int64_t ldv, double *y, int6
     const int32_t *perm = static_cast<const int32_t *>(plan->perm.ptr);
     double *vin = static_cast<double *>(plan->vin.ptr);
     double *yacc = static_cast<double *>(plan->yacc.ptr);
-    launch_gather_in(v, ldv, nrhs, perm, plan->n, vin, W, s);
-    MM_TRY(sweep_into(plan, vin, yacc, W, R, s));
-    launch_scatter_out(vin, yacc, W, nrhs, perm, plan->n, plan->kernel.outputscale2, diag_shift, y, ldy, s);
+    (void)perm;
+    launch_gather_caller(plan, v, ldv, nrhs, vin, W, s);
+    int tail[2] = {0, 1};
+    MM_TRY(sweep_all(plan, vin, yacc, W, R, s, tail));
+    launch_finish_out(plan, vin, static_cast<const double *>(plan->part.ptr), tail[0], tail[1], yacc, W, nrhs,
+                      plan->kernel.outputscale2, diag_shift, y, ldy, s);
     MM_HIP_TRY(hipGetLastError());
     return MM_OK;
 }
@@ -341,12 +407,13 @@ mm_status matern_mvm_dlengthscale(mm_plan plan, const double *v, int64_t ldv, do
     const int32_t *perm = static_cast<const int32_t *>(plan->perm.ptr);
     double *vin = static_cast<double *>(plan->vin.ptr);
     double *yacc = static_cast<double *>(plan->yacc.ptr);
-    launch_gather_in(v, ldv, nrhs, perm, plan->n, vin, W, s);
+    (void)perm;
+    launch_gather_caller(plan, v, ldv, nrhs, vin, W, s);
     MM_TRY(sweep_all_dl(plan, vin, yacc, W, R, s));
     // dK/dl = outputscale2 / l * (l dk/dl sums)
     const double scale = plan->kernel.outputscale2 / plan->kernel.lengthscale;
-    hipLaunchKernelGGL(scale_out_kernel, dim3(grid1(plan->n * nrhs)), dim3(BS), 0, s, yacc, W, nrhs, perm,
-                       plan->n, scale, y, ldy);
+    hipLaunchKernelGGL(scale_out_kernel, dim3(grid1(plan->n * W)), dim3(BS), 0, s, yacc, W, nrhs,
+                       static_cast<const int32_t *>(plan->iperm.ptr), plan->n, scale, y, ldy);
     MM_HIP_TRY(hipGetLastError());
     return MM_OK;
 }

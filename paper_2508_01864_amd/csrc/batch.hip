@@ -22,13 +22,16 @@ struct MvmIo {
 
 // Per-problem constants of the batch.
 struct MvmDesc {
-    const int32_t *perm;
-    double *vin, *yacc;
+    const int32_t *iperm;   // caller index -> canonical index
+    double *vin;
+    const double *part;     // the G per-pass partial slabs (n x W each)
     int64_t n;
-    int W, nrhs;
+    int W, nrhs, G;
     double s2;
 };
 
+// vin[iperm[i], r] = v[r * ldv + i] (padding columns zero), as matern_mvm's
+// gather: items are chunks of (caller point, column) pairs, column fastest.
 __global__ void gather_batch_kernel(const MvmDesc *ds, const MvmIo *io, const int2 *items, int nitems) {
     for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
         const int2 it = items[i];
@@ -38,27 +41,34 @@ __global__ void gather_batch_kernel(const MvmDesc *ds, const MvmIo *io, const in
         const int64_t lo = (int64_t)it.y * CHUNK;
         const int64_t hi = lo + CHUNK < total ? lo + CHUNK : total;
         for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-            const int64_t c = e / d.W;
-            const int r = (int)(e - c * d.W);
-            d.vin[e] = r < d.nrhs ? q.v[(int64_t)r * q.ldv + d.perm[c]] : 0.0;
+            const int64_t pt = e / d.W;
+            const int r = (int)(e - pt * d.W);
+            d.vin[(int64_t)d.iperm[pt] * d.W + r] = r < d.nrhs ? q.v[(int64_t)r * q.ldv + pt] : 0.0;
         }
     }
 }
 
+// y[r * ldy + i] = s2 (vin + sum of the pass slabs in pass order) + shift vin at
+// canonical row iperm[i]: the arithmetic of matern_mvm's output step.
 __global__ void scatter_batch_kernel(const MvmDesc *ds, const MvmIo *io, const int2 *items, int nitems,
                                      double shift) {
     for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
         const int2 it = items[i];
         const MvmDesc d = ds[it.x];
         const MvmIo q = io[it.x];
-        const int64_t total = d.n * d.nrhs;
+        const int64_t total = d.n * d.W;
+        const int64_t len = d.n * d.W;
         const int64_t lo = (int64_t)it.y * CHUNK;
         const int64_t hi = lo + CHUNK < total ? lo + CHUNK : total;
         for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-            const int r = (int)(e / d.n);
-            const int64_t c = e - (int64_t)r * d.n;
-            const double vv = d.vin[c * d.W + r];
-            q.y[(int64_t)r * q.ldy + d.perm[c]] = fma(shift, vv, d.s2 * (vv + d.yacc[c * d.W + r]));
+            const int64_t pt = e / d.W;
+            const int r = (int)(e - pt * d.W);
+            if (r >= d.nrhs) continue;
+            const int64_t c = (int64_t)d.iperm[pt] * d.W + r;
+            double acc = 0.0;
+            for (int g = 0; g < d.G; ++g) acc += d.part[(int64_t)g * len + c];
+            const double vv = d.vin[c];
+            q.y[(int64_t)r * q.ldy + pt] = fma(shift, vv, d.s2 * (vv + acc));
         }
     }
 }
@@ -83,7 +93,7 @@ using namespace mm;
 struct mm_mvm_batch_s {
     std::vector<mm_plan> plans;
     int nrhs = 1, W = 1, WB = 1;
-    DevBuf work;                 // per problem: vin, yacc, aggregates, partial slabs
+    DevBuf work;                 // per problem: vin, aggregates, partial slabs
     DevBuf desc, io_dev, items_in, items_out;
     int n_in = 0, n_out = 0;
     MvmIo *io_host = nullptr;    // pinned staging of the per-call pointers
@@ -141,7 +151,7 @@ mm_status mvm_batch_build(mm_mvm_batch b) {
             return MM_ERR_ARG;
         }
         const size_t vec = ((size_t)p->n * b->W * sizeof(double) + 255) & ~size_t(255);
-        total += 2 * vec + ((aggb[k] + 255) & ~size_t(255)) + ((partb[k] + 255) & ~size_t(255));
+        total += vec + ((aggb[k] + 255) & ~size_t(255)) + ((partb[k] + 255) & ~size_t(255));
     }
     MM_TRY(dev_alloc(b->work, total));
     char *base = static_cast<char *>(b->work.ptr);
@@ -152,20 +162,19 @@ mm_status mvm_batch_build(mm_mvm_batch b) {
         mm_plan p = b->plans[k];
         const size_t vec = ((size_t)p->n * b->W * sizeof(double) + 255) & ~size_t(255);
         double *vin = reinterpret_cast<double *>(base);
-        double *yacc = reinterpret_cast<double *>(base + vec);
-        double *agg = reinterpret_cast<double *>(base + 2 * vec);
-        base += 2 * vec + ((aggb[k] + 255) & ~size_t(255));
+        double *agg = reinterpret_cast<double *>(base + vec);
+        base += vec + ((aggb[k] + 255) & ~size_t(255));
         double *part = reinterpret_cast<double *>(base);
         base += (partb[k] + 255) & ~size_t(255);
-        ent.push_back(BatchEntry{p, vin, yacc, agg, part});
-        descs.push_back(MvmDesc{static_cast<const int32_t *>(p->perm.ptr), vin, yacc, p->n, b->W, b->nrhs,
-                                p->kernel.outputscale2});
+        ent.push_back(BatchEntry{p, vin, nullptr, agg, part});  // no sum buffer: the output step sums the slabs
+        descs.push_back(MvmDesc{static_cast<const int32_t *>(p->iperm.ptr), vin, part, p->n, b->W, b->nrhs,
+                                (int)p->passes.size(), p->kernel.outputscale2});
         const int64_t nin = (p->n * b->W + CHUNK - 1) / CHUNK;
         for (int64_t c = 0; c < nin; ++c) ii.push_back(make_int2((int)k, (int)c));
-        const int64_t nout = (p->n * b->nrhs + CHUNK - 1) / CHUNK;
-        for (int64_t c = 0; c < nout; ++c) io.push_back(make_int2((int)k, (int)c));
+        for (int64_t c = 0; c < nin; ++c) io.push_back(make_int2((int)k, (int)c));
     }
     MM_TRY(sweep_batch_build(ent, b->W, b->WB, b->sweep));
+    b->sweep.skip_accum = true;  // the output step sums the per-pass partials itself
     MM_TRY(upload_tab(b->desc, descs));
     MM_TRY(upload_tab(b->items_in, ii));
     MM_TRY(upload_tab(b->items_out, io));

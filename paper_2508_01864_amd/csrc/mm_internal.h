@@ -97,6 +97,7 @@ struct mm_plan_s {
 
     mm::DevBuf xc;                // d x n canonical coordinates (SoA, x1-rank order)
     mm::DevBuf perm;              // n int32: canonical index -> caller index
+    mm::DevBuf iperm;             // n int32: caller index -> canonical index
     mm::DevBuf structure;         // stored orders (int32; released once the pass geometry is built)
     mm::DevBuf geo;               // per-pass geometry in pass order (cf, xs, w1, w2)
     std::vector<mm::Pass> passes;
@@ -185,7 +186,17 @@ struct SweepBatch {
 mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB, SweepBatch &out);
 mm_status sweep_batch_run(SweepBatch &b, hipStream_t s);
 void sweep_batch_free(SweepBatch &b);
-mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int R, hipStream_t s);
+// Workspaces of a product supplied by the caller instead of the plan's own
+// (aggregates of sweep_agg_bytes, partial slabs of sweep_part_bytes).
+struct SweepWs {
+    double *agg;
+    double *part;
+};
+// yacc <- the off-diagonal sums of K applied to vin (unscaled; canonical order).  With tail,
+// the last pass group's slabs stay in the partial-slab workspace unsummed (see run_passes);
+// ws replaces the plan's workspaces (no profiling then).
+mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int R, hipStream_t s, int *tail = nullptr,
+                    const SweepWs *ws = nullptr);
 // yacc <- the off-diagonal sums of l dK/dl applied to vin (unscaled; canonical order)
 mm_status sweep_all_dl(mm_plan p, const double *vin, double *yacc, int W, int R, hipStream_t s);
 int rhs_block(const mm_kernel &k, int d, int nrhs);
@@ -202,10 +213,11 @@ mm_status mvm_internal(mm_plan p, const double *vin, double *yout, int W, int nr
 mm_status ensure_work(mm_plan p, int W, bool der = false);
 
 // permutation kernels
-void launch_gather_in(const double *v, int64_t ldv, int nrhs, const int32_t *perm, int64_t n,
-                      double *vin, int W, hipStream_t s);
-void launch_scatter_out(const double *vin, const double *yacc, int W, int nrhs,
-                        const int32_t *perm, int64_t n, double s2, double shift, double *y,
-                        int64_t ldy, hipStream_t s);
+// y (caller column-major) = s2 (vin + sum of the G pass slabs) + shift vin: the sum over
+// passes in pass order, fused with the diagonal and the un-permutation
+void launch_finish_out(mm_plan p, const double *vin, const double *part, int G, int first, const double *yacc,
+                       int W, int nrhs, double s2, double shift, double *y, int64_t ldy, hipStream_t s);
+// vin (canonical point-major, W columns, padding zero) from v (caller column-major)
+void launch_gather_caller(mm_plan p, const double *v, int64_t ldv, int nrhs, double *vin, int W, hipStream_t s);
 
 }  // namespace mm

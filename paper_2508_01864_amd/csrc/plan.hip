@@ -330,6 +330,12 @@ __global__ void part_scatter(const int32_t *src, int32_t *dst, int64_t n, int bi
     }
 }
 
+// iperm[perm[c]] = c: caller index -> canonical index
+__global__ void invert_perm(const int32_t *perm, int64_t n, int32_t *iperm) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+        iperm[perm[c]] = (int32_t)c;
+}
+
 __global__ void gather_coords(const double *x, int64_t ldx, int64_t n, int d, const int32_t *perm,
                               double *xc) {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
@@ -515,7 +521,7 @@ size_t plan_footprint(int64_t n, int d, int nrhs, const mm_kernel &k) {
     const int R = rhs_block(k, d, nrhs);
     const int64_t W = (nrhs + R - 1) / R * R;
     // the stored orders and the geometry coexist while the plan is built
-    size_t b = (size_t)d * n * 8 + (size_t)n * 4 + structure_ints(n, d) * 4 + geo_bytes(n, d);
+    size_t b = (size_t)d * n * 8 + (size_t)n * 8 + structure_ints(n, d) * 4 + geo_bytes(n, d);
     b += 2 * (size_t)n * W * 8;                       // product buffers
     b += sweep_agg_bytes(n, d, (int)W, k);
     {
@@ -556,6 +562,7 @@ mm_status plan_build(mm_plan p, const double *x, int64_t ldx, hipStream_t s) {
     BUILD_TRY(dev_alloc(tmp.bad, 16));
     BUILD_TRY(dev_alloc(p->xc, (size_t)d * n * 8));
     BUILD_TRY(dev_alloc(p->perm, (size_t)n * 4));
+    BUILD_TRY(dev_alloc(p->iperm, (size_t)n * 4));
 
     // finiteness of every coordinate
     if (hipMemsetAsync(tmp.bad.ptr, 0, 16, s) != hipSuccess) { cleanup(); set_error("memset"); return MM_ERR_HIP; }
@@ -581,6 +588,8 @@ mm_status plan_build(mm_plan p, const double *x, int64_t ldx, hipStream_t s) {
     }
     hipLaunchKernelGGL(gather_coords, dim3(grid_for(n)), dim3(BS), 0, s, x, ldx, n, d,
                        static_cast<const int32_t *>(p->perm.ptr), static_cast<double *>(p->xc.ptr));
+    hipLaunchKernelGGL(invert_perm, dim3(grid_for(n)), dim3(BS), 0, s, static_cast<const int32_t *>(p->perm.ptr),
+                       n, static_cast<int32_t *>(p->iperm.ptr));
     const double *xc = static_cast<const double *>(p->xc.ptr);
 
     p->passes.clear();

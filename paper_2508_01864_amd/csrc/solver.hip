@@ -20,10 +20,12 @@ namespace {
 constexpr int BS = 256;
 constexpr int WAVE = 64;   // lanes per wavefront
 constexpr int NRED = 1024;  // row blocks of the column dot products (fixed: deterministic sums)
-constexpr int NS = 10;     // scalars per column: [0] r.r [1] p.Ap [2] alpha [3] beta
+constexpr int NS = 11;     // scalars per column: [0] r.r [1] p.Ap [2] alpha [3] beta
                            // [4] |b| [5] active [6] iterations while active [7] |r|
                            // [8] r.r and [9] active as the update left them (read by
                            //     every workgroup of the direction step, which rewrites [0], [5])
+                           // [10] the column's stopping tolerance (relative to |b|): rtol,
+                           //     tightened when a recomputed residual misses rtol
 constexpr int CHUNK = 1024;
 constexpr int PUB = 1024;     // row blocks of the partial products L^T r (fixed: deterministic)
 constexpr int PC_MAXW = 8;    // columns of a preconditioned solver
@@ -171,6 +173,7 @@ __global__ void cg_init_scalars_b(const CgDesc *ds, int nsol) {
             c[7] = sqrt(s);
             c[8] = c[0];
             c[9] = c[5];
+            c[10] = d.rtol;
         }
         if (r == 0) {
             d.flags[0] = 0;
@@ -212,7 +215,7 @@ __device__ __forceinline__ void alpha_record(const CgDesc &d, int r, double s) {
 __device__ __forceinline__ void beta_record(const CgDesc &d, int r, double s, double rz) {
     double *c = d.sc + r * NS;
     if (c[9] != 0.0) {
-        if (sqrt(s) <= d.rtol * c[4]) {
+        if (sqrt(s) <= c[10] * c[4]) {
             c[5] = 0.0;
             c[3] = 0.0;
         } else {
@@ -347,12 +350,95 @@ __global__ void cg_dir_b(const CgDesc *ds, const int2 *items, int nitems) {
         const double s = fused ? tot[r] : d.red[d.W + r];
         const double rz = d.rank > 0 ? (fused ? tz[r] : d.red[2 * d.W + r]) : s;
         const double *c = d.sc + r * NS;
-        const bool on = c[9] != 0.0 && !(sqrt(s) <= d.rtol * c[4]);
+        const bool on = c[9] != 0.0 && !(sqrt(s) <= c[10] * c[4]);
         const double be = on ? rz / c[8] : 0.0;
         if (it.y == 0 && (int)threadIdx.x < d.W) beta_record(d, r, s, rz);
         if (!on) continue;
         const double *src = d.rank > 0 ? d.Z : d.R;
         for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) d.P[e] = fma(be, d.P[e], src[e]);
+    }
+}
+
+// ---- recomputed residual and restart (residual replacement) ----
+// After Q = A X (the product of the iterate, through the same sweeps and
+// apply step): R = B - Q, partial r.r per column into part2 and, for the
+// fixed-effects combination of Section 3.2, partial |r_0 - sum_i beta_i r_{1+i}|^2
+// into column 0 of part (y - H beta - A alpha = r_0 - sum_i beta_i r_{1+i}).
+__global__ void cg_resid_b(const CgDesc *ds, const int2 *items, int nitems, int nb, double b0, double b1, double b2,
+                           double b3) {
+    __shared__ double sm[BS];
+    __shared__ double sr[BS];
+    const double bt[4] = {b0, b1, b2, b3};
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        const CgDesc d = ds[it.x];
+        int64_t lo, hi;
+        row_range(d.n, it.y, lo, hi);
+        double acc = 0.0, comb = 0.0;
+        // BS / W whole rows per step (W divides BS): thread t holds column t mod W
+        for (int64_t base = lo * d.W; base < hi * d.W; base += BS) {
+            const int64_t e = base + threadIdx.x;
+            double r = 0.0;
+            if (e < hi * d.W) {
+                r = d.B[e] - d.Q[e];
+                d.R[e] = r;
+            }
+            acc = fma(r, r, acc);
+            sr[threadIdx.x] = r;
+            __syncthreads();
+            const int row = threadIdx.x;
+            if (nb > 0 && row < BS / d.W && base + (int64_t)row * d.W < hi * d.W) {
+                double t = sr[row * d.W];
+                for (int k = 0; k < nb; ++k) t = fma(-bt[k], sr[row * d.W + 1 + k], t);
+                comb = fma(t, t, comb);
+            }
+            __syncthreads();
+        }
+        block_col_sum(acc, d.W, sm, d.part2, it.y);
+        block_col_sum(comb, 1, sm, d.part, it.y);  // one column: the sum of every thread's value
+    }
+}
+
+// P = R: the restart direction without a preconditioner
+__global__ void cg_restart_dir_b(const CgDesc *ds, const int2 *items, int nitems) {
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        const CgDesc d = ds[it.x];
+        const int64_t lo = (int64_t)it.y * CHUNK;
+        const int64_t len = d.n * d.W;
+        const int64_t hi = lo + CHUNK < len ? lo + CHUNK : len;
+        for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) d.P[e] = d.R[e];
+    }
+}
+
+// Scalars of a restart from the recomputed residual: r.z (r.r without a
+// preconditioner), |r|, the tolerances tol[r] (host-chosen), and the active
+// flags: a column is active while |r| > tol |b|, unless freeze (every column
+// frozen: the solve has met its tolerance).  |b| and the iteration counts stay.
+__global__ void cg_restart_scalars_b(const CgDesc *ds, const double *tol, int freeze) {
+    __shared__ double red[BS];
+    __shared__ double tot[64];
+    __shared__ double tz[64];
+    const CgDesc d = ds[0];
+    reduce_cols(d.part2, d.W, red, tot);
+    if (d.rank > 0) reduce_cols(d.part_rz, d.W, red, tz);
+    const int r = threadIdx.x;
+    if (r < d.W) {
+        double *c = d.sc + r * NS;
+        const double rr = tot[r];
+        c[0] = d.rank > 0 ? tz[r] : rr;
+        c[1] = 0.0;
+        c[2] = 0.0;
+        c[3] = 0.0;
+        c[7] = sqrt(rr);
+        c[10] = tol[r];
+        c[5] = (!freeze && r < d.ncols && c[4] > 0.0 && c[7] > c[10] * c[4]) ? 1.0 : 0.0;
+        c[8] = c[0];
+        c[9] = c[5];
+    }
+    if (r == 0) {
+        d.flags[0] = 0;
+        d.flags[1] = 0;
     }
 }
 
@@ -679,6 +765,8 @@ struct mm_solver_s {
     int64_t iters = 0;
     mm_solver_batch self = nullptr;  // batch of one for solitary iterations
     mm_precond pc = nullptr;         // preconditioner (pinned while the solver lives)
+    double true_rel = -1.0;          // residual recomputed by the last check (-1: none)
+    int64_t checked_iters = -1;      // iterations at that check
 };
 
 struct mm_solver_batch_s {
@@ -1207,19 +1295,14 @@ mm_status solver_run(mm_solver sv, int maxit, hipStream_t s) {
     return MM_OK;
 }
 
-// GLS from the solved columns [A^-1 y, A^-1 H] (Section 3.2) and alpha in caller order.
-mm_status solver_output(mm_solver sv, double *alpha, double *beta, hipStream_t s) {
+// GLS estimate beta = (H^T A^-1 H)^{-1} H^T A^-1 y from the solved columns
+// [A^-1 y, A^-1 H] (Section 3.2), on the host: hb[0..d].
+mm_status solver_gls(mm_solver sv, double *hb, hipStream_t s) {
     mm_plan plan = sv->plan;
     const int64_t n = plan->n;
     const int d = plan->d;
     const int W = sv->W;
-    const int32_t *perm = static_cast<const int32_t *>(plan->perm.ptr);
     const double *xc = static_cast<const double *>(plan->xc.ptr);
-    if (!sv->fe) {
-        hipLaunchKernelGGL(col_out_kernel, dim3(grid1(n)), dim3(BS), 0, s, sv->desc.X, perm, n, W, 1, alpha, n);
-        MM_HIP_TRY(hipGetLastError());
-        return MM_OK;
-    }
     const int nb = d + 1;
     double *part = sv->desc.part;
     hipLaunchKernelGGL(fe_gram_kernel, dim3(NRED), dim3(BS), 0, s, sv->desc.X, xc, n, d, W, part);
@@ -1230,7 +1313,8 @@ mm_status solver_output(mm_solver sv, double *alpha, double *beta, hipStream_t s
     for (int b = 0; b < NRED; ++b)
         for (int i = 0; i < nb; ++i)
             for (int j = 0; j < W; ++j) HX[i * W + j] += hp[((size_t)b * nb + i) * W + j];
-    double G[4][4], g[4], Lm[4][4] = {{0}}, w[4], hb[4] = {0, 0, 0, 0};
+    double G[4][4], g[4], Lm[4][4] = {{0}}, w[4];
+    for (int i = 0; i < 4; ++i) hb[i] = 0.0;
     for (int i = 0; i < nb; ++i) {
         g[i] = HX[i * W + 0];
         for (int j = 0; j < nb; ++j) G[i][j] = 0.5 * (HX[i * W + 1 + j] + HX[j * W + 1 + i]);
@@ -1259,6 +1343,23 @@ mm_status solver_output(mm_solver sv, double *alpha, double *beta, hipStream_t s
         for (int k = i + 1; k < nb; ++k) t -= Lm[k][i] * hb[k];
         hb[i] = t / Lm[i][i];
     }
+    return MM_OK;
+}
+
+// GLS from the solved columns and alpha = A^-1 y - (A^-1 H) beta in caller order.
+mm_status solver_output(mm_solver sv, double *alpha, double *beta, hipStream_t s) {
+    mm_plan plan = sv->plan;
+    const int64_t n = plan->n;
+    const int W = sv->W;
+    const int32_t *perm = static_cast<const int32_t *>(plan->perm.ptr);
+    if (!sv->fe) {
+        hipLaunchKernelGGL(col_out_kernel, dim3(grid1(n)), dim3(BS), 0, s, sv->desc.X, perm, n, W, 1, alpha, n);
+        MM_HIP_TRY(hipGetLastError());
+        return MM_OK;
+    }
+    const int nb = plan->d + 1;
+    double hb[4];
+    MM_TRY(solver_gls(sv, hb, s));
     for (int i = 0; i < nb; ++i) beta[i] = hb[i];
     hipLaunchKernelGGL(fe_alpha_kernel, dim3(grid1(n)), dim3(BS), 0, s, sv->desc.X, perm, n, W, nb, hb[0], hb[1],
                        hb[2], hb[3], alpha);
@@ -1266,7 +1367,91 @@ mm_status solver_output(mm_solver sv, double *alpha, double *beta, hipStream_t s
     return MM_OK;
 }
 
-mm_status status_of(int conv, int ncols, int brk, int iters, double rel) {
+// The residual of the current iterate recomputed with a fresh product (the
+// recurrence residual of Algorithm 2 drifts from it, and with fixed effects
+// the solved columns combine into y - H beta - A alpha = r_0 - sum_i beta_i r_i),
+// then a restart from it: R = B - A X, P = R (P^{-1} R with a preconditioner),
+// the scalars recomputed.  *rel_out is |y - H beta - A alpha| / |y| with fixed
+// effects, else the largest |b_j - A x_j| / |b_j|; *passed is rel_out <= rtol,
+// and then every column is frozen.  Otherwise, with tighten and every column
+// converged by the recurrence, the column tolerances shrink by
+// 0.5 rtol / rel_out (within [0.05, 0.5]: the columns that missed, or all
+// of them with fixed effects), so further iterations continue the solve.
+mm_status solver_check(mm_solver sv, hipStream_t s, bool tighten, int *passed, double *rel_out) {
+    mm_plan plan = sv->plan;
+    mm_solver_batch b = sv->self;
+    const int64_t n = plan->n;
+    const int W = sv->W;
+    CgDesc &d = sv->desc;
+    std::vector<double> hsc((size_t)W * NS);
+    MM_HIP_TRY(hipMemcpyAsync(hsc.data(), d.sc, hsc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    MM_HIP_TRY(hipStreamSynchronize(s));
+    bool all_conv = true;
+    for (int r = 0; r < sv->ncols; ++r)
+        if (hsc[r * NS + 5] != 0.0) all_conv = false;
+    double hb[4] = {0.0, 0.0, 0.0, 0.0};
+    const int nb = sv->fe ? plan->d + 1 : 0;
+    if (sv->fe) MM_TRY(solver_gls(sv, hb, s));
+    // Q = A X through the solver's own product (its sweeps read P)
+    MM_HIP_TRY(hipMemcpyAsync(d.P, d.X, (size_t)n * W * sizeof(double), hipMemcpyDeviceToDevice, s));
+    const CgDesc *ds = static_cast<const CgDesc *>(b->cg_desc.ptr);
+    const int2 *ib = static_cast<const int2 *>(b->items_blk.ptr);
+    if (b->plain) {
+        MM_TRY(sweep_all(plan, d.P, d.Y, W, rhs_block(plan->kernel, sv->d, W), s));
+    } else {
+        for (SweepBatch &sb : b->sweeps) MM_TRY(sweep_batch_run(sb, s));
+    }
+    hipLaunchKernelGGL(cg_apply_b, dim3(pgrid(b->n_blk, b->grid_cap)), dim3(BS), 0, s, ds, ib, b->n_blk);
+    hipLaunchKernelGGL(cg_resid_b, dim3(pgrid(b->n_blk, b->grid_cap)), dim3(BS), 0, s, ds, ib, b->n_blk, nb, hb[0],
+                       hb[1], hb[2], hb[3]);
+    std::vector<double> hr((size_t)NRED * W), hc(NRED);
+    MM_HIP_TRY(hipMemcpyAsync(hr.data(), d.part2, hr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    MM_HIP_TRY(hipMemcpyAsync(hc.data(), d.part, hc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    MM_HIP_TRY(hipStreamSynchronize(s));
+    std::vector<double> rn(W, 0.0);
+    double comb = 0.0;
+    for (int blk = 0; blk < NRED; ++blk) {
+        for (int r = 0; r < W; ++r) rn[r] += hr[(size_t)blk * W + r];
+        comb += hc[blk];
+    }
+    std::vector<double> rel(W, 0.0), tol(W);
+    double worst = 0.0;
+    for (int r = 0; r < W; ++r) {
+        const double bn = hsc[r * NS + 4];
+        rel[r] = bn > 0.0 ? std::sqrt(rn[r]) / bn : 0.0;
+        tol[r] = hsc[r * NS + 10];
+        if (r < sv->ncols && rel[r] > worst) worst = rel[r];
+    }
+    const double bn0 = hsc[4];
+    const double trel = sv->fe ? (bn0 > 0.0 ? std::sqrt(comb) / bn0 : 0.0) : worst;
+    const bool ok = trel <= sv->rtol;
+    if (!ok && tighten && all_conv) {
+        double f = 0.5 * sv->rtol / trel;
+        f = f < 0.05 ? 0.05 : (f > 0.5 ? 0.5 : f);
+        for (int r = 0; r < sv->ncols; ++r)
+            if (sv->fe || rel[r] > sv->rtol) tol[r] *= f;
+    }
+    if (b->n_pa > 0) {
+        MM_TRY(precond_enqueue(b, s, 1));  // Z = P^{-1} R, P = Z, partial r.z
+    } else {
+        hipLaunchKernelGGL(cg_restart_dir_b, dim3(pgrid(b->n_chunk, b->grid_cap)), dim3(BS), 0, s, ds,
+                           static_cast<const int2 *>(b->items_chunk.ptr), b->n_chunk);
+    }
+    double *tstage = d.part + (size_t)4 * NRED * W;  // unused part of the partial-sum area
+    MM_HIP_TRY(hipMemcpyAsync(tstage, tol.data(), W * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(cg_restart_scalars_b, dim3(1), dim3(BS), 0, s, ds, static_cast<const double *>(tstage),
+                       ok ? 1 : 0);
+    MM_HIP_TRY(hipGetLastError());
+    MM_HIP_TRY(hipStreamSynchronize(s));
+    sv->true_rel = trel;
+    sv->checked_iters = sv->iters;
+    if (passed) *passed = ok ? 1 : 0;
+    if (rel_out) *rel_out = trel;
+    return MM_OK;
+}
+
+mm_status status_of(int conv, int ncols, int brk, int iters, double rel, double true_rel = -1.0,
+                    double rtol = 0.0) {
     if (brk) {
         set_error("conjugate gradients broke down (p^T A p <= 0)");
         return MM_ERR_BREAKDOWN;
@@ -1275,7 +1460,31 @@ mm_status status_of(int conv, int ncols, int brk, int iters, double rel) {
         set_error("conjugate gradients did not reach rtol in %d iterations (relres %.3e)", iters, rel);
         return MM_ERR_NOCONV;
     }
+    if (true_rel > rtol) {
+        set_error("the recomputed residual %.3e misses rtol %.3e after %d iterations", true_rel, rtol, iters);
+        return MM_ERR_NOCONV;
+    }
     return MM_OK;
+}
+
+// Iterate until the recurrence converges, then check the recomputed residual;
+// a miss tightens the column tolerances and the solve continues from the
+// recomputed residual (at most MAX_CHECKS checks, within maxit iterations).
+constexpr int MAX_CHECKS = 8;
+
+mm_status solver_solve(mm_solver sv, int maxit, hipStream_t s) {
+    for (int chk = 0;; ++chk) {
+        MM_TRY(solver_run(sv, maxit, s));
+        int conv = 0, brk = 0;
+        double rel = 0.0;
+        MM_TRY(solver_summary(sv, s, &conv, &brk, &rel, nullptr));
+        if (brk || conv < sv->ncols) return MM_OK;  // breakdown or maxit: finish reports it
+        const bool more = chk + 1 < MAX_CHECKS && sv->iters < maxit;
+        int passed = 0;
+        double tr = 0.0;
+        MM_TRY(solver_check(sv, s, more, &passed, &tr));
+        if (passed || !more) return MM_OK;
+    }
 }
 
 }  // namespace
@@ -1379,10 +1588,30 @@ mm_status mm_solver_finish(mm_solver solver, double *alpha, double *beta, mm_sol
     double rel = 0.0;
     mm_solve_info inf{};
     MM_TRY(solver_summary(solver, s, &conv, &brk, &rel, &inf));
+    if (!brk && solver->checked_iters != solver->iters) {
+        // the residual of the returned iterate, recomputed (no tightening)
+        MM_TRY(solver_check(solver, s, false, nullptr, nullptr));
+        MM_TRY(solver_summary(solver, s, &conv, &brk, &rel, &inf));
+    }
+    inf.true_relres = brk ? -1.0 : solver->true_rel;
     if (info) *info = inf;
     MM_TRY(solver_output(solver, alpha, beta, s));
     MM_HIP_TRY(hipStreamSynchronize(s));
-    return status_of(conv, solver->ncols, brk, inf.iters, rel);
+    return status_of(conv, solver->ncols, brk, inf.iters, rel, inf.true_relres, solver->rtol);
+}
+
+mm_status mm_solver_check(mm_solver solver, int32_t tighten, int32_t *passed, double *true_relres, void *stream) {
+    clear_error();
+    if (!solver) {
+        set_error("solver is NULL");
+        return MM_ERR_ARG;
+    }
+    int ok = 0;
+    double tr = 0.0;
+    MM_TRY(solver_check(solver, static_cast<hipStream_t>(stream), tighten != 0, &ok, &tr));
+    if (passed) *passed = ok;
+    if (true_relres) *true_relres = tr;
+    return MM_OK;
 }
 
 mm_status mm_solver_destroy(mm_solver solver) {
@@ -1495,7 +1724,7 @@ mm_status pcg_impl(mm_plan plan, const double *y, double sigma2, int32_t fixed_e
     hipStream_t s = static_cast<hipStream_t>(stream);
     mm_solver sv = nullptr;
     MM_TRY(solver_create_impl(plan, y, sigma2, fixed_effects, rtol, pc, stream, &sv));
-    mm_status st = solver_run(sv, maxit, s);
+    mm_status st = solver_solve(sv, maxit, s);
     if (st == MM_OK) st = mm_solver_finish(sv, alpha, beta, info, stream);
     if (st != MM_OK && st != MM_ERR_NOCONV && st != MM_ERR_BREAKDOWN) {
         mm_solver_destroy(sv);
@@ -1825,12 +2054,17 @@ mm_status gp_cg_solve_multi(mm_plan plan, const double *Bc, int64_t ldb, int32_t
                                              nrhs, static_cast<const int32_t *>(plan->perm.ptr), plan->n, B, W);
                       },
                       &sv));
-    mm_status st = solver_run(sv, maxit, s);
+    mm_status st = solver_solve(sv, maxit, s);
     int conv = 0, brk = 0;
     double rel = 0.0;
     mm_solve_info inf{};
     if (st == MM_OK) st = solver_summary(sv, s, &conv, &brk, &rel, &inf);
+    if (st == MM_OK && !brk && sv->checked_iters != sv->iters) {
+        st = solver_check(sv, s, false, nullptr, nullptr);
+        if (st == MM_OK) st = solver_summary(sv, s, &conv, &brk, &rel, &inf);
+    }
     if (st == MM_OK) {
+        inf.true_relres = brk ? -1.0 : sv->true_rel;
         if (info) *info = inf;
         hipLaunchKernelGGL(col_out_kernel, dim3(grid1(plan->n * nrhs)), dim3(BS), 0, s, sv->desc.X,
                            static_cast<const int32_t *>(plan->perm.ptr), plan->n, sv->W, nrhs, Xc, ldx);
@@ -1838,7 +2072,7 @@ mm_status gp_cg_solve_multi(mm_plan plan, const double *Bc, int64_t ldb, int32_t
             set_error("HIP error after the solve");
             st = MM_ERR_HIP;
         } else {
-            st = status_of(conv, nrhs, brk, inf.iters, rel);
+            st = status_of(conv, nrhs, brk, inf.iters, rel, inf.true_relres, rtol);
         }
     }
     std::string msg = last_error_str();

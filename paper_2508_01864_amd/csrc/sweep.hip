@@ -140,7 +140,8 @@ mm_status upload_pass_tables(mm_plan p) {
 }
 
 // WB: columns per wave (1, 2, 4 or 32); W a multiple of WB.
-mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int WB, hipStream_t s) {
+mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int WB, hipStream_t s, int *tail,
+                    const SweepWs *ws) {
     const KParams kp = kparams(p->kernel, p->d);
     if ((WB != 1 && WB != 2 && WB != 4 && WB != 32) || W % WB != 0) {
         set_error("internal: width %d does not match the block %d", W, WB);
@@ -148,7 +149,7 @@ mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int WB, h
     }
     return with_cfg(p->d, kp, WB, W, [&](auto t) {
         using C = typename decltype(t)::type;
-        return run_passes<C>(p, vin, yacc, W, s);
+        return run_passes<C>(p, vin, yacc, W, s, false, tail, ws);
     });
 }
 

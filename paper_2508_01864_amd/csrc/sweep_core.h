@@ -1308,8 +1308,15 @@ mm_status profile_begin(mm_plan p, int passes_covered, hipStream_t s, hipEvent_t
     return MM_OK;
 }
 
+// The passes of plan p applied to vin, summed into yacc (added to it with add).
+// With tail non-null, the last pass group's slabs are left unsummed in the
+// plan's partial-slab buffer for the caller to fold into its output:
+// tail[0] = that group's passes, tail[1] = 1 when yacc holds no earlier group.
 template <class C>
-mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStream_t s, bool add = false) {
+mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStream_t s, bool add = false,
+                     int *tail = nullptr, const SweepWs *ws = nullptr) {
+    double *const ws_agg = ws ? ws->agg : static_cast<double *>(p->agg.ptr);
+    double *const ws_part = ws ? ws->part : static_cast<double *>(p->part.ptr);
     static_assert(C::T == 128 || C::T == 256 || C::T == 512 || C::T == 1024, "tile sizes with a cross-tile pass list");
     const KParams kp = kparams(p->kernel, p->d);
     const int64_t n = p->n;
@@ -1318,6 +1325,11 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
     const int npass = (int)p->passes.size();
     const int64_t len = n * W;
     if (npass == 0) {
+        if (tail) {
+            tail[0] = 0;
+            tail[1] = 1;
+            return MM_OK;
+        }
         if (add) return MM_OK;
         hipLaunchKernelGGL(zero_kernel, dim3(grid_1d(len)), dim3(BS1), 0, s, yacc, len);
         MM_HIP_TRY(hipGetLastError());
@@ -1331,13 +1343,13 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
     A.passes = static_cast<const PassDev *>(p->pass_dev.ptr);
     A.xt = static_cast<const int32_t *>(p->pass_xt[ti].ptr);
     A.vin = vin;
-    A.ypart = static_cast<double *>(p->part.ptr);
+    A.ypart = ws_part;
     A.n = n;
     A.ntile = ntile;
     A.W = W;
     A.a = kp.a;
     const size_t aggslab = (size_t)2 * gmax * ntile * W * C::NSUB * C::NSLOT;
-    A.agg = static_cast<double *>(p->agg.ptr);
+    A.agg = ws_agg;
     A.car = A.agg + aggslab;
     A.anc = A.car + aggslab;
     A.dec = A.anc + (size_t)2 * gmax * ntile;
@@ -1367,11 +1379,16 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
                                    dim3(256), 0, s, A);
         }
         hipEvent_t ev1 = nullptr;
-        MM_TRY(profile_begin(p, G, s, &ev1));
+        if (!ws) MM_TRY(profile_begin(p, G, s, &ev1));  // (profiling creates events: not with a caller workspace)
         hipLaunchKernelGGL((sweep_kernel<C, 0>), dim3((unsigned)(G * ntile), (unsigned)ncb), dim3(WAVE), 0, s, A);
         if (ev1) MM_HIP_TRY(hipEventRecord(ev1, s));
-        hipLaunchKernelGGL(accum_kernel, dim3(grid_1d(len)), dim3(BS1), 0, s,
-                           static_cast<const double *>(p->part.ptr), G, len, yacc, g0 == 0 && !add ? 1 : 0);
+        if (tail && g0 + G >= npass) {
+            tail[0] = G;
+            tail[1] = g0 == 0 ? 1 : 0;
+        } else {
+            hipLaunchKernelGGL(accum_kernel, dim3(grid_1d(len)), dim3(BS1), 0, s,
+                               static_cast<const double *>(ws_part), G, len, yacc, g0 == 0 && !add ? 1 : 0);
+        }
     }
     MM_HIP_TRY(hipGetLastError());
     return MM_OK;

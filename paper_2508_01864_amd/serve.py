@@ -8,9 +8,9 @@ advances all of them together: each tick runs ``chunk`` iterations of one
 launches), then polls.  Finished requests leave (their GLS estimate and
 posterior mean at z are computed, their memory is released) and waiting
 requests are admitted in arrival order as slots and device memory free up.
-Admission is by device footprint: the plan, the solver and the temporary
-prediction plan of a request are bounded on the host before anything is
-allocated, and a request is admitted only while the sum over admitted
+Admission is by device footprint: the plan, the solver, the optional
+pivoted Cholesky preconditioner and the temporary prediction plan of a
+request are bounded on the host before anything is allocated, and a request is admitted only while the sum over admitted
 requests stays within the memory budget.
 
 Every request's result equals what gp_cg_solve + gp_predict give for it alone
@@ -32,7 +32,7 @@ from typing import Dict, List, Optional
 
 import numpy as np
 
-from . import (Kernel, Plan, Solver, SolverBatch, autotune, footprint_bytes,
+from . import (Kernel, Plan, Precond, Solver, SolverBatch, autotune, footprint_bytes,
                solver_footprint_bytes)
 from .batched import batch_key
 
@@ -48,6 +48,7 @@ class Request:
     z: np.ndarray             # (m, d) prediction points
     rtol: float = 1e-8
     maxit: int = 20000
+    precond_rank: int = 0     # rank of the pivoted Cholesky preconditioner (0: plain CG)
 
 
 @dataclass
@@ -66,12 +67,17 @@ class Response:
         return self.done - self.arrival
 
 
-def request_bytes(n: int, d: int, m: int, kernel: Kernel) -> int:
+def request_bytes(n: int, d: int, m: int, kernel: Kernel, precond_rank: int = 0) -> int:
     """Device-memory bound of one request: its plan, its solver (fixed
-    effects), its input copies and the temporary plan of the prediction."""
+    effects), its input copies, the temporary plan of the prediction and its
+    preconditioner (the n x rank factor, the preconditioned solver's vectors and
+    the Woodbury factors)."""
     b = footprint_bytes(n, d, 1, kernel) + solver_footprint_bytes(n, d, True, kernel)
     b += 8 * (n * (d + 1) + m * (d + 1))
     b += footprint_bytes(n + m, d, 1, kernel) + 8 * (n + m) * (d + 2)
+    if precond_rank > 0:
+        k = min(precond_rank, n)
+        b += 8 * n * k + 8 * (2 * n * 8 + 1024 * 8 * (2 + 2 * k) + 4 * k * k) + (1 << 20)
     return b
 
 
@@ -107,9 +113,16 @@ class _Live:
         self.y = torch.as_tensor(req.y, device=device)
         self.z = torch.as_tensor(req.z, device=device)
         self.plan = Plan(self.x, req.kernel)
-        self.solver = Solver(self.plan, self.y, req.sigma2, fixed_effects=True, rtol=req.rtol)
+        self.pc = Precond(self.plan, max_rank=req.precond_rank) if req.precond_rank > 0 else None
+        self.solver = Solver(self.plan, self.y, req.sigma2, fixed_effects=True, rtol=req.rtol, precond=self.pc)
         self.iters = 0
-        self.bytes = request_bytes(len(req.y), req.x.shape[1], len(req.z), req.kernel)
+        self.bytes = request_bytes(len(req.y), req.x.shape[1], len(req.z), req.kernel, req.precond_rank)
+
+    def close(self):
+        self.solver.close()
+        if self.pc is not None:
+            self.pc.close()
+        self.plan.close()
 
 
 class Server:
@@ -150,7 +163,7 @@ class Server:
                 changed = False
                 while queue and len(live) < self.max_slots:
                     r = queue[0]
-                    need = request_bytes(len(r.y), r.x.shape[1], len(r.z), r.kernel)
+                    need = request_bytes(len(r.y), r.x.shape[1], len(r.z), r.kernel, r.precond_rank)
                     if need > self.budget:
                         raise RuntimeError("request %d needs %d bytes, more than the whole budget %d"
                                            % (r.rid, need, self.budget))
@@ -186,6 +199,11 @@ class Server:
                 finished = []
                 for i, st in zip(members, status):
                     live[i].iters += k
+                    if st == 0 and live[i].iters < live[i].req.maxit:
+                        # converged by the recurrence: the recomputed residual decides
+                        passed, _ = live[i].solver.check(tighten=True)
+                        if not passed:
+                            continue
                     if st <= 0 or live[i].iters >= live[i].req.maxit:
                         finished.append(i)
                 if finished:
@@ -195,8 +213,7 @@ class Server:
                         lv = live.pop(i)
                         alpha, beta, info = lv.solver.finish(raise_on_error=False)
                         mean = lv.plan.predict(alpha, lv.z, beta=beta)
-                        lv.solver.close()
-                        lv.plan.close()
+                        lv.close()
                         out.append(Response(i, lv.req.arrival, lv.admitted, now(), alpha, beta, mean, info))
                         used -= lv.bytes
                         if on_done is not None:
@@ -205,8 +222,7 @@ class Server:
             if batch is not None:
                 batch.close()
             for lv in live.values():
-                lv.solver.close()
-                lv.plan.close()
+                lv.close()
         return sorted(out, key=lambda r: r.rid)
 
 
@@ -227,10 +243,13 @@ def run_plain(requests: List[Request], device=None, on_done=None) -> List[Respon
         y = torch.as_tensor(r.y, device=dev)
         z = torch.as_tensor(r.z, device=dev)
         plan = Plan(x, r.kernel)
+        pc = Precond(plan, max_rank=r.precond_rank) if r.precond_rank > 0 else None
         alpha, beta, info = plan.cg_solve(y, r.sigma2, fixed_effects=True, rtol=r.rtol, maxit=r.maxit,
-                                          raise_on_error=False)
+                                          raise_on_error=False, precond=pc)
         mean = plan.predict(alpha, z, beta=beta)
         torch.cuda.synchronize()
+        if pc is not None:
+            pc.close()
         plan.close()
         service = time.perf_counter() - t0
         free_at = start + service

@@ -36,3 +36,14 @@ def mvm_errors(y, yref, yabs):
 def say(*args):
     print(*args, flush=True)
     sys.stdout.flush()
+
+
+def converged(solvers, status, passed):
+    """One round of the stop rule of gp_cg_solve for hand-driven solvers: a
+    solver whose columns all converged by the recurrence (status 0) has its
+    residual recomputed (mm_solver_check); a miss restarts it with tighter
+    tolerances.  passed[k] records the solvers done; True when all are."""
+    for k, (s, st) in enumerate(zip(solvers, status)):
+        if not passed[k] and st == 0:
+            passed[k] = s.check(tighten=True)[0]
+    return all(passed)

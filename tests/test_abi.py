@@ -90,6 +90,8 @@ def test_null_pointers_rejected_on_host():
     assert L.gp_lml(None, None, 0.1, None, 1, 1, 10, 1e-8, None, None, None) == mm.MM_ERR_ARG
     assert L.mm_plan_destroy(None) == mm.MM_OK
     assert L.mm_plan_profile_enable(None, 1) == mm.MM_ERR_ARG
+    kk = mm.Kernel(3, "product", 0.1).c()
+    assert L.mm_plan_set_kernel(None, ctypes.byref(kk), None) == mm.MM_ERR_ARG
 
 
 def test_solver_entry_points_reject_null_handles_on_host():
@@ -100,6 +102,7 @@ def test_solver_entry_points_reject_null_handles_on_host():
     assert L.mm_solver_iterate(None, 1, None) == mm.MM_ERR_ARG
     assert L.mm_solver_poll(None, None, None, None, None) == mm.MM_ERR_ARG
     assert L.mm_solver_finish(None, None, None, None, None) == mm.MM_ERR_ARG
+    assert L.mm_solver_check(None, 1, None, None, None) == mm.MM_ERR_ARG
     assert L.mm_solver_destroy(None) == mm.MM_OK
     assert L.mm_solver_batch_create(None, 0, 1, ctypes.byref(h)) == mm.MM_ERR_ARG
     assert L.mm_solver_batch_iterate(None, 1, None) == mm.MM_ERR_ARG

@@ -44,3 +44,74 @@ def test_torch_allocator_serves_every_buffer(oracle_lib):
     for a, b in zip(ref[:2], got[:2]):
         assert np.array_equal(a, b)
     assert np.array_equal(ref[2], got[2])
+
+
+def test_allocator_switch_with_live_objects():
+    """Objects created under one allocator are released through it after the
+    process has switched allocators (the callbacks stay alive)."""
+    p = workloads.random_problem(9701, 2000, 2, 3, "product", 0.1)
+    mm.use_torch_allocator(True)
+    try:
+        plan_a = mm.Plan(to_gpu(p.x), mm.Kernel(3, "product", 0.1))
+        ya = to_np(plan_a.mvm(to_gpu(p.v)))
+        mm.use_torch_allocator(True)              # a second registration replaces the first
+        plan_b = mm.Plan(to_gpu(p.x), mm.Kernel(3, "product", 0.1))
+    finally:
+        mm.use_torch_allocator(False)             # back to hipMalloc with both plans alive
+    plan_c = mm.Plan(to_gpu(p.x), mm.Kernel(3, "product", 0.1))
+    yb = to_np(plan_b.mvm(to_gpu(p.v)))
+    yc = to_np(plan_c.mvm(to_gpu(p.v)))
+    plan_a.close()                                # frees through the first pair of callbacks
+    plan_b.close()
+    plan_c.close()
+    assert np.array_equal(ya, yb) and np.array_equal(ya, yc)
+
+
+def test_nomem_from_the_caller_allocator():
+    """An allocator that runs out (returns NULL) makes the call fail with
+    MM_ERR_NOMEM; buffers obtained before the failure are returned to it."""
+    import ctypes
+    import torch
+    p = workloads.random_problem(9702, 3000, 2, 3, "product", 0.1)
+    x = to_gpu(p.x)
+    for allow in (0, 3):
+        live = {}
+
+        def _alloc(nbytes, stream, ctx):
+            if len(live) >= allow:
+                return None
+            ptr = int(torch.cuda.caching_allocator_alloc(int(nbytes)))
+            live[ptr] = nbytes
+            return ptr
+
+        def _free(ptr, stream, ctx):
+            live.pop(int(ptr))
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        fa, ff = mm._ALLOC_FN(_alloc), mm._FREE_FN(_free)
+        mm._allocator_refs.append((fa, ff))
+        L = mm.lib()
+        assert L.mm_set_allocator(ctypes.cast(fa, ctypes.c_void_p), ctypes.cast(ff, ctypes.c_void_p), None) == 0
+        try:
+            with pytest.raises(mm.MaternError) as e:
+                mm.Plan(x, mm.Kernel(3, "product", 0.1))
+        finally:
+            mm.use_torch_allocator(False)
+        say("allocator allowing %d buffers: %s" % (allow, e.value))
+        assert e.value.status == mm.MM_ERR_NOMEM
+        assert not live                           # every buffer it gave went back
+    # a plan's product workspace is allocated at the first product: NOMEM there too
+    plan = mm.Plan(x, mm.Kernel(3, "product", 0.1))
+    fa = mm._ALLOC_FN(lambda n, s, c: None)
+    ff = mm._FREE_FN(lambda ptr, s, c: None)
+    mm._allocator_refs.append((fa, ff))
+    assert mm.lib().mm_set_allocator(ctypes.cast(fa, ctypes.c_void_p), ctypes.cast(ff, ctypes.c_void_p), None) == 0
+    try:
+        with pytest.raises(mm.MaternError) as e:
+            plan.mvm(to_gpu(p.v))
+    finally:
+        mm.use_torch_allocator(False)
+    assert e.value.status == mm.MM_ERR_NOMEM
+    y = to_np(plan.mvm(to_gpu(p.v)))              # usable again with hipMalloc
+    assert np.all(np.isfinite(y))
+    plan.close()

@@ -12,7 +12,7 @@ import pytest
 import oracle
 import paper_2508_01864_amd as mm
 import workloads
-from gpu_util import SOLVE_TOL, say, to_gpu, to_np
+from gpu_util import SOLVE_TOL, converged, say, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -54,12 +54,13 @@ def _solve_batched(probs, fe, rtol, maxit, use_graph, chunk=8):
         solvers.append(mm.Solver(plan, to_gpu(pr["y"]), pr["sig2"], fixed_effects=fe, rtol=rtol))
     batch = mm.SolverBatch(solvers, use_graph=use_graph)
     done = 0
+    passed = [False] * len(solvers)
     while done < maxit:
         batch.iterate(chunk)
         done += chunk
         # unrelated eager work on the same stream between graph replays
         _ = to_gpu(np.arange(1000.0)).sum()
-        if all(a == 0 for a in batch.poll()):
+        if converged(solvers, batch.poll(), passed):
             break
     outs = []
     for s in solvers:
@@ -83,7 +84,7 @@ def test_solver_steps_equal_gp_cg_solve(oracle_lib):
         s.iterate(5)
         act, brk, info = s.poll()
         assert brk == 0
-        if act == 0:
+        if act == 0 and s.check(tighten=True)[0]:
             break
     alpha, beta, info = s.finish()
     say("steps: iters %d vs %d" % (info["iters"], i0["iters"]))

@@ -45,12 +45,14 @@ def test_dlengthscale_tiny_with_ties(oracle_lib, d, two_nu, form):
             assert comp <= MVM_TOL and nrm <= MVM_TOL, (n, ties, comp, nrm)
 
 
-@pytest.mark.parametrize("d,n", [(1, 5000), (2, 3000), (2, 5001), (3, 2500)])
+# d = 1 has one form (the two coincide), so it is listed once
+DL_TILE_CASES = [(d, n, form) for d, n in [(1, 5000), (2, 3000), (2, 5001), (3, 2500)]
+                 for form in (["product"] if d == 1 else ["l1", "product"])]
+
+
+@pytest.mark.parametrize("d,n,form", DL_TILE_CASES)
 @pytest.mark.parametrize("two_nu", [1, 3, 5])
-@pytest.mark.parametrize("form", ["l1", "product"])
 def test_dlengthscale_several_tiles(oracle_lib, d, n, two_nu, form):
-    if d == 1 and form == "l1":
-        pytest.skip("one dimension: the forms coincide")
     p = workloads.random_problem(8000 + n + two_nu, n, d, two_nu, form, 0.05 if d < 3 else 0.15)
     say("dl tiles d=%d n=%d nu=%d/2 %s" % (d, n, two_nu, form))
     comp, nrm = dl_case(p.x, p.v, two_nu, form, p.ell)

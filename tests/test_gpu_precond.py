@@ -13,7 +13,7 @@ import pytest
 import oracle
 import paper_2508_01864_amd as mm
 import workloads
-from gpu_util import SOLVE_TOL, say, to_gpu, to_np
+from gpu_util import SOLVE_TOL, converged, say, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -107,9 +107,10 @@ def test_pcg_gls_and_batch_equal_alone(oracle_lib):
     solvers = [mm.Solver(pl, to_gpu(y), 0.02, fixed_effects=True, rtol=1e-12, precond=pc if i != 3 else None)
                for i, (pl, pc, (x, y, d)) in enumerate(zip(plans, pcs, probs))]
     batch = mm.SolverBatch(solvers, use_graph=True)
+    passed = [False] * len(solvers)
     for _ in range(400):
         batch.iterate(8)
-        if all(a == 0 for a in batch.poll()):
+        if converged(solvers, batch.poll(), passed):
             break
     for i, (s, (a0, b0, it0)) in enumerate(zip(solvers, alone)):
         a, b, info = s.finish()

@@ -112,3 +112,59 @@ def test_no_convergence_reported(oracle_lib):
     assert info["status"] == "MM_ERR_NOCONV" and info["iters"] == 3
     assert np.all(np.isfinite(to_np(alpha)))
     plan.close()
+
+
+def test_config2_full_solve_oracle_residual(oracle_lib):
+    """Configuration 2's metric solve (N = 100,000, fixed effects, rtol 1e-8):
+    the residual y - H beta - (K + sigma^2 I) alpha recomputed with the oracle's
+    dense product over every row must meet rtol (Appendix A, Algorithm 2;
+    Section 3.2), and the library's own recomputed residual must agree with it."""
+    p = workloads.config2()
+    plan = mm.Plan(to_gpu(p.x), mm.Kernel(3, "product", 0.1))
+    alpha, beta, info = plan.cg_solve(to_gpu(p.y), 0.01, fixed_effects=True, rtol=1e-8, maxit=20000)
+    a = to_np(alpha)
+    say("config2 n=100000: iters %d, recurrence %.3e, library residual %.4e" %
+        (info["iters"], info["relres_max"], info["true_relres"]))
+    ka = oracle.mvm(p.x, a, 3, "product", 0.1)
+    res = p.y - oracle.design_matrix(p.x) @ beta - ka - 0.01 * a
+    rel_res = float(np.linalg.norm(res) / np.linalg.norm(p.y))
+    say("oracle residual %.4e (oracle on %d threads)" % (rel_res, oracle.num_threads()))
+    assert info["status"] == "MM_OK"
+    assert rel_res <= 1e-8
+    assert info["true_relres"] <= 1e-8
+    # both evaluate the same residual; its rounding is ~eps ||K|alpha|| / (1e-8 ||y||)
+    assert abs(info["true_relres"] - rel_res) <= 1e-3 * rel_res
+    plan.close()
+
+
+def test_check_mid_solve_restarts_and_converges(oracle_lib):
+    """mm_solver_check on a solver that has not converged: its recomputed
+    residual matches the oracle's for the current iterate, the solve restarts
+    from it, and the continued solve still reaches the Cholesky solution."""
+    n, d, ell, sig2 = 1500, 2, 0.15, 0.01
+    p = workloads.random_problem(611, n, d, 3, "product", ell)
+    y = workloads.field_sin_cos(p.x) + 0.1 * np.random.default_rng(2).standard_normal(n)
+    plan = mm.Plan(to_gpu(p.x), mm.Kernel(3, "product", ell))
+    s = mm.Solver(plan, to_gpu(y), sig2, rtol=1e-12)
+    s.iterate(7)
+    passed, trel = s.check(tighten=True)
+    alpha7, _, _ = s.finish(raise_on_error=False)
+    a7 = to_np(alpha7)
+    ref7 = np.linalg.norm(y - oracle.mvm(p.x, a7, 3, "product", ell) - sig2 * a7) / np.linalg.norm(y)
+    say("after 7 iterations: library residual %.6e, oracle %.6e" % (trel, ref7))
+    assert not passed
+    assert abs(trel - ref7) <= 1e-6 * ref7
+    for _ in range(4000):
+        s.iterate(8)
+        act, brk, _ = s.poll()
+        assert brk == 0
+        if act == 0 and s.check(tighten=True)[0]:
+            break
+    alpha, _, info = s.finish()
+    ref = oracle.gp_solve(p.x, y, 3, "product", ell, 1.0, sig2)
+    say("restarted solve: iters %d err %.2e residual %.2e" % (info["iters"], rel(to_np(alpha), ref),
+                                                             info["true_relres"]))
+    assert info["true_relres"] <= 1e-12
+    assert rel(to_np(alpha), ref) <= SOLVE_TOL
+    s.close()
+    plan.close()
