@@ -1,41 +1,42 @@
 #!/usr/bin/env python3
 """Benchmark of the exact Matern kernel product and the GP solve built on it.
 
-Workload: d = 2, N = 100,000, nu = 3/2, product form, lengthscale 0.1,
-x ~ U[0,1]^2, y = sin(2 pi x1) cos(2 pi x2) + N(0, 0.1^2), sigma^2 = 0.01
-(synthetic, seeded).
+Headline workload: d = 2, N = 100,000, nu = 3/2, product form, lengthscale 0.1,
+x ~ U[0,1]^2 (synthetic, seeded), plan prebuilt, inputs resident in HBM.
 
-One step is one pass of the whole hot path with the inputs already in HBM:
-  plan build (sort, stored divide-and-conquer orders)  ->  one plain product
-  y = K v  ->  conjugate-gradient solve of (K + sigma^2 I) with the linear
-  fixed effects [1, x1, x2] (GLS), relative residual 1e-8  ->  posterior mean
-  at 1000 new points.
-`value` is the number of product point-columns (N x right-hand sides, summed
-over every product of the step) per second of step wall time.
+One step is one call of matern_mvm, y = K v, on that plan with 32 right-hand
+sides (the width of the multi-probe products).  `value` is N x nrhs / step
+time (product point-columns per second) over the timed steps.
 
 Also printed in the same JSON line:
-  roofline      the dominant kernel, the divide-and-conquer sweep launch of a CG
-                iteration (one launch covers every pass of the 4-column product):
-                algorithmic bytes per launch (passes x N x (4 + 16 x 4)) over its
-                average duration, measured with HIP events on its stream during
-                the timed solves, against the 8 TB/s HBM peak; `traffic` is the
-                measured HBM bytes per launch from the committed rocprofv3 counter
-                summary, when that summary matches the current kernel source;
-  mvm           the plain product alone at 1, 8 and 32 right-hand sides;
-  batched       256 independent problems of uneven N, d, nu and lengthscale
-                (N log-uniform in [1e3, 2e5], d in {1,2,3}, nu in {1/2,3/2,5/2}):
-                one product each and a fixed number of CG iterations each, run
-                batched (shared launches, HIP-graph replay, autotuned grids)
-                and one problem at a time through the plain entry points, on
-                the same inputs; results are checked bitwise equal;
-  pcg           the same solve with the rank-100 pivoted Cholesky preconditioner
-                against plain CG: iterations and time to solution;
-  served        a bounded sample of the served GP-regression stream (fixed
-                effects, Poisson arrivals at 0.9x the plain path's measured
-                capacity): p50/p99 latency and solves/s of the continuous-
-                batching server against first-come-first-served plain solves;
+  roofline      the dominant kernel, the main divide-and-conquer sweep launch of
+                the headline product (one launch covers every pass): algorithmic
+                bytes per launch (passes x N x (4 + 16 x 32)) over its average
+                duration measured with HIP events on its stream during the timed
+                steps, against the 8 TB/s HBM peak; `traffic` is the measured HBM
+                bytes per launch from the committed rocprofv3 counter summary,
+                when that summary matches the current kernel source;
+  mvm           the median of one product (product and L1 forms) at 1, 8 and
+                32 right-hand sides: points/s and the fraction of the HBM peak and
+                of the measured copy bandwidth for the whole call against the
+                level-streaming bytes N (8d + 16 nrhs + L (4 + 16 nrhs)), with the
+                main sweep launch's own fraction beside it;
+  plan_build_s  the plan build (sorts and stored orders), timed on its own;
+  stream_copy   a device-to-device copy's measured bandwidth (read + write);
+  solve         the configuration-2 GP regression: plan build, CG with the linear
+                fixed effects (GLS) to relative residual 1e-8 and prediction at
+                1000 points; the residual of the returned solution recomputed with
+                the CPU oracle's dense product over every row;
+  pcg           the same solve with the rank-100 pivoted Cholesky preconditioner;
+  gradient      lengthscale-derivative products and the likelihood gradient;
+  config3       d = 3, N = 500,000, nu = 5/2: the 32-probe product, the stochastic
+                log-determinant and one preconditioned solve;
+  batched       256 independent problems of uneven N, d, nu and lengthscale,
+                batched against one at a time, results checked bitwise equal;
+  served        a bounded sample of the served GP-regression stream at three
+                arrival rates against first-come-first-served plain solves;
   cpu_baseline  the dense FP64 CPU oracle timed on a bounded sample of target
-                rows of the same product (all host cores).
+                rows of the headline product (all host cores).
 """
 from __future__ import annotations
 
@@ -71,7 +72,7 @@ def b_pass(n: int, cols: int) -> float:
     return float(n) * (4.0 + 16.0 * cols)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_main_d2_n100k_nu32_w4.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_main_d2_n100k_nu32_w32.txt")
 SWEEP_SRC = os.path.join(ROOT, "paper_2508_01864_amd", "csrc", "sweep_core.h")
 
 
@@ -95,21 +96,164 @@ def recorded_traffic():
         return None
 
 
-def cpu_baseline(x, v, seconds: float):
+def host_cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(x, nrhs: int, seconds: float):
+    """The oracle's dense product (each kernel entry evaluated once for all
+    columns) on a bounded sample of target rows of the headline product."""
     import oracle
     oracle.build(force=False)
-    rows = 200
+    v = np.random.default_rng(7 + nrhs).standard_normal((N, nrhs))
+    rows = 50
     t0 = time.perf_counter()
-    oracle.mvm(x, v, TWO_NU, "product", ELL, z=x[:rows])
+    oracle.mvm(x, v, TWO_NU, "product", ELL, z=x[:rows], shared_kernel=True)
     dt = time.perf_counter() - t0
     rows = int(min(N, max(rows, rows * seconds / max(dt, 1e-6))))
     t0 = time.perf_counter()
-    oracle.mvm(x, v, TWO_NU, "product", ELL, z=x[:rows])
+    oracle.mvm(x, v, TWO_NU, "product", ELL, z=x[:rows], shared_kernel=True)
     dt = time.perf_counter() - t0
-    return {"value": rows / dt, "unit": "points/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "dense FP64 product K v for %d of the %d target rows (nrhs=1, %.1f s), "
-                      "points/s = rows / time" % (rows, N, dt)}
+    return {"value": rows * nrhs / dt, "unit": "points/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "cpu_model": host_cpu_model(),
+            "sample": "dense FP64 product K v for %d of the %d target rows at nrhs=%d (%.1f s); "
+                      "points/s = rows x nrhs / time" % (rows, N, nrhs, dt)}
+
+
+def b_alg(n: int, d: int, nrhs: int, L: int) -> float:
+    """Level-streaming algorithmic bytes of one product: x and v read, y written
+    once, and per pass the 4-byte order index plus, per column, an 8-byte weight
+    read and an 8-byte partial-sum write per point."""
+    return float(n) * (8.0 * d + 16.0 * nrhs + L * (4.0 + 16.0 * nrhs))
+
+
+def stream_copy_gbs(dev, mib: int = 1024, reps: int = 10) -> float:
+    """Measured device-to-device copy bandwidth, bytes read + written per second."""
+    import torch
+    src = torch.ones(mib * 131072, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del src, dst
+    return 2.0 * mib * 1048576 / (float(np.median(ts)) * 1e-3) / 1e9
+
+
+def median_ms(fn, reps: int) -> float:
+    """Median of `reps` single calls timed with HIP events on the current stream."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def bench_mvm(mm, x, dev, reps: int, copy_gbs: float):
+    """Median matern_mvm at 1, 8 and 32 columns, product and L1 forms."""
+    import torch
+    L = mm.levels(N)
+    out = {}
+    for form in ("product", "l1"):
+        plan = mm.Plan(x, mm.Kernel(TWO_NU, form, ELL))
+        rows = {}
+        for nrhs in (1, 8, 32):
+            vv = torch.as_tensor(np.random.default_rng(7 + nrhs).standard_normal((nrhs, N)), device=dev)
+            yy = torch.empty_like(vv)
+            for _ in range(3):
+                plan.mvm_raw(vv, yy, nrhs)
+            torch.cuda.synchronize()
+            ms = median_ms(lambda: plan.mvm_raw(vv, yy, nrhs), reps)
+            plan.profile_enable(True)
+            plan.profile_read(reset=True)
+            for _ in range(reps):
+                plan.mvm_raw(vv, yy, nrhs)
+            sms, scnt, _ = plan.profile_read(reset=True)
+            plan.profile_enable(False)
+            sweep_ms = sms / max(scnt, 1)
+            ba = b_alg(N, D, nrhs, L)
+            rows[str(nrhs)] = {
+                "median_ms": round(ms, 4), "points_per_s": N * nrhs / (ms * 1e-3),
+                "b_alg_bytes": ba, "gbs": ba / (ms * 1e-3) / 1e9,
+                "frac_hbm_peak": ba / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "frac_copy_peak": ba / (ms * 1e-3) / 1e9 / copy_gbs,
+                "main_sweep_ms": round(sweep_ms, 4),
+                "main_sweep_frac_hbm_peak": L * b_pass(N, nrhs) / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            }
+            log("mvm %s nrhs=%d: median %.4f ms, %.3e points/s, %.3f of HBM peak" %
+                (form, nrhs, ms, N * nrhs / (ms * 1e-3), rows[str(nrhs)]["frac_hbm_peak"]))
+        plan.close()
+        out[form] = rows
+    return out
+
+
+def oracle_residual(x, y, alpha, beta, sigma2: float) -> float:
+    """||y - H beta - (K + sigma2 I) alpha|| / ||y|| with the oracle's dense product."""
+    import oracle
+    oracle.build(force=False)
+    ka = oracle.mvm(x, alpha, TWO_NU, "product", ELL)
+    res = y - oracle.design_matrix(x) @ np.asarray(beta) - ka - sigma2 * alpha
+    return float(np.linalg.norm(res) / np.linalg.norm(y))
+
+
+def bench_solve(mm, p, dev, reps: int, maxit: int, check_oracle: bool):
+    """Configuration 2's GP regression: plan, CG + GLS to 1e-8, predict 1000 points."""
+    import torch
+    x = torch.as_tensor(p.x, device=dev)
+    y = torch.as_tensor(p.y, device=dev)
+    z = torch.as_tensor(np.random.default_rng(20021).uniform(0.0, 1.0, size=(NPREDICT, D)), device=dev)
+    kern = mm.Kernel(TWO_NU, "product", ELL, 1.0)
+    best = None
+    for r in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = mm.Plan(x, kern)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        alpha, beta, info = plan.cg_solve(y, SIGMA2, fixed_effects=True, rtol=RTOL, maxit=maxit,
+                                          raise_on_error=maxit >= 20000)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        mean = plan.predict(alpha, z, beta=beta)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        plan.close()
+        rec = {"plan_build_s": t1 - t0, "solve_s": t2 - t1, "predict_s": t3 - t2, "total_s": t3 - t0,
+               "iters": info["iters"], "status": info["status"], "relres_recurrence": info["relres_max"],
+               "true_relres_library": info["true_relres"],
+               "per_iteration_ms": (t2 - t1) / max(info["iters"], 1) * 1e3}
+        log("solve %d: %d iterations, %.3f s, library residual %.3e" % (r, info["iters"], t2 - t1,
+                                                                        info["true_relres"]))
+        if best is None or rec["total_s"] < best["total_s"]:
+            best = rec
+            best_out = (alpha, beta, mean)
+    if check_oracle:
+        t0 = time.perf_counter()
+        best["true_relres_oracle"] = oracle_residual(p.x, p.y, best_out[0].cpu().numpy(), best_out[1], SIGMA2)
+        log("oracle residual %.4e (%.1f s)" % (best["true_relres_oracle"], time.perf_counter() - t0))
+    best["workload"] = ("d=2 N=%d nu=3/2 product ell=0.1 sigma2=0.01: plan build, CG + GLS (fixed effects "
+                        "1, x1, x2) to 1e-8, predict %d points" % (N, NPREDICT))
+    best["points_per_s"] = N * (1 + 4 * best["iters"]) / best["total_s"]
+    return best
 
 
 def _events_ms(fn, reps):
@@ -127,7 +271,7 @@ def _events_ms(fn, reps):
 def bench_pcg(mm, x, y, kern, rank, reps=2):
     """The headline solve (fixed effects, rtol 1e-8) with the rank-k pivoted
     Cholesky preconditioner, against plain CG: iterations and time to solution
-    (plan and preconditioner build included), and the true residual."""
+    (plan and preconditioner build included), and the library's recomputed residual."""
     import torch
     out = {"rank": rank}
     for label, use_pc in (("plain", False), ("preconditioned", True)):
@@ -142,14 +286,11 @@ def bench_pcg(mm, x, y, kern, rank, reps=2):
             alpha, beta, info = plan.cg_solve(y, SIGMA2, fixed_effects=True, rtol=RTOL, maxit=20000, precond=pc)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
-            Ka = plan.mvm(alpha, shift=SIGMA2)
-            H = torch.cat([torch.ones(N, 1, dtype=torch.float64, device=x.device), x], dim=1)
-            res = float(torch.linalg.norm(y - H @ torch.as_tensor(beta, device=x.device) - Ka) / torch.linalg.norm(y))
             if pc is not None:
                 pc.close()
             plan.close()
             rec = {"iters": info["iters"], "setup_s": t1 - t0, "solve_s": t2 - t1, "total_s": t2 - t0,
-                   "true_relres": res}
+                   "true_relres": info["true_relres"]}
             if best is None or rec["total_s"] < best["total_s"]:
                 best = rec
         out[label] = best
@@ -192,11 +333,12 @@ def bench_gradient(mm, x, y, kern, probes, reps):
     return out
 
 
-def bench_config3(dev, steps, rank):
+def bench_config3(dev, steps, rank, maxit):
     """d=3, N=500k, nu=5/2, lengthscale 0.3, x ~ N(0, I): one product with the 32
-    Rademacher probes (product and L1 forms), the stochastic log-determinant from
-    those probes (`steps` Lanczos steps), and one CG solve of the sin/cos
-    targets (sigma2 0.01) preconditioned with the rank-`rank` pivoted Cholesky."""
+    Rademacher probes (product and L1 forms, median of 3), the stochastic
+    log-determinant from those probes (`steps` Lanczos steps), and one CG solve
+    of the sin/cos targets (sigma2 0.01, rtol 1e-8, at most `maxit` iterations)
+    preconditioned with the rank-`rank` pivoted Cholesky."""
     import torch
     import paper_2508_01864_amd as mm
     import workloads
@@ -214,8 +356,11 @@ def bench_config3(dev, steps, rank):
         Zc = Z.t().contiguous()
         Yc = torch.empty_like(Zc)
         plan.mvm_raw(Zc, Yc, 32)
-        ms = _events_ms(lambda: plan.mvm_raw(Zc, Yc, 32), 2)
-        out[form] = {"plan_build_s": tb, "mvm32_ms": ms, "points_per_s": n * 32 / (ms * 1e-3)}
+        ms = median_ms(lambda: plan.mvm_raw(Zc, Yc, 32), 3)
+        Lp = mm.passes(n, 3)
+        ba = float(n) * (8.0 * 3 + 16.0 * 32 + Lp * (4.0 + 16.0 * 32))
+        out[form] = {"plan_build_s": tb, "mvm32_ms": ms, "points_per_s": n * 32 / (ms * 1e-3),
+                     "b_alg_bytes": ba, "frac_hbm_peak": ba / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         log("config 3 %s: 32-column product %.1f ms" % (form, ms))
         if form == "product":
             torch.cuda.synchronize()
@@ -232,11 +377,13 @@ def bench_config3(dev, steps, rank):
             pc = mm.Precond(plan, max_rank=rank)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            alpha, _, info = plan.cg_solve(y, 0.01, rtol=1e-8, maxit=4000, precond=pc, raise_on_error=False)
+            alpha, _, info = plan.cg_solve(y, 0.01, rtol=1e-8, maxit=maxit, precond=pc, raise_on_error=False)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
             out["pcg_solve"] = {"rank": rank, "precond_s": t1 - t0, "solve_s": t2 - t1, "iters": info["iters"],
-                                "status": info["status"], "relres": info["relres_max"]}
+                                "maxit": maxit, "status": info["status"], "relres": info["relres_max"],
+                                "true_relres": info["true_relres"],
+                                "per_iteration_ms": (t2 - t1) / max(info["iters"], 1) * 1e3}
             log("config 3 PCG: %d iterations, %.2f s" % (info["iters"], t2 - t1))
             pc.close()
         plan.close()
@@ -314,73 +461,91 @@ def bench_batched(dev, count, iters):
     }
 
 
-def bench_served(dev, count):
-    """The served stream against plain first-come-first-served solves."""
+SERVED_N_HI = 30_000
+SERVED_RANK = 64
+
+
+def bench_served(dev, count, rates):
+    """A bounded sample of the served stream against plain first-come-first-served
+    solves, at several arrival rates (multiples of the plain path's measured
+    capacity).  The sample is the first `count` requests of the configuration-5
+    stream with N log-uniform in [5e3, 3e4] (instead of [5e3, 3e5]), each solved
+    by rank-64 preconditioned CG on both paths."""
     import torch
     import paper_2508_01864_amd as mm
     from paper_2508_01864_amd import serve
     import workloads
-    probs = workloads.config5(count=count, rate=1.0)
+    probs = workloads.config5(count=count, rate=1.0, n_hi=SERVED_N_HI)
     base = [p.arrival for p in probs]          # unit-rate Poisson arrival times
     reqs = [serve.Request(k, 0.0, p.x, p.y, mm.Kernel(p.two_nu, p.form, p.ell), p.sigma2, p.z,
-                          rtol=1e-8, maxit=20000) for k, p in enumerate(probs)]
+                          rtol=1e-8, maxit=20000, precond_rank=SERVED_RANK) for k, p in enumerate(probs)]
     # plain service times (all requests back to back) give the plain capacity
-    def done(tag):
-        return lambda r: log("%s: request %d (n=%d) done, %d iterations" % (tag, r.rid, len(reqs[r.rid].y),
-                                                                          r.info.get("iters", -1)))
-
-    plain0 = serve.run_plain(reqs, on_done=done("plain"))
+    plain0 = serve.run_plain(reqs)
     service = [r.done - r.admitted for r in plain0]
     cap = len(reqs) / sum(service)
-    rate = 0.9 * cap
-    for r, a in zip(reqs, base):
-        r.arrival = a / rate
-    # plain FIFO latencies for these arrivals from the measured service times
-    free_at = 0.0
-    plain = []
-    for r, sv in zip(reqs, service):
-        start = max(free_at, r.arrival)
-        free_at = start + sv
-        plain.append(serve.Response(r.rid, r.arrival, start, free_at, None, None, None, {}))
-    srv = serve.Server(chunk=16)
-    served = srv.run(reqs, on_done=done("served"))
-    same = all(torch.equal(a.alpha, b.alpha) and torch.equal(a.mean, b.mean) for a, b in zip(served, plain0))
-    sp, ss = serve.summary(plain), serve.summary(served)
-    return {
-        "workload": "first %d requests of the served stream: N log-uniform [5e3, 3e5], d/nu uniform, "
-                    "sigma2 log-uniform [1e-3, 1e-1], affine trend + sin/cos field, fixed effects, "
-                    "1000 predict points, rtol 1e-8; Poisson arrivals at 0.9x plain capacity" % count,
-        "n": [len(r.y) for r in reqs], "d": [int(r.x.shape[1]) for r in reqs],
-        "rate_per_s": rate, "plain_capacity_per_s": cap,
-        "plain": sp, "served": ss, "served_bitwise_equal_alone": bool(same),
-        "iters": [r.info["iters"] for r in served],
-        "server": {"ticks": srv.ticks, "rebuilds": srv.rebuilds, "peak_slots": srv.peak_slots,
-                   "peak_bytes": srv.peak_bytes, "budget_bytes": srv.budget},
+    log("served: plain capacity %.2f solves/s over %d requests" % (cap, len(reqs)))
+    out = {
+        "workload": "first %d requests of the served stream with N log-uniform [5e3, %d] (bounded sample; the "
+                    "stream's own range is [5e3, 3e5]), d/nu uniform, sigma2 log-uniform [1e-3, 1e-1], affine "
+                    "trend + sin/cos field, fixed effects, rank-%d pivoted Cholesky PCG to rtol 1e-8, 1000 "
+                    "predict points; Poisson arrivals at the given multiples of the plain path's measured "
+                    "capacity" % (count, SERVED_N_HI, SERVED_RANK),
+        "requests": count, "n": [len(r.y) for r in reqs], "d": [int(r.x.shape[1]) for r in reqs],
+        "plain_capacity_per_s": cap,
+        "plain_latency_note": "plain-path latencies follow from the measured service times by the "
+                              "first-come-first-served recursion on the same arrivals",
+        "rates": {},
     }
+    for mult in rates:
+        rate = mult * cap
+        for r, a in zip(reqs, base):
+            r.arrival = a / rate
+        free_at = 0.0
+        plain = []
+        for r, sv in zip(reqs, service):
+            start = max(free_at, r.arrival)
+            free_at = start + sv
+            plain.append(serve.Response(r.rid, r.arrival, start, free_at, None, None, None, {}))
+        srv = serve.Server(chunk=16)
+        served = srv.run(reqs)
+        same = all(torch.equal(a.alpha, b.alpha) and torch.equal(a.mean, b.mean) for a, b in zip(served, plain0))
+        sp, ss = serve.summary(plain), serve.summary(served)
+        log("served at %.1fx capacity: p50 %.3f s p99 %.3f s (plain %.3f / %.3f), %.2f vs %.2f solves/s" %
+            (mult, ss["p50_s"], ss["p99_s"], sp["p50_s"], sp["p99_s"], ss["solves_per_s"], sp["solves_per_s"]))
+        out["rates"]["%.1f" % mult] = {
+            "rate_per_s": rate, "plain": sp, "served": ss, "served_bitwise_equal_alone": bool(same),
+            "server": {"ticks": srv.ticks, "rebuilds": srv.rebuilds, "peak_slots": srv.peak_slots,
+                       "peak_bytes": srv.peak_bytes, "budget_bytes": srv.budget}}
+    out["iters"] = [r.info["iters"] for r in plain0]
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mvm-reps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--nrhs", type=int, default=32, help="right-hand sides of the headline product")
+    ap.add_argument("--mvm-reps", type=int, default=21)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mvm", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-oracle-residual", action="store_true")
     ap.add_argument("--batched-count", type=int, default=256)
     ap.add_argument("--batched-iters", type=int, default=32)
-    ap.add_argument("--served-count", type=int, default=4)
+    ap.add_argument("--served-count", type=int, default=32)
+    ap.add_argument("--served-rates", type=str, default="0.5,0.9,1.2")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--config3", action="store_true",
-                    help="also run the d=3 N=500k nu=5/2 section: one 32-probe product, the "
-                         "stochastic log-determinant from those probes and one preconditioned solve")
+    ap.add_argument("--no-config3", action="store_true")
     ap.add_argument("--logdet-steps", type=int, default=30)
     ap.add_argument("--lml-probes", type=int, default=31,
                     help="probes of the likelihood-gradient section (0: skip the section)")
     ap.add_argument("--pcg-rank", type=int, default=100,
                     help="rank of the pivoted Cholesky preconditioner of the extra PCG section (0: skip)")
+    ap.add_argument("--c3-rank", type=int, default=256, help="preconditioner rank of the configuration-3 solve")
+    ap.add_argument("--c3-maxit", type=int, default=3000)
     ap.add_argument("--maxit", type=int, default=20000,
                     help="CG iteration limit (below the default only for short profiling runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -399,32 +564,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     p = workloads.config2()
-    rng = np.random.default_rng(20021)
-    z_np = rng.uniform(0.0, 1.0, size=(NPREDICT, D))
     x = torch.as_tensor(p.x, device=dev)
-    y = torch.as_tensor(p.y, device=dev)
-    v = torch.as_tensor(p.v, device=dev)
-    z = torch.as_tensor(z_np, device=dev)
     kern = mm.Kernel(TWO_NU, "product", ELL, 1.0)
     L = mm.levels(N)
-
-    def step(profile: bool):
-        plan = mm.Plan(x, kern)
-        y1 = plan.mvm(v)
-        if profile:                          # bracket the solve's sweep launches only
-            plan.profile_enable(True)
-        alpha, beta, info = plan.cg_solve(y, SIGMA2, fixed_effects=True, rtol=RTOL, maxit=args.maxit,
-                                          raise_on_error=args.maxit >= 20000)
-        prof = plan.profile_read() if profile else (0.0, 0, 0)
-        if profile:
-            plan.profile_enable(False)
-        mean = plan.predict(alpha, z, beta=beta)
-        plan.close()
-        cols = 1 + 4 * info["iters"]        # plain product + CG columns (y, 1, x1, x2)
-        pts = N * cols + (N + NPREDICT)      # + predict on the union of points
-        # algorithmic bytes of the profiled launches: one per CG iteration, L passes, 4 columns
-        sweep_bytes = info["iters"] * L * b_pass(N, 4)
-        return pts, info, prof, sweep_bytes, (y1, alpha, beta, mean)
+    R = args.nrhs
 
     if args.calib_copy_mib > 0:
         src = torch.ones(args.calib_copy_mib * 131072, dtype=torch.float64, device=dev)
@@ -435,86 +578,69 @@ def main():
         log("calibration copy: %d MiB read + %d MiB written per launch" % (args.calib_copy_mib, args.calib_copy_mib))
         del src, dst
 
-    for w in range(args.warmup):
-        log("warmup step %d" % w)
-        step(False)
-    torch.cuda.synchronize()
+    # plan build, timed on its own (median of three)
+    builds = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = mm.Plan(x, kern)
+        torch.cuda.synchronize()
+        builds.append(time.perf_counter() - t0)
+        plan.close()
+    plan_build_s = float(np.median(builds))
+    log("plan build %.4f s" % plan_build_s)
 
+    # the headline: one product with R columns per step
+    plan = mm.Plan(x, kern)
+    vv = torch.as_tensor(np.random.default_rng(7 + R).standard_normal((R, N)), device=dev)
+    yy = torch.empty_like(vv)
+    for _ in range(args.warmup):
+        plan.mvm_raw(vv, yy, R)
+    torch.cuda.synchronize()
     log("timed steps: %d" % args.steps)
+    plan.profile_enable(True)
+    plan.profile_read(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tot_pts = 0
-    tot_ms = 0.0
-    tot_launch = 0
-    tot_bytes = 0.0
-    iters = []
-    last = None
-    for s in range(args.steps):
-        pts, info, prof, sb, last = step(True)
-        tot_pts += pts
-        tot_ms += prof[0]
-        tot_launch += prof[1]
-        tot_bytes += sb
-        iters.append(info["iters"])
-        log("step %d: CG iters %d relres %.2e" % (s, info["iters"], info["relres_max"]))
+    for _ in range(args.steps):
+        plan.mvm_raw(vv, yy, R)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    value = tot_pts / elapsed
-    avg_launch_ms = tot_ms / max(tot_launch, 1)
-    # algorithmic bytes per launch (total over the launches / their number) over the
-    # average launch duration
-    achieved = (tot_bytes / max(tot_launch, 1)) / (avg_launch_ms * 1e-3) / 1e9 if tot_launch else 0.0
-
-    # true residual of the last solve: ||y - H beta - (K + s I) alpha|| / ||y||
-    _, alpha, beta, _ = last
-    plan = mm.Plan(x, kern)
-    Ka = plan.mvm(alpha, shift=SIGMA2)
-    H = torch.cat([torch.ones(N, 1, dtype=torch.float64, device=dev), x], dim=1)
-    bt = torch.as_tensor(beta, device=dev)
-    true_res = float(torch.linalg.norm(y - H @ bt - Ka) / torch.linalg.norm(y))
-
-    mvm_rows = {}
-    if not args.no_mvm:
-        for nrhs in (1, 8, 32):
-            vv = torch.as_tensor(np.random.default_rng(7 + nrhs).standard_normal((nrhs, N)), device=dev)
-            yy = torch.empty_like(vv)
-            for _ in range(3):
-                plan.mvm_raw(vv, yy, nrhs)
-            plan.profile_enable(True)
-            plan.profile_read(reset=True)
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(args.mvm_reps):
-                plan.mvm_raw(vv, yy, nrhs)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / args.mvm_reps
-            sms, scnt, _ = plan.profile_read(reset=True)
-            plan.profile_enable(False)
-            sweep_ms = sms / max(scnt, 1)           # one launch covers all L passes
-            mvm_rows[str(nrhs)] = {
-                "ms": round(ms, 4), "points_per_s": N * nrhs / (ms * 1e-3),
-                "sweep_ms": round(sweep_ms, 4),
-                "sweep_gbs": L * b_pass(N, nrhs) / (sweep_ms * 1e-3) / 1e9,
-            }
-            log("mvm nrhs=%d: %.3f ms (%.3e points/s)" % (nrhs, ms, N * nrhs / (ms * 1e-3)))
+    sms, scnt, _ = plan.profile_read(reset=True)
+    plan.profile_enable(False)
     plan.close()
+    value = N * R * args.steps / elapsed
+    avg_launch_ms = sms / max(scnt, 1)
+    bytes_launch = L * b_pass(N, R)
+    achieved = bytes_launch / (avg_launch_ms * 1e-3) / 1e9 if scnt else 0.0
+    log("headline: %.4f ms per product, %.3e points/s; main sweep %.4f ms, %.0f GB/s" %
+        (elapsed / args.steps * 1e3, value, avg_launch_ms, achieved))
+
+    copy_gbs = stream_copy_gbs(dev)
+    log("device copy: %.0f GB/s (read + write)" % copy_gbs)
+
+    mvm_rows = None
+    if not args.no_mvm:
+        mvm_rows = bench_mvm(mm, x, dev, args.mvm_reps, copy_gbs)
+
+    solve_out = None
+    if not args.no_solve:
+        solve_out = bench_solve(mm, p, dev, 2, args.maxit, not args.no_oracle_residual)
 
     pcg_out = None
     if args.pcg_rank > 0:
         log("preconditioned solve: rank %d" % args.pcg_rank)
-        pcg_out = bench_pcg(mm, x, y, kern, args.pcg_rank)
+        pcg_out = bench_pcg(mm, x, torch.as_tensor(p.y, device=dev), kern, args.pcg_rank)
 
     grad_out = None
     if args.lml_probes > 0:
         log("gradient: dK/dl products and the likelihood with %d probes" % args.lml_probes)
-        grad_out = bench_gradient(mm, x, y, kern, args.lml_probes, args.mvm_reps)
+        grad_out = bench_gradient(mm, x, torch.as_tensor(p.y, device=dev), kern, args.lml_probes, args.mvm_reps)
 
     c3_out = None
-    if args.config3:
+    if not args.no_config3:
         log("config 3: d=3 N=500k nu=5/2, 32 probes")
-        c3_out = bench_config3(dev, args.logdet_steps, args.pcg_rank or 100)
+        c3_out = bench_config3(dev, args.logdet_steps, args.c3_rank, args.c3_maxit)
 
     batched_out = None
     if not args.no_batched:
@@ -523,12 +649,12 @@ def main():
     served_out = None
     if not args.no_served and args.served_count > 0:
         log("served: %d requests" % args.served_count)
-        served_out = bench_served(dev, args.served_count)
+        served_out = bench_served(dev, args.served_count, [float(r) for r in args.served_rates.split(",")])
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(p.x, p.v, args.cpu_seconds)
+        cpu = cpu_baseline(p.x, R, args.cpu_seconds)
 
     out = {
         "metric": "Matern MVM points/s (N x nrhs) d=2 N=100k nu=3/2",
@@ -543,20 +669,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "d=2 N=100000 nu=3/2 product ell=0.1 sigma2=0.01: plan build, "
-                               "K v, CG+GLS to 1e-8, predict 1000 points",
-                   "n": N, "d": D, "two_nu": TWO_NU, "form": "product", "lengthscale": ELL,
-                   "sigma2": SIGMA2, "rtol": RTOL, "npredict": NPREDICT},
+        "config": {"workload": "matern_mvm y = K v, d=2 N=100000 nu=3/2 product form ell=0.1, "
+                               "x ~ U[0,1]^2, %d right-hand sides, plan prebuilt" % R,
+                   "n": N, "d": D, "two_nu": TWO_NU, "form": "product", "lengthscale": ELL, "nrhs": R},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(),
-                     "algorithmic_bytes_per_launch": L * b_pass(N, 4),
-                     "kernel": "sweep_batch_kernel<d=2, nu=3/2, product, 4 columns> main launch of a CG "
-                               "iteration (all %d divide-and-conquer passes per launch)" % L,
-                     "avg_launch_ms": avg_launch_ms, "launches": tot_launch},
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "kernel": "main divide-and-conquer sweep launch of the headline product "
+                               "(d=2, nu=3/2, product, %d columns; all %d passes per launch)" % (R, L),
+                     "avg_launch_ms": avg_launch_ms, "launches": scnt,
+                     "whole_product_frac": b_alg(N, D, R, L) / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS},
         "cpu_baseline": cpu,
-        "cg_iters": iters,
-        "true_relres": true_res,
+        "plan_build_s": plan_build_s,
+        "stream_copy_gbs": copy_gbs,
         "mvm": mvm_rows,
+        "solve": solve_out,
         "pcg": pcg_out,
         "gradient": grad_out,
         "config3": c3_out,

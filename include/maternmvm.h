@@ -133,6 +133,30 @@ size_t mm_plan_footprint_bytes(int64_t n, int32_t d, int32_t nrhs, const mm_kern
 mm_status mm_plan_create(const double *x, int64_t n, int32_t d, int64_t ldx,
                          const mm_kernel *kernel, void *stream, mm_plan *out);
 
+/*
+ * Scan schedule of the plan's products at one padded width (the number of
+ * right-hand sides rounded up to the column block: 1, 2, 4, multiples of 4
+ * below 32, multiples of 32): columns per wavefront `wb`, positions per lane
+ * run `e` (tiles of 64 / wb * e positions, 128 to 1024), and whether the
+ * tile-aggregate pre-pass stores every run's within-tile carry for the main
+ * launch (`runex`; d <= 2 below 32 columns).  Every product of the plan at
+ * that width uses it: matern_mvm, solvers and batches (a problem gives the
+ * same bits alone and batched whenever their schedules agree).  The
+ * schedules are an implementation choice of the divide-and-conquer sweeps
+ * (Section 2.2) and never change the exact result beyond rounding; the
+ * autotuner picks them by measurement.  Available: (wb, e) = (1, 4), (2, 8),
+ * (4, 16), (4, 32), (32, 128) for every kernel, and also (1, 8), (1, 16),
+ * (4, 8), (8, 16), (8, 32), (16, 32), (16, 64), (32, 64) for the product form
+ * with nu = 3/2 in d = 2 and nu = 5/2 in d = 3; e = 0 selects the default run
+ * length of the block.  MM_ERR_ARG for other values, a width that wb does not
+ * divide, or while solvers or batches of the plan are alive.
+ * mm_plan_set_kernel clears the plan's schedules.  Host only.
+ */
+mm_status mm_plan_set_schedule(mm_plan plan, int32_t width, int32_t wb, int32_t e, int32_t runex);
+
+/* The schedule in effect at a width (set, or the default of that width). */
+mm_status mm_plan_get_schedule(mm_plan plan, int32_t width, int32_t *wb, int32_t *e, int32_t *runex);
+
 /* Replace the kernel (nu, form, lengthscale, outputscale) of a plan; the
  * stored sorting outputs are kept.  Later products on `stream` use the new
  * kernel; the lengthscale factors are evaluated on chip by every product, so
@@ -160,6 +184,7 @@ mm_status mm_plan_destroy(mm_plan plan);
  */
 mm_status matern_mvm(mm_plan plan, const double *v, int64_t ldv, double *y, int64_t ldy,
                      int32_t nrhs, double diag_shift, void *stream);
+
 
 /*
  * Exact product with the lengthscale derivative of the kernel matrix (the

@@ -75,6 +75,9 @@ _SIGS = {
                                                   ctypes.POINTER(_MMKernel)]),
     "mm_plan_create": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
                                       ctypes.POINTER(_MMKernel), _P, ctypes.POINTER(_P)]),
+    "mm_plan_set_schedule": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "mm_plan_get_schedule": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "mm_plan_set_kernel": (ctypes.c_int, [_P, ctypes.POINTER(_MMKernel), _P]),
     "mm_plan_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(_MMKernel)]),
@@ -271,6 +274,17 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def set_schedule(self, width: int, wb: int, e: int = 0, runex: bool = True):
+        """Scan schedule of this plan's products at padded width `width`
+        (mm_plan_set_schedule): wb columns per wave, runs of e positions."""
+        _check(lib().mm_plan_set_schedule(self._h, int(width), int(wb), int(e), 1 if runex else 0))
+
+    def schedule(self, width: int):
+        """(wb, e, runex) in effect at padded width `width`."""
+        wb, e, rx = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().mm_plan_get_schedule(self._h, int(width), ctypes.byref(wb), ctypes.byref(e), ctypes.byref(rx)))
+        return wb.value, e.value, bool(rx.value)
 
     def set_kernel(self, kernel: Kernel):
         k = kernel.c()

@@ -114,3 +114,96 @@ def tune(batch, key: str, step: Callable[[], None], reps: int = 2,
     if use_cache:
         _store(key, (best_wg, best_g), timings)
     return best_wg, best_g
+
+
+# ---------------------------------------------------------------------------
+# Scan schedules of a plan's products (mm_plan_set_schedule): the column block
+# of a wavefront, the run length of a lane (hence the tile length) and whether
+# the tile-aggregate pre-pass stores the runs' within-tile carries.  They change
+# the launch shapes and the order in which tiles join, never the exact result
+# (only its rounding), and they are chosen per (d, nu, form, size bucket,
+# width) by timing the product at that width.
+# ---------------------------------------------------------------------------
+BASE_SCHEDULES = ((1, 4), (2, 8), (4, 16), (4, 32), (32, 128))
+TUNED_SCHEDULES = ((1, 8), (1, 16), (4, 8), (8, 16), (8, 32), (16, 32), (16, 64), (32, 64))
+
+
+def rhs_block(nrhs: int) -> int:
+    """The library's default column block for nrhs right-hand sides."""
+    return 32 if nrhs >= 32 else (4 if nrhs >= 4 else (2 if nrhs >= 2 else 1))
+
+
+def product_width(nrhs: int) -> int:
+    """Padded width of a product with nrhs right-hand sides (matern_mvm's rule)."""
+    r = rhs_block(nrhs)
+    return (nrhs + r - 1) // r * r
+
+
+def schedule_candidates(d: int, two_nu: int, form: str, width: int) -> List[Tuple[int, int, int]]:
+    """(wb, e, runex) schedules compiled for the kernel class at this width."""
+    tuned = form == "product" and ((d == 2 and two_nu == 3) or (d == 3 and two_nu == 5))
+    pairs = list(BASE_SCHEDULES) + (list(TUNED_SCHEDULES) if tuned else [])
+    out = []
+    for wb, e in pairs:
+        if width % wb:
+            continue
+        stores = d <= 2 and width < 32 and wb >= 2 and e <= 32   # the pre-pass can store run carries
+        for rx in ((1, 0) if stores else (1,)):
+            out.append((wb, e, rx))
+    return out
+
+
+def schedule_key(n: int, d: int, two_nu: int, form: str, width: int) -> str:
+    return "sched|d%d.nu%d.%s|N%d|w%d" % (d, two_nu, form, int(round(math.log2(max(n, 1)))), width)
+
+
+def _median_ms(step: Callable[[], None], reps: int) -> float:
+    import torch
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune_schedule(plan, nrhs: int, reps: int = 5, use_cache: bool = True, vectors=None):
+    """Pick the scan schedule of ``plan``'s products at nrhs right-hand sides
+    (its padded width) by timing matern_mvm under each compiled candidate,
+    set it on the plan, and return (wb, e, runex).  Cached by
+    (d, nu, form, log2 n, width)."""
+    import torch
+    import numpy as np
+    width = product_width(nrhs)
+    k = plan.kernel
+    key = schedule_key(plan.n, plan.d, k.two_nu, k.form, width)
+    if use_cache:
+        hit = _load().get(key)
+        if hit:
+            sc = tuple(int(v) for v in hit["schedule"])
+            plan.set_schedule(width, *sc)
+            return sc
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if vectors is None:
+        vc = torch.as_tensor(np.random.default_rng(0).standard_normal((nrhs, plan.n)), device=dev)
+    else:
+        vc = vectors
+    yc = torch.empty_like(vc)
+    timings: Dict[str, float] = {}
+    best, best_t = None, float("inf")
+    for wb, e, rx in schedule_candidates(plan.d, k.two_nu, k.form, width):
+        plan.set_schedule(width, wb, e, bool(rx))
+        plan.mvm_raw(vc, yc, nrhs)          # first touch of the workspaces outside the timing
+        t = _median_ms(lambda: plan.mvm_raw(vc, yc, nrhs), reps)
+        timings["wb%d/e%d/rx%d" % (wb, e, rx)] = t
+        if t < best_t:
+            best, best_t = (wb, e, rx), t
+    plan.set_schedule(width, *best)
+    if use_cache:
+        _store(key, best, timings)
+    return best

@@ -320,7 +320,54 @@ mm_status mm_plan_set_kernel(mm_plan plan, const mm_kernel *kernel, void *stream
         return MM_ERR_ARG;
     }
     plan->kernel = *kernel;
+    plan->sched.clear();  // schedules belong to a kernel class
     plan->last_stream = static_cast<hipStream_t>(stream);
+    return MM_OK;
+}
+
+mm_status mm_plan_set_schedule(mm_plan plan, int32_t width, int32_t wb, int32_t e, int32_t runex) {
+    clear_error();
+    if (!plan) {
+        set_error("plan is NULL");
+        return MM_ERR_ARG;
+    }
+    if (plan->npins > 0) {
+        set_error("the plan is in use by %d solver(s) or batch(es); release them before changing its schedule",
+                  plan->npins);
+        return MM_ERR_ARG;
+    }
+    if (width < 1 || width > 256) {
+        set_error("width must be in [1, 256] (got %d)", width);
+        return MM_ERR_ARG;
+    }
+    const Sched sc{wb, e, runex ? 1 : 0};
+    const KParams kp = kparams(plan->kernel, plan->d);
+    if (!sched_available(plan->d, kp, sc, width)) {
+        set_error("no compiled schedule with %d-column blocks and runs of %d for this kernel at width %d", wb, e,
+                  width);
+        return MM_ERR_ARG;
+    }
+    for (auto &en : plan->sched)
+        if (en.first == width) {
+            en.second = sc;
+            return MM_OK;
+        }
+    plan->sched.push_back({width, sc});
+    return MM_OK;
+}
+
+mm_status mm_plan_get_schedule(mm_plan plan, int32_t width, int32_t *wb, int32_t *e, int32_t *runex) {
+    clear_error();
+    if (!plan || width < 1 || width > 256) {
+        set_error("plan is NULL or width outside [1, 256]");
+        return MM_ERR_ARG;
+    }
+    Sched sc = plan_sched(plan, width, rhs_block(plan->kernel, plan->d, width));
+    if (sc.e == 0)  // the default run length of the block (tiles of 256; 512 for 4-column blocks above 8 columns in d = 2)
+        sc.e = sc.wb == 32 ? 128 : (sc.wb == 4 ? (plan->d == 2 && width > 8 ? 32 : 16) : (sc.wb == 2 ? 8 : 4));
+    if (wb) *wb = sc.wb;
+    if (e) *e = sc.e;
+    if (runex) *runex = sc.runex;
     return MM_OK;
 }
 

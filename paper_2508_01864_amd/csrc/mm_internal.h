@@ -82,6 +82,17 @@ struct KParams {
 
 KParams kparams(const mm_kernel &k, int d);
 
+// Scan schedule of the products at one padded width: wb columns per wave (the
+// column block), runs of e positions per lane (tiles of 64 / wb * e
+// positions), and whether the tile-aggregate pre-pass stores the runs'
+// within-tile carries for the main launch (d <= 2, below 32 columns).  e = 0
+// selects the default run length of the block.
+struct Sched {
+    int wb = 1;
+    int e = 0;
+    int runex = 1;
+};
+
 }  // namespace mm
 
 // ---------------------------------------------------------------------------
@@ -109,6 +120,9 @@ struct mm_plan_s {
     mm::DevBuf seg_tab[NTS];        // per tile size: (pass, first tile, end tile) of those segments
     std::vector<int> seg_off[NTS];  //   offset of each cross-tile pass's first segment
     std::vector<int4> seg_host[NTS];  // host copy of seg_tab
+
+    // scan schedules chosen for particular widths (mm_plan_set_schedule; others: the default)
+    std::vector<std::pair<int, mm::Sched>> sched;
 
     // product work buffers (grow on demand)
     mm::DevBuf vin;               // n x W point-major canonical input
@@ -171,6 +185,7 @@ struct SweepBatch {
     struct Cls {
         int key = 0, d = 1;
         KParams kp;
+        Sched sc;                  // the members' common schedule
         std::vector<int> members;
         DevBuf descs, items_agg, items_carry, items_main;
         int n_agg = 0, n_carry = 0, n_main = 0;
@@ -200,6 +215,10 @@ mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int R, hi
 // yacc <- the off-diagonal sums of l dK/dl applied to vin (unscaled; canonical order)
 mm_status sweep_all_dl(mm_plan p, const double *vin, double *yacc, int W, int R, hipStream_t s);
 int rhs_block(const mm_kernel &k, int d, int nrhs);
+// the schedule of plan p's products at width W (default column block WB)
+Sched plan_sched(mm_plan p, int W, int WB);
+// whether schedule sc is compiled for the kernel class (d, kp) at width W
+bool sched_available(int d, const KParams &kp, const Sched &sc, int W);
 size_t sweep_agg_bytes(int64_t n, int d, int W, const mm_kernel &k, bool der = false);
 int agg_per_rhs(int d, const mm_kernel &k, bool der);
 size_t sweep_part_bytes(int64_t n, int npass, int W);

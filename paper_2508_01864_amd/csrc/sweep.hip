@@ -139,7 +139,16 @@ mm_status upload_pass_tables(mm_plan p) {
     return MM_OK;
 }
 
-// WB: columns per wave (1, 2, 4 or 32); W a multiple of WB.
+Sched plan_sched(mm_plan p, int W, int WB) {
+    for (const auto &e : p->sched)
+        if (e.first == W) return e.second;
+    return Sched{WB, 0, 1};
+}
+
+bool sched_available(int d, const KParams &kp, const Sched &sc, int W) { return sched_compiled(d, kp, sc, W); }
+
+// WB: the default column block (1, 2, 4 or 32); W a multiple of WB.  The plan's
+// schedule for W, if one was set, replaces the default.
 mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int WB, hipStream_t s, int *tail,
                     const SweepWs *ws) {
     const KParams kp = kparams(p->kernel, p->d);
@@ -147,9 +156,10 @@ mm_status sweep_all(mm_plan p, const double *vin, double *yacc, int W, int WB, h
         set_error("internal: width %d does not match the block %d", W, WB);
         return MM_ERR_ARG;
     }
-    return with_cfg(p->d, kp, WB, W, [&](auto t) {
+    const Sched sc = plan_sched(p, W, WB);
+    return with_cfg(p->d, kp, sc, W, [&](auto t) {
         using C = typename decltype(t)::type;
-        return run_passes<C>(p, vin, yacc, W, s, false, tail, ws);
+        return run_passes<C>(p, vin, yacc, W, s, false, tail, ws, sc.runex);
     });
 }
 
@@ -198,7 +208,9 @@ mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB,
     for (size_t k = 0; k < probs.size(); ++k) {
         mm_plan p = probs[k].p;
         const KParams kp = kparams(p->kernel, p->d);
-        const int key = (p->d * 4 + kp.P) * 2 + (kp.prod ? 1 : 0);
+        const Sched sc = plan_sched(p, W, WB);
+        // one class per kernel configuration and schedule
+        const int key = ((((p->d * 4 + kp.P) * 2 + (kp.prod ? 1 : 0)) * 64 + sc.wb) * 256 + sc.e) * 2 + sc.runex;
         size_t c = 0;
         while (c < keys.size() && keys[c] != key) ++c;
         if (c == keys.size()) {
@@ -207,6 +219,7 @@ mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB,
             out.classes.back().key = key;
             out.classes.back().d = p->d;
             out.classes.back().kp = kp;
+            out.classes.back().sc = sc;
         }
         out.classes[c].members.push_back((int)k);
         size_t ab = 0, pb = 0;
@@ -228,7 +241,7 @@ mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB,
     MM_TRY(upload(out.acc_items, ai));
     out.n_acc = (int)ai.size();
     for (auto &cl : out.classes) {
-        MM_TRY(with_cfg(cl.d, cl.kp, WB, W, [&](auto t) {
+        MM_TRY(with_cfg(cl.d, cl.kp, cl.sc, W, [&](auto t) {
             using C = typename decltype(t)::type;
             const int ti = tile_index(C::T);
             std::vector<SweepArgs> descs;
@@ -237,7 +250,7 @@ mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB,
                 const BatchEntry &e = probs[cl.members[m]];
                 mm_plan p = e.p;
                 const int npass = (int)p->passes.size();
-                SweepArgs A = make_args<C>(p, e.vin, e.agg, e.part, W, npass > 0 ? npass : 1);
+                SweepArgs A = make_args<C>(p, e.vin, e.agg, e.part, W, npass > 0 ? npass : 1, cl.sc.runex);
                 descs.push_back(A);
                 if (npass == 0) continue;
                 const int ncb = W / C::WCOL;
@@ -271,7 +284,7 @@ mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB,
 
 mm_status sweep_batch_run(SweepBatch &b, hipStream_t s) {
     for (auto &cl : b.classes) {
-        MM_TRY(with_cfg(cl.d, cl.kp, b.WB, b.W, [&](auto t) {
+        MM_TRY(with_cfg(cl.d, cl.kp, cl.sc, b.W, [&](auto t) {
             using C = typename decltype(t)::type;
             const SweepArgs *descs = static_cast<const SweepArgs *>(cl.descs.ptr);
             if (cl.n_agg > 0)

@@ -241,11 +241,12 @@ struct Cfg {
     // keep the targets' sums in registers over the sweep (runs of 4, small states)
     static constexpr bool REGOUT = E <= 4 && E * NSLOT <= 64;
     // otherwise the targets' sums of the two directions (and sub-sweeps)
-    // gather per lane and reach the pass's slab once, for up to 4 columns a
-    // wave: in registers for d <= 2 (the run's block loop is unrolled so that
-    // every index is constant), in LDS for d = 3 (larger states)
-    static constexpr bool OUTREG = !REGOUT && WCOL <= 4 && D <= 2;
-    static constexpr bool LDSOUT = !REGOUT && !OUTREG && WCOL <= 4;
+    // gather per lane and reach the pass's slab once: in registers for d <= 2
+    // and runs of at most 32 (a ring, see run_direction), in LDS for d = 3
+    // (larger states) while the tile's sums take at most 16 KB; beyond both,
+    // each direction updates the slab in place
+    static constexpr bool OUTREG = !REGOUT && D <= 2 && E <= 32;
+    static constexpr bool LDSOUT = !REGOUT && !OUTREG && T * WCOL <= 2048;
     static constexpr bool SUMREG = REGOUT || OUTREG;   // outv holds the run's sums
     // the tile-aggregate pre-pass stores every run's within-tile carry of the
     // cross-tile passes, so the main launch skips their aggregate pass and lane scan
@@ -1314,7 +1315,7 @@ mm_status profile_begin(mm_plan p, int passes_covered, hipStream_t s, hipEvent_t
 // tail[0] = that group's passes, tail[1] = 1 when yacc holds no earlier group.
 template <class C>
 mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStream_t s, bool add = false,
-                     int *tail = nullptr, const SweepWs *ws = nullptr) {
+                     int *tail = nullptr, const SweepWs *ws = nullptr, int runex = 1) {
     double *const ws_agg = ws ? ws->agg : static_cast<double *>(p->agg.ptr);
     double *const ws_part = ws ? ws->part : static_cast<double *>(p->part.ptr);
     static_assert(C::T == 128 || C::T == 256 || C::T == 512 || C::T == 1024, "tile sizes with a cross-tile pass list");
@@ -1353,7 +1354,7 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
     A.car = A.agg + aggslab;
     A.anc = A.car + aggslab;
     A.dec = A.anc + (size_t)2 * gmax * ntile;
-    A.runex = (p->d <= 2 && W < 32) ? A.dec + (size_t)2 * gmax * ntile : nullptr;  // see agg_bytes_for
+    A.runex = (p->d <= 2 && W < 32 && runex) ? A.dec + (size_t)2 * gmax * ntile : nullptr;  // see agg_bytes_for
     A.xtpos = static_cast<const int32_t *>(p->pass_xtpos[ti].ptr);
     for (int g0 = 0; g0 < npass; g0 += gmax) {
         const int G = npass - g0 < gmax ? npass - g0 : gmax;
@@ -1394,50 +1395,88 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
     return MM_OK;
 }
 
-// Lane layout by the padded width W (a multiple of the block WB returned by
-// rhs_block): WCOL = WB columns per wave and runs of E = 256*WCOL/64
-// positions (tiles of 256 positions); in d = 2 with more than 8 columns the
-// 4-column blocks take runs of 32 (tiles of 512: measured 5% faster at 16
-// columns, slower at 5 to 8 and in d = 1 and 3).  with_cfg calls
-// f(Tag<Cfg<...>>) for the configuration of (d, nu, form, WB, W).
+// Lane layout by the schedule: WCOL = sc.wb columns per wave and runs of E
+// positions.  The default run length (sc.e = 0) gives tiles of 256 positions
+// (E = 256 * WCOL / 64); in d = 2 with more than 8 columns the 4-column blocks
+// take runs of 32 (tiles of 512: measured 5% faster at 16 columns, slower at 5
+// to 8 and in d = 1 and 3).  The kernels of the headline configurations (the
+// product form with nu = 3/2 in d = 2 and nu = 5/2 in d = 3) also come with
+// the schedules the autotuner searches: blocks of 1 to 32 columns and tiles of
+// 128 to 1024 positions.  with_cfg calls f(Tag<Cfg<...>>) for the
+// configuration of (d, nu, form, schedule, W).
 template <class C>
 struct Tag {
     using type = C;
 };
 
+template <int D, int P, bool PROD>
+constexpr bool TUNED = PROD && ((D == 2 && P == 2) || (D == 3 && P == 3));
+
+// The extra (column block, run length) pairs of the tuned configurations.
+constexpr int NTUNED = 8;
+constexpr int TUNED_WB[NTUNED] = {1, 1, 4, 8, 8, 16, 16, 32};
+constexpr int TUNED_E[NTUNED] = {8, 16, 8, 16, 32, 32, 64, 64};
+
 template <int D, int P, bool PROD, int GJ = -1, class F>
-mm_status with_wb(int WB, int W, F &&f) {
+mm_status with_wb(const Sched &sc, int W, F &&f) {
+    if constexpr (GJ == -1 && TUNED<D, P, PROD>) {
+        if (sc.wb == 1 && sc.e == 8) return f(Tag<Cfg<D, P, PROD, 1, 8, GJ>>{});
+        if (sc.wb == 1 && sc.e == 16) return f(Tag<Cfg<D, P, PROD, 1, 16, GJ>>{});
+        if (sc.wb == 4 && sc.e == 8) return f(Tag<Cfg<D, P, PROD, 4, 8, GJ>>{});
+        if (sc.wb == 8 && sc.e == 16) return f(Tag<Cfg<D, P, PROD, 8, 16, GJ>>{});
+        if (sc.wb == 8 && sc.e == 32) return f(Tag<Cfg<D, P, PROD, 8, 32, GJ>>{});
+        if (sc.wb == 16 && sc.e == 32) return f(Tag<Cfg<D, P, PROD, 16, 32, GJ>>{});
+        if (sc.wb == 16 && sc.e == 64) return f(Tag<Cfg<D, P, PROD, 16, 64, GJ>>{});
+        if (sc.wb == 32 && sc.e == 64) return f(Tag<Cfg<D, P, PROD, 32, 64, GJ>>{});
+    }
+    const int WB = sc.wb;
     if (WB == 32) return f(Tag<Cfg<D, P, PROD, 32, 128, GJ>>{});
+    if (WB == 4 && sc.e == 32) return f(Tag<Cfg<D, P, PROD, 4, 32, GJ>>{});
     if constexpr (D == 2)
-        if (WB == 4 && W > 8) return f(Tag<Cfg<D, P, PROD, 4, 32, GJ>>{});
+        if (WB == 4 && W > 8 && sc.e == 0) return f(Tag<Cfg<D, P, PROD, 4, 32, GJ>>{});
     if (WB == 4) return f(Tag<Cfg<D, P, PROD, 4, 16, GJ>>{});
     if (WB == 2) return f(Tag<Cfg<D, P, PROD, 2, 8, GJ>>{});
     return f(Tag<Cfg<D, P, PROD, 1, 4, GJ>>{});
 }
 
+// Whether (wb, e) names a compiled configuration of the kernel class at width W
+// (e = 0: the default run length of the block).
+inline bool sched_compiled(int d, const KParams &kp, const Sched &sc, int W) {
+    if (sc.wb < 1 || W % sc.wb != 0) return false;
+    if (sc.e == 0) return sc.wb == 1 || sc.wb == 2 || sc.wb == 4 || sc.wb == 32;
+    const bool base = (sc.wb == 1 && sc.e == 4) || (sc.wb == 2 && sc.e == 8) || (sc.wb == 4 && sc.e == 16) ||
+                      (sc.wb == 4 && sc.e == 32) || (sc.wb == 32 && sc.e == 128);
+    if (base) return true;
+    const bool tuned = kp.prod && ((d == 2 && kp.P == 2) || (d == 3 && kp.P == 3));
+    if (!tuned) return false;
+    for (int k = 0; k < NTUNED; ++k)
+        if (TUNED_WB[k] == sc.wb && TUNED_E[k] == sc.e) return true;
+    return false;
+}
+
 template <int D, class F>
-mm_status with_p(const KParams &kp, int WB, int W, F &&f) {
-    if (kp.P == 1) return with_wb<D, 1, true>(WB, W, f);
+mm_status with_p(const KParams &kp, const Sched &sc, int W, F &&f) {
+    if (kp.P == 1) return with_wb<D, 1, true>(sc, W, f);
     if constexpr (D == 1) {
-        if (kp.P == 2) return with_wb<D, 2, true>(WB, W, f);
-        return with_wb<D, 3, true>(WB, W, f);
+        if (kp.P == 2) return with_wb<D, 2, true>(sc, W, f);
+        return with_wb<D, 3, true>(sc, W, f);
     } else {
-        if (kp.P == 2) return kp.prod ? with_wb<D, 2, true>(WB, W, f) : with_wb<D, 2, false>(WB, W, f);
-        return kp.prod ? with_wb<D, 3, true>(WB, W, f) : with_wb<D, 3, false>(WB, W, f);
+        if (kp.P == 2) return kp.prod ? with_wb<D, 2, true>(sc, W, f) : with_wb<D, 2, false>(sc, W, f);
+        return kp.prod ? with_wb<D, 3, true>(sc, W, f) : with_wb<D, 3, false>(sc, W, f);
     }
 }
 
 template <class F>
-mm_status with_cfg(int d, const KParams &kp, int WB, int W, F &&f) {
-    if (d == 1) return with_p<1>(kp, WB, W, f);
-    if (d == 2) return with_p<2>(kp, WB, W, f);
-    return with_p<3>(kp, WB, W, f);
+mm_status with_cfg(int d, const KParams &kp, const Sched &sc, int W, F &&f) {
+    if (d == 1) return with_p<1>(kp, sc, W, f);
+    if (d == 2) return with_p<2>(kp, sc, W, f);
+    return with_p<3>(kp, sc, W, f);
 }
 
 // Arguments of a problem's single pass group (all passes) for configuration C,
 // with caller-owned aggregate and partial-slab workspaces.
 template <class C>
-SweepArgs make_args(mm_plan p, const double *vin, double *agg, double *part, int W, int gmax) {
+SweepArgs make_args(mm_plan p, const double *vin, double *agg, double *part, int W, int gmax, int runex = 1) {
     const KParams kp = kparams(p->kernel, p->d);
     const int ti = tile_index(C::T);
     const int64_t ntile = (p->n + C::T - 1) / C::T;
@@ -1456,7 +1495,7 @@ SweepArgs make_args(mm_plan p, const double *vin, double *agg, double *part, int
     A.car = A.agg + aggslab;
     A.anc = A.car + aggslab;
     A.dec = A.anc + (size_t)2 * gmax * ntile;
-    A.runex = (p->d <= 2 && W < 32) ? A.dec + (size_t)2 * gmax * ntile : nullptr;  // see agg_bytes_for
+    A.runex = (p->d <= 2 && W < 32 && runex) ? A.dec + (size_t)2 * gmax * ntile : nullptr;  // see agg_bytes_for
     A.xtpos = static_cast<const int32_t *>(p->pass_xtpos[ti].ptr);
     A.nslice = C::NSUB * C::NCLS * C::NTH * W;
     A.segs = static_cast<const int4 *>(p->seg_tab[ti].ptr);

@@ -18,7 +18,8 @@ namespace mm {
 namespace {
 
 template <int D, int P, bool PROD, class F>
-mm_status with_gj(int gj, int WB, int W, F &&f) {
+mm_status with_gj(int gj, int WBlk, int W, F &&f) {
+    const Sched WB{WBlk, 0, 1};  // the derivative sweeps run the default schedule of the block
     if constexpr (!PROD) {
         (void)gj;
         return with_wb<D, P, false, D - 1>(WB, W, f);

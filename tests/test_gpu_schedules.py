@@ -1,0 +1,105 @@
+"""Scan schedules (mm_plan_set_schedule): every compiled (column block, run
+length, stored run carries) schedule of a plan's products gives the oracle's
+product within the parity tolerance, at several widths, with tiles of 128 to
+1024 positions, segments wider than a tile and a ragged last tile; a batch and
+a solver follow the schedule of their plan (bitwise equal to the plan's own
+product / solve alone)."""
+import numpy as np
+import pytest
+
+import paper_2508_01864_amd as mm
+from paper_2508_01864_amd import autotune
+import workloads
+from gpu_util import MVM_TOL, SOLVE_TOL, mvm_errors, say, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(2, 3, 5001, 1), (2, 3, 5001, 4), (2, 3, 5001, 8), (2, 3, 5001, 32),
+         (3, 5, 2500, 1), (3, 5, 2500, 8), (3, 5, 2500, 32), (2, 5, 3000, 4)]
+
+
+@pytest.mark.parametrize("d,two_nu,n,nrhs", CASES)
+def test_every_schedule_matches_the_oracle(oracle_lib, d, two_nu, n, nrhs):
+    import torch
+    p = workloads.random_problem(1300 + 10 * d + n + nrhs, n, d, two_nu, "product", 0.1 if d == 2 else 0.2,
+                                 nrhs=max(nrhs, 2))
+    v = p.v[:, :nrhs]
+    yref, yabs = oracle_lib.mvm(p.x, v, two_nu, "product", p.ell, with_abs=True, shared_kernel=True)
+    plan = mm.Plan(to_gpu(p.x), mm.Kernel(two_nu, "product", p.ell))
+    width = autotune.product_width(nrhs)
+    vc = to_gpu(np.ascontiguousarray(v.T))
+    yc = torch.empty_like(vc)
+    for wb, e, rx in autotune.schedule_candidates(d, two_nu, "product", width):
+        plan.set_schedule(width, wb, e, bool(rx))
+        assert plan.schedule(width) == (wb, e, bool(rx))
+        plan.mvm_raw(vc, yc, nrhs)
+        comp, nrm = mvm_errors(to_np(yc).T, yref, yabs)
+        say("d=%d nu=%d/2 n=%d nrhs=%d schedule (%d, %d, %d): comp %.2e nrm %.2e" %
+            (d, two_nu, n, nrhs, wb, e, rx, comp, nrm))
+        assert comp <= MVM_TOL and nrm <= MVM_TOL, (wb, e, rx)
+    plan.close()
+
+
+def test_schedule_rules():
+    p = workloads.random_problem(1400, 300, 2, 1, "product", 0.2)
+    plan = mm.Plan(to_gpu(p.x), mm.Kernel(1, "product", 0.2))
+    assert plan.schedule(32) == (32, 128, True)
+    assert plan.schedule(8) == (4, 16, True)
+    with pytest.raises(mm.MaternError):
+        plan.set_schedule(32, 16, 32)          # compiled only for the tuned kernel classes
+    with pytest.raises(mm.MaternError):
+        plan.set_schedule(4, 8, 16)            # 8 does not divide 4
+    plan.set_schedule(4, 2, 8, False)
+    assert plan.schedule(4) == (2, 8, False)
+    plan.set_kernel(mm.Kernel(3, "product", 0.2))
+    assert plan.schedule(4) == (4, 16, True)   # cleared with the kernel
+    plan.close()
+
+
+def test_batch_and_solver_follow_the_plan_schedule(oracle_lib):
+    import torch
+    probs = [workloads.random_problem(1500 + k, n, 2, 3, "product", 0.1) for k, n in enumerate((2000, 4500, 3100))]
+    plans = [mm.Plan(to_gpu(q.x), mm.Kernel(3, "product", 0.1)) for q in probs]
+    plans[0].set_schedule(4, 4, 8)
+    plans[0].set_schedule(1, 1, 16)
+    plans[1].set_schedule(4, 2, 8, False)
+    plans[1].set_schedule(1, 1, 8)
+    # products: one column, batched against alone
+    vcs = [to_gpu(q.v).view(1, -1) for q in probs]
+    alone = []
+    for pl, vc in zip(plans, vcs):
+        y = torch.empty_like(vc)
+        pl.mvm_raw(vc, y, 1)
+        alone.append(to_np(y))
+    mb = mm.MvmBatch(plans, nrhs=1, use_graph=True)
+    ycs = [torch.empty_like(vc) for vc in vcs]
+    mb.run_raw(vcs, ycs)
+    mb.close()
+    for a, b in zip(alone, ycs):
+        assert np.array_equal(a, to_np(b))
+    # solves with fixed effects (width 4): alone against a batch, and the oracle
+    ys = [workloads.field_sin_cos(q.x) + 0.05 * q.v for q in probs]
+    ref = []
+    for pl, y in zip(plans, ys):
+        a, b, info = pl.cg_solve(to_gpu(y), 0.02, fixed_effects=True, rtol=1e-11)
+        ref.append((to_np(a), b))
+    from gpu_util import converged
+    solvers = [mm.Solver(pl, to_gpu(y), 0.02, fixed_effects=True, rtol=1e-11) for pl, y in zip(plans, ys)]
+    batch = mm.SolverBatch(solvers, use_graph=True)
+    passed = [False] * len(solvers)
+    for _ in range(2000):
+        batch.iterate(8)
+        if converged(solvers, batch.poll(), passed):
+            break
+    for k, (s, (a0, b0)) in enumerate(zip(solvers, ref)):
+        a, b, info = s.finish()
+        assert np.array_equal(to_np(a), a0) and np.array_equal(b, b0)
+        q = probs[k]
+        bref, aref = oracle_lib.gls(q.x, ys[k], 3, "product", 0.1, 1.0, 0.02)
+        err = float(np.linalg.norm(to_np(a) - aref) / np.linalg.norm(aref))
+        say("solve %d schedule %s: err %.2e" % (k, plans[k].schedule(4), err))
+        assert err <= SOLVE_TOL
+        s.close()
+    batch.close()
+    for pl in plans:
+        pl.close()
