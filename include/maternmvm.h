@@ -185,6 +185,24 @@ mm_status mm_plan_destroy(mm_plan plan);
 mm_status matern_mvm(mm_plan plan, const double *v, int64_t ldv, double *y, int64_t ldy,
                      int32_t nrhs, double diag_shift, void *stream);
 
+/*
+ * matern_mvm without device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, hosts that forbid
+ * allocation.  Same arguments, layouts, errors and results (bitwise) as
+ * matern_mvm; the plan must have been created beforehand.  Its work buffers
+ * (canonical input and sum, tile aggregates and carries, per-pass partial
+ * slabs) come from one fixed scratch array of MM_NOALLOC_SCRATCH_MIB MiB in
+ * device memory, which each device the library runs on holds until the
+ * process ends.  Sizes whose work buffers exceed it are refused with
+ * MM_ERR_ARG (the headline d = 2, n = 100,000 fits up to 4 right-hand sides;
+ * use matern_mvm beyond).  Every call on a device shares that device's array:
+ * calls that overlap on one device (concurrent streams or threads) race and
+ * must be serialised by the caller.  Nothing in the array needs to start at
+ * zero: every buffer is written before it is read.
+ */
+#define MM_NOALLOC_SCRATCH_MIB 256
+mm_status matern_mvm_noalloc(mm_plan plan, const double *v, int64_t ldv, double *y, int64_t ldy,
+                             int32_t nrhs, double diag_shift, void *stream);
 
 /*
  * Exact product with the lengthscale derivative of the kernel matrix (the

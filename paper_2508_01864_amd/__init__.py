@@ -84,6 +84,8 @@ _SIGS = {
     "mm_plan_destroy": (ctypes.c_int, [_P]),
     "matern_mvm": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int32,
                                   ctypes.c_double, _P]),
+    "matern_mvm_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_double, _P]),
     "matern_mvm_dlengthscale": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int32, _P]),
     "gp_lml": (ctypes.c_int, [_P, _P, ctypes.c_double, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                               ctypes.c_double, ctypes.POINTER(_MMLmlInfo), _P, _P]),
@@ -301,6 +303,14 @@ class Plan:
                                 ctypes.c_void_p(yc.data_ptr()), self.n, nrhs, float(shift),
                                 _stream_ptr(self._stream)))
         return yc.view(-1) if v.dim() == 1 else yc.t()
+
+    def mvm_noalloc_raw(self, vc, yc, nrhs: int, shift: float = 0.0):
+        """matern_mvm_noalloc on preallocated column-major buffers (nrhs, n): the
+        product without any device allocation (work buffers in the library's
+        fixed scratch array)."""
+        _check(lib().matern_mvm_noalloc(self._h, ctypes.c_void_p(vc.data_ptr()), self.n,
+                                        ctypes.c_void_p(yc.data_ptr()), self.n, int(nrhs), float(shift),
+                                        _stream_ptr(self._stream)))
 
     def mvm_dlengthscale(self, v, out=None):
         """y = (dK/d lengthscale) v for v of shape (n,) or (n, nrhs)."""

@@ -19,7 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmaternmvm.so")
-SOURCES = ["plan.hip", "sweep.hip", "sweep_dl.hip", "api.hip", "solver.hip", "batch.hip", "precond.hip"]
+SOURCES = ["plan.hip", "sweep.hip", "sweep_dl.hip", "api.hip", "solver.hip", "batch.hip", "precond.hip",
+           "noalloc.hip"]
 ARCH = "gfx950"
 
 
