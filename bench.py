@@ -169,8 +169,10 @@ def median_ms(fn, reps: int) -> float:
 
 
 def bench_mvm(mm, x, dev, reps: int, copy_gbs: float):
-    """Median matern_mvm at 1, 8 and 32 columns, product and L1 forms."""
+    """Median matern_mvm at 1, 8 and 32 columns, product and L1 forms, each on the
+    schedule the autotuner picks for its width."""
     import torch
+    from paper_2508_01864_amd import autotune
     L = mm.levels(N)
     out = {}
     for form in ("product", "l1"):
@@ -179,6 +181,7 @@ def bench_mvm(mm, x, dev, reps: int, copy_gbs: float):
         for nrhs in (1, 8, 32):
             vv = torch.as_tensor(np.random.default_rng(7 + nrhs).standard_normal((nrhs, N)), device=dev)
             yy = torch.empty_like(vv)
+            sched = autotune.tune_schedule(plan, nrhs, vectors=vv)
             for _ in range(3):
                 plan.mvm_raw(vv, yy, nrhs)
             torch.cuda.synchronize()
@@ -192,7 +195,7 @@ def bench_mvm(mm, x, dev, reps: int, copy_gbs: float):
             sweep_ms = sms / max(scnt, 1)
             ba = b_alg(N, D, nrhs, L)
             rows[str(nrhs)] = {
-                "median_ms": round(ms, 4), "points_per_s": N * nrhs / (ms * 1e-3),
+                "median_ms": round(ms, 4), "points_per_s": N * nrhs / (ms * 1e-3), "schedule": list(sched),
                 "b_alg_bytes": ba, "gbs": ba / (ms * 1e-3) / 1e9,
                 "frac_hbm_peak": ba / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 "frac_copy_peak": ba / (ms * 1e-3) / 1e9 / copy_gbs,
@@ -222,11 +225,16 @@ def bench_solve(mm, p, dev, reps: int, maxit: int, check_oracle: bool):
     y = torch.as_tensor(p.y, device=dev)
     z = torch.as_tensor(np.random.default_rng(20021).uniform(0.0, 1.0, size=(NPREDICT, D)), device=dev)
     kern = mm.Kernel(TWO_NU, "product", ELL, 1.0)
+    from paper_2508_01864_amd import autotune
+    tp = mm.Plan(x, kern)
+    sched = autotune.tune_schedule(tp, 4)       # the solver's width (y, 1, x1, x2); cached for the plans below
+    tp.close()
     best = None
     for r in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         plan = mm.Plan(x, kern)
+        autotune.tune_schedule(plan, 4)          # a cache hit: sets the tuned schedule
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         alpha, beta, info = plan.cg_solve(y, SIGMA2, fixed_effects=True, rtol=RTOL, maxit=maxit,
@@ -253,6 +261,7 @@ def bench_solve(mm, p, dev, reps: int, maxit: int, check_oracle: bool):
     best["workload"] = ("d=2 N=%d nu=3/2 product ell=0.1 sigma2=0.01: plan build, CG + GLS (fixed effects "
                         "1, x1, x2) to 1e-8, predict %d points" % (N, NPREDICT))
     best["points_per_s"] = N * (1 + 4 * best["iters"]) / best["total_s"]
+    best["schedule_width4"] = list(sched)
     return best
 
 
@@ -341,6 +350,7 @@ def bench_config3(dev, steps, rank, maxit):
     preconditioned with the rank-`rank` pivoted Cholesky."""
     import torch
     import paper_2508_01864_amd as mm
+    from paper_2508_01864_amd import autotune
     import workloads
     p = workloads.config3()
     n = p.n
@@ -355,11 +365,12 @@ def bench_config3(dev, steps, rank, maxit):
         tb = time.perf_counter() - t0
         Zc = Z.t().contiguous()
         Yc = torch.empty_like(Zc)
+        sched = autotune.tune_schedule(plan, 32, reps=1, vectors=Zc)
         plan.mvm_raw(Zc, Yc, 32)
         ms = median_ms(lambda: plan.mvm_raw(Zc, Yc, 32), 3)
         Lp = mm.passes(n, 3)
         ba = float(n) * (8.0 * 3 + 16.0 * 32 + Lp * (4.0 + 16.0 * 32))
-        out[form] = {"plan_build_s": tb, "mvm32_ms": ms, "points_per_s": n * 32 / (ms * 1e-3),
+        out[form] = {"plan_build_s": tb, "mvm32_ms": ms, "points_per_s": n * 32 / (ms * 1e-3), "schedule": list(sched),
                      "b_alg_bytes": ba, "frac_hbm_peak": ba / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         log("config 3 %s: 32-column product %.1f ms" % (form, ms))
         if form == "product":
@@ -372,20 +383,23 @@ def bench_config3(dev, steps, rank, maxit):
                              "seconds": time.perf_counter() - t0}
             log("config 3 log det ~ %.6e (%d steps)" % (est, int(msteps.max())))
             y = torch.as_tensor(p.y, device=dev)
+            s1 = autotune.tune_schedule(plan, 1, reps=3)       # the single column's schedule
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            pc = mm.Precond(plan, max_rank=rank)
+            pc = mm.Precond(plan, max_rank=rank) if rank > 0 else None
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             alpha, _, info = plan.cg_solve(y, 0.01, rtol=1e-8, maxit=maxit, precond=pc, raise_on_error=False)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
-            out["pcg_solve"] = {"rank": rank, "precond_s": t1 - t0, "solve_s": t2 - t1, "iters": info["iters"],
+            out["pcg_solve"] = {"rank": rank, "schedule": list(s1), "precond_s": t1 - t0, "solve_s": t2 - t1,
+                                "iters": info["iters"],
                                 "maxit": maxit, "status": info["status"], "relres": info["relres_max"],
                                 "true_relres": info["true_relres"],
                                 "per_iteration_ms": (t2 - t1) / max(info["iters"], 1) * 1e3}
             log("config 3 PCG: %d iterations, %.2f s" % (info["iters"], t2 - t1))
-            pc.close()
+            if pc is not None:
+                pc.close()
         plan.close()
     return out
 
@@ -590,10 +604,14 @@ def main():
     plan_build_s = float(np.median(builds))
     log("plan build %.4f s" % plan_build_s)
 
-    # the headline: one product with R columns per step
+    # the headline: one product with R columns per step, on the schedule the
+    # autotuner picks for this width (tuning runs before the timed region)
+    from paper_2508_01864_amd import autotune
     plan = mm.Plan(x, kern)
     vv = torch.as_tensor(np.random.default_rng(7 + R).standard_normal((R, N)), device=dev)
     yy = torch.empty_like(vv)
+    head_sched = autotune.tune_schedule(plan, R, vectors=vv)
+    log("headline schedule (columns per wave, run length, stored run carries): %s" % (head_sched,))
     for _ in range(args.warmup):
         plan.mvm_raw(vv, yy, R)
     torch.cuda.synchronize()
@@ -671,7 +689,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "matern_mvm y = K v, d=2 N=100000 nu=3/2 product form ell=0.1, "
                                "x ~ U[0,1]^2, %d right-hand sides, plan prebuilt" % R,
-                   "n": N, "d": D, "two_nu": TWO_NU, "form": "product", "lengthscale": ELL, "nrhs": R},
+                   "n": N, "d": D, "two_nu": TWO_NU, "form": "product", "lengthscale": ELL, "nrhs": R,
+                   "schedule": {"columns_per_wave": head_sched[0], "run_length": head_sched[1],
+                                "stored_run_carries": bool(head_sched[2]), "chosen_by": "autotune.tune_schedule"}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(),
                      "algorithmic_bytes_per_launch": bytes_launch,

@@ -446,12 +446,38 @@ mm_status mm_solver_batch_destroy(mm_solver_batch batch);
  *   logdet  host, the estimate
  *   quad    host, nprobes per-probe terms ||z_i||^2 e_1^T log(T_i) e_1 (may be NULL)
  *   lanczos_steps host, nprobes sizes of the T_i (may be NULL)
- * No preconditioner (the preconditioned estimator needs probes drawn from the
- * preconditioner's distribution).  Synchronises.
+ * No preconditioner (gp_logdet_pc draws its probes from the preconditioner's
+ * distribution).  Synchronises.
  */
 mm_status gp_logdet(mm_plan plan, double sigma2, const double *Z, int64_t ldz, int32_t nprobes,
                     int32_t steps, double rtol, double *logdet, double *quad, int32_t *lanczos_steps,
                     void *stream);
+
+/*
+ * Preconditioned stochastic log-determinant (Appendix A, the preconditioned
+ * log-determinant with the pivoted Cholesky preconditioner P = L L^T + sigma2 I):
+ *     log det A = log det P + log det(P^{-1/2} A P^{-1/2}),
+ *     log det P = n log sigma2 + log det(I_k + L^T L / sigma2)   (Sylvester),
+ * the second term by Lanczos quadrature from preconditioned CG (Algorithm 2
+ * with s_P = P^{-1}): probes z_i = L g1_i + sqrt(sigma2) g2_i are N(0, P)
+ * draws, so P^{-1/2} z_i ~ N(0, I) and each (z_i^T P^{-1} z_i) e_1^T log(T_i) e_1
+ * is an unbiased term (T_i the Lanczos matrix of P^{-1/2} A P^{-1/2} from the
+ * PCG coefficients).  The caller draws the standard normal numbers:
+ *   pc      preconditioner of this plan (mm_precond_create), rank k = its rank
+ *   G1      device, k x nprobes column-major, leading dimension ldg1 >= k
+ *           (may be NULL when k = 0)
+ *   G2      device, n x nprobes column-major (caller order), ldg2 >= n
+ *   nprobes 1..64 (solved in blocks of 8); steps, rtol as gp_logdet
+ *   logdet  host, the estimate (log det P included)
+ *   quad    host, nprobes per-probe terms (without log det P; may be NULL)
+ *   lanczos_steps host, nprobes sizes of the T_i (may be NULL)
+ *   logdet_precond host, log det P (may be NULL)
+ * Synchronises.
+ */
+mm_status gp_logdet_pc(mm_plan plan, double sigma2, mm_precond pc, const double *G1, int64_t ldg1,
+                       const double *G2, int64_t ldg2, int32_t nprobes, int32_t steps, double rtol,
+                       double *logdet, double *quad, int32_t *lanczos_steps, double *logdet_precond,
+                       void *stream);
 
 /*
  * Log marginal likelihood and its gradient (eq. gp_log_likelihood and eq.

@@ -343,6 +343,70 @@ def cg_lanczos(A, b, steps: int, rtol: float = 0.0):
     return np.array(alphas), np.array(betas)
 
 
+def pcg_lanczos(A, b, Pinv, steps: int, rtol: float = 0.0):
+    """Preconditioned conjugate gradients on dense A with a null start
+    (Appendix A, Algorithm 2 with the preconditioner solve s_P = Pinv),
+    recording alpha_k = r_k^T z_k / p_k^T A p_k and
+    beta_k = r_{k+1}^T z_{k+1} / r_k^T z_k.  These define the Lanczos matrix of
+    P^{-1/2} A P^{-1/2} started from P^{-1/2} b.  Stops like cg_lanczos on the
+    unpreconditioned residual.  Returns (alphas, betas, b^T P^{-1} b)."""
+    A = np.asarray(A, dtype=np.float64)
+    r = np.asarray(b, dtype=np.float64).copy()
+    x = np.zeros_like(r)
+    z = Pinv(r)
+    p = z.copy()
+    rz = float(r @ z)
+    rz0 = rz
+    bnorm = float(np.sqrt(r @ r))
+    alphas, betas = [], []
+    for _ in range(steps):
+        Ap = A @ p
+        alpha = rz / float(p @ Ap)
+        alphas.append(alpha)
+        x += alpha * p
+        r -= alpha * Ap
+        if np.sqrt(float(r @ r)) <= rtol * bnorm:
+            break
+        z = Pinv(r)
+        rz_new = float(r @ z)
+        beta = rz_new / rz
+        betas.append(beta)
+        p = z + beta * p
+        rz = rz_new
+    return np.array(alphas), np.array(betas), rz0
+
+
+def logdet_lowrank_plus_noise(L, sigma2: float) -> float:
+    """log det(L L^T + sigma^2 I_n) = n log sigma^2 + log det(I_k + L^T L / sigma^2)
+    (Sylvester's determinant identity), the second term by this module's Cholesky."""
+    L = np.asarray(L, dtype=np.float64)
+    n, k = L.shape
+    M = np.eye(k) + (L.T @ L) / sigma2
+    return float(n * np.log(sigma2) + 2.0 * np.sum(np.log(np.diag(cholesky(M)))))
+
+
+def logdet_pc_estimate(A, L, sigma2: float, G1, G2, steps: int, rtol: float = 0.0):
+    """Preconditioned stochastic log-determinant (Appendix A, the preconditioned
+    variant of eq. approximationLogDet): probes z_i = L g1_i + sigma g2_i are
+    N(0, P) draws for P = L L^T + sigma^2 I; each gives the quadrature
+    (z_i^T P^{-1} z_i) e_1^T log(T_i) e_1 from PCG with s_P = P^{-1}, an unbiased
+    term of log det(P^{-1/2} A P^{-1/2}); the estimate adds log det P.
+    Returns (estimate, per-probe quadratures)."""
+    G1 = np.asarray(G1, dtype=np.float64)
+    G2 = np.asarray(G2, dtype=np.float64)
+    if G1.ndim == 1:
+        G1, G2 = G1[:, None], G2[:, None]
+    Z = np.asarray(L, dtype=np.float64) @ G1 + np.sqrt(sigma2) * G2
+    quads = []
+    for i in range(Z.shape[1]):
+        al, be, rz0 = pcg_lanczos(A, Z[:, i], lambda r: woodbury_apply(L, sigma2, r), steps, rtol)
+        # T is built from the iterations that continued (one per beta); a solve
+        # that ends in its first step leaves the 1 x 1 matrix [1 / alpha_0]
+        quads.append(logquad_from_cg(al, be, rz0) if len(be) else rz0 * float(np.log(1.0 / al[0])))
+    quads = np.array(quads)
+    return logdet_lowrank_plus_noise(L, sigma2) + float(np.mean(quads)), quads
+
+
 def lanczos_tridiagonal(alphas, betas):
     """The Lanczos tridiagonal matrix from CG coefficients (Algorithm 2):
     T[k,k] = 1/alpha_k + beta_{k-1}/alpha_{k-1} (beta_0/alpha_0 = 0) and

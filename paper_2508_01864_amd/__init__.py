@@ -137,6 +137,10 @@ _SIGS = {
     "mm_mvm_batch_run": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int64), ctypes.c_double, _P]),
     "mm_mvm_batch_destroy": (ctypes.c_int, [_P]),
+    "gp_logdet_pc": (ctypes.c_int, [_P, ctypes.c_double, _P, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_double), _P]),
     "mm_plan_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "mm_plan_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_int64),
@@ -449,6 +453,28 @@ class Plan:
         _check(lib().gp_logdet(self._h, float(sigma2), ctypes.c_void_p(Zc.data_ptr()), self.n, k, int(steps),
                                float(rtol), ctypes.byref(est), quad, steps_out, _stream_ptr(self._stream)))
         return est.value, np.array(quad[:]), np.array(steps_out[:])
+
+    def logdet_pc(self, sigma2: float, precond, G1, G2, steps: int = 200, rtol: float = 0.0):
+        """Preconditioned stochastic log det(K + sigma2 I) (gp_logdet_pc): probes
+        L g1 + sigma g2 from standard normal G1 (rank, l) and G2 (n, l).
+        Returns (estimate, per-probe terms, Lanczos sizes, log det P)."""
+        G2c = _colmajor(G2, self.n)
+        k = G2c.shape[0]
+        rank = precond.info()[0]
+        G1c = None
+        if rank > 0:
+            G1c = G1.t().contiguous() if G1.dim() == 2 else G1.contiguous().view(1, -1)
+            if G1c.shape != (k, rank):
+                raise ValueError("G1 must have shape (rank, nprobes) = (%d, %d)" % (rank, k))
+        est = ctypes.c_double()
+        ldp = ctypes.c_double()
+        quad = (ctypes.c_double * k)()
+        steps_out = (ctypes.c_int32 * k)()
+        _check(lib().gp_logdet_pc(self._h, float(sigma2), precond.handle,
+                                  ctypes.c_void_p(G1c.data_ptr()) if G1c is not None else None, max(rank, 1),
+                                  ctypes.c_void_p(G2c.data_ptr()), self.n, k, int(steps), float(rtol),
+                                  ctypes.byref(est), quad, steps_out, ctypes.byref(ldp), _stream_ptr(self._stream)))
+        return est.value, np.array(quad[:]), np.array(steps_out[:]), ldp.value
 
     def profile_enable(self, on: bool = True):
         _check(lib().mm_plan_profile_enable(self._h, 1 if on else 0))

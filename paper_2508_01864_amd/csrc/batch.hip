@@ -22,6 +22,7 @@ struct MvmIo {
 
 // Per-problem constants of the batch.
 struct MvmDesc {
+    const int32_t *perm;    // canonical index -> caller index
     const int32_t *iperm;   // caller index -> canonical index
     double *vin;
     const double *part;     // the G per-pass partial slabs (n x W each)
@@ -60,15 +61,29 @@ __global__ void scatter_batch_kernel(const MvmDesc *ds, const MvmIo *io, const i
         const int64_t len = d.n * d.W;
         const int64_t lo = (int64_t)it.y * CHUNK;
         const int64_t hi = lo + CHUNK < total ? lo + CHUNK : total;
-        for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-            const int64_t pt = e / d.W;
-            const int r = (int)(e - pt * d.W);
-            if (r >= d.nrhs) continue;
-            const int64_t c = (int64_t)d.iperm[pt] * d.W + r;
-            double acc = 0.0;
-            for (int g = 0; g < d.G; ++g) acc += d.part[(int64_t)g * len + c];
-            const double vv = d.vin[c];
-            q.y[(int64_t)r * q.ldy + pt] = fma(shift, vv, d.s2 * (vv + acc));
+        if (d.W >= 4) {
+            // caller order, whole canonical rows read (as matern_mvm's output step)
+            for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+                const int64_t pt = e / d.W;
+                const int r = (int)(e - pt * d.W);
+                if (r >= d.nrhs) continue;
+                const int64_t c = (int64_t)d.iperm[pt] * d.W + r;
+                double acc = 0.0;
+                for (int g = 0; g < d.G; ++g) acc += d.part[(int64_t)g * len + c];
+                const double vv = d.vin[c];
+                q.y[(int64_t)r * q.ldy + pt] = fma(shift, vv, d.s2 * (vv + acc));
+            }
+        } else {
+            // narrow rows: canonical order, sequential slab reads, writes at perm[c]
+            for (int64_t c = lo + threadIdx.x; c < hi; c += blockDim.x) {
+                const int64_t pt = c / d.W;
+                const int r = (int)(c - pt * d.W);
+                if (r >= d.nrhs) continue;
+                double acc = 0.0;
+                for (int g = 0; g < d.G; ++g) acc += d.part[(int64_t)g * len + c];
+                const double vv = d.vin[c];
+                q.y[(int64_t)r * q.ldy + d.perm[pt]] = fma(shift, vv, d.s2 * (vv + acc));
+            }
         }
     }
 }
@@ -167,7 +182,8 @@ mm_status mvm_batch_build(mm_mvm_batch b) {
         double *part = reinterpret_cast<double *>(base);
         base += (partb[k] + 255) & ~size_t(255);
         ent.push_back(BatchEntry{p, vin, nullptr, agg, part});  // no sum buffer: the output step sums the slabs
-        descs.push_back(MvmDesc{static_cast<const int32_t *>(p->iperm.ptr), vin, part, p->n, b->W, b->nrhs,
+        descs.push_back(MvmDesc{static_cast<const int32_t *>(p->perm.ptr), static_cast<const int32_t *>(p->iperm.ptr),
+                                vin, part, p->n, b->W, b->nrhs,
                                 (int)p->passes.size(), p->kernel.outputscale2});
         const int64_t nin = (p->n * b->W + CHUNK - 1) / CHUNK;
         for (int64_t c = 0; c < nin; ++c) ii.push_back(make_int2((int)k, (int)c));

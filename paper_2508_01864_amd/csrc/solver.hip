@@ -608,6 +608,28 @@ __global__ void gather_cols_kernel(const double *v, int64_t ldv, int nrhs, const
     }
 }
 
+// Preconditioned log-determinant probes z = L g1 + sigma g2 (N(0, L L^T +
+// sigma^2 I) draws from standard normal g1, g2), canonical rows, W columns
+// (the padding zero): L is the preconditioner's factor (canonical rows of kmax,
+// rank columns used), g1 rank x nb and g2 (caller rows) n x nb, column-major.
+__global__ void pc_probe_kernel(const double *Lpc, int kmax, int rank, const double *G1, int64_t ldg1,
+                                const double *G2, int64_t ldg2, int nb, double sigma, const int32_t *perm,
+                                int64_t n, double *B, int W) {
+    const int64_t total = n * W;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / W;
+        const int r = (int)(e - c * W);
+        double z = 0.0;
+        if (r < nb) {
+            const double *lr = Lpc + c * kmax;
+            const double *g = G1 + (int64_t)r * ldg1;
+            for (int j = 0; j < rank; ++j) z = fma(lr[j], g[j], z);
+            z = fma(sigma, G2[(int64_t)r * ldg2 + perm[c]], z);
+        }
+        B[e] = z;
+    }
+}
+
 // partial sums of H^T X for the (d+1) x W block, H = [1, x_1..x_d]
 __global__ void fe_gram_kernel(const double *X, const double *xc, int64_t n, int d, int W, double *part) {
     __shared__ double sm[BS];
@@ -1051,10 +1073,12 @@ bool lanczos_logquad(const std::vector<double> &alpha, const std::vector<double>
 // coefficients: c the column's scalars (NS), tl the coefficient log
 // [iteration][W][alpha, beta].  The iterations that continued past their
 // alpha define T (Algorithm 2).  False if T has no positive spectrum.
-bool column_logquad(const double *c, const std::vector<double> &tl, int W, int r, double *q, int *msteps) {
+bool column_logquad(const double *c, const std::vector<double> &tl, int W, int r, double *q, int *msteps,
+                    double norm2 = -1.0) {
     const int na = (int)c[6];                  // alphas recorded
     const int m = c[5] != 0.0 ? na : na - 1;   // iterations that continued
-    const double znorm2 = c[4] * c[4];
+    // ||z||^2 of the probe, or z^T P^{-1} z for the preconditioned estimator
+    const double znorm2 = norm2 >= 0.0 ? norm2 : c[4] * c[4];
     *q = 0.0;
     *msteps = m > 0 ? m : na;
     if (m >= 1) {
@@ -1224,6 +1248,8 @@ mm_status solver_new(mm_plan plan, int ncols, int fe, double sigma2, double rtol
         return MM_ERR_NOMEM;
     }
     b->members.push_back(sv);
+    // solitary iterations are enqueued directly: replaying captured chunks of 8
+    // iterations measured 4.6% slower per iteration on the headline solve
     b->use_graph = 0;
     st = batch_build(b);
     if (st == MM_OK) {
@@ -1817,6 +1843,106 @@ mm_status gp_logdet(mm_plan plan, double sigma2, const double *Zc, int64_t ldz, 
     mm_solver_destroy(sv);
     if (st != MM_OK) set_error("%s", msg.c_str());
     return st;
+}
+
+mm_status gp_logdet_pc(mm_plan plan, double sigma2, mm_precond pc, const double *G1, int64_t ldg1, const double *G2,
+                       int64_t ldg2, int32_t nprobes, int32_t steps, double rtol, double *logdet, double *quad,
+                       int32_t *lanczos_steps, double *logdet_precond, void *stream) {
+    clear_error();
+    MM_TRY(check_solve_args(plan, sigma2, rtol > 0.0 ? rtol : 1.0));
+    if (!pc || !G2 || !logdet || (pc->rank > 0 && !G1)) {
+        set_error("pc, G2 and logdet (and G1 for a preconditioner of rank > 0) must be non-NULL");
+        return MM_ERR_ARG;
+    }
+    if (pc->plan != plan) {
+        set_error("the preconditioner was built for another plan");
+        return MM_ERR_ARG;
+    }
+    if (nprobes < 1 || nprobes > 64 || steps < 1 || ldg2 < plan->n || (pc->rank > 0 && ldg1 < pc->rank) ||
+        !(rtol >= 0.0)) {
+        set_error("nprobes in [1, 64], steps >= 1, ldg1 >= rank, ldg2 >= n and rtol >= 0 are required");
+        return MM_ERR_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = plan->n;
+    const int rank = pc->rank;
+    // log det P = n log sigma2 + log det(I + L^T L / sigma2) (Sylvester), by Cholesky on the host
+    double ldp = (double)n * std::log(sigma2);
+    {
+        const int r = rank;
+        std::vector<double> C((size_t)r * r, 0.0);
+        for (int j = 0; j < r; ++j) {
+            double dj = 1.0 + pc->gram[(size_t)j * r + j] / sigma2;
+            for (int k = 0; k < j; ++k) dj -= C[(size_t)j * r + k] * C[(size_t)j * r + k];
+            if (!(dj > 0.0)) {
+                set_error("preconditioner Gram factor is not positive definite");
+                return MM_ERR_NOTPD;
+            }
+            C[(size_t)j * r + j] = std::sqrt(dj);
+            ldp += 2.0 * std::log(C[(size_t)j * r + j]);
+            for (int i = j + 1; i < r; ++i) {
+                double t = pc->gram[(size_t)i * r + j] / sigma2;
+                for (int k = 0; k < j; ++k) t -= C[(size_t)i * r + k] * C[(size_t)j * r + k];
+                C[(size_t)i * r + j] = t / C[(size_t)j * r + j];
+            }
+        }
+    }
+    const double sigma = std::sqrt(sigma2);
+    double sum = 0.0;
+    mm_status st = MM_OK;
+    // preconditioned solvers take at most PC_MAXW columns: blocks of probes
+    for (int r0 = 0; r0 < nprobes && st == MM_OK; r0 += PC_MAXW) {
+        const int nb = nprobes - r0 < PC_MAXW ? nprobes - r0 : PC_MAXW;
+        mm_solver sv = nullptr;
+        st = solver_new(plan, nb, 0, sigma2, rtol > 0.0 ? rtol : 1e-300, pc, s,
+                        [&](double *B, int W) {
+                            hipLaunchKernelGGL(pc_probe_kernel, dim3(grid1(n * W)), dim3(BS), 0, s,
+                                               static_cast<const double *>(pc->L.ptr), pc->kmax, rank,
+                                               G1 ? G1 + (size_t)r0 * ldg1 : nullptr, ldg1, G2 + (size_t)r0 * ldg2,
+                                               ldg2, nb, sigma, static_cast<const int32_t *>(plan->perm.ptr), n, B,
+                                               W);
+                        },
+                        &sv, steps);
+        if (st != MM_OK) break;
+        const int W = sv->W;
+        // z^T P^{-1} z of each probe: the initial r.z
+        std::vector<double> h0((size_t)W * NS), hsc((size_t)W * NS), tl((size_t)steps * W * 2);
+        if (hipMemcpyAsync(h0.data(), sv->desc.sc, h0.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            set_error("HIP error reading the initial residuals");
+            st = MM_ERR_HIP;
+        }
+        if (st == MM_OK) st = solver_run(sv, steps, s);
+        if (st == MM_OK &&
+            (hipMemcpyAsync(hsc.data(), sv->desc.sc, hsc.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
+                 hipSuccess ||
+             hipMemcpyAsync(tl.data(), sv->desc.tlog, tl.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
+                 hipSuccess ||
+             hipStreamSynchronize(s) != hipSuccess)) {
+            set_error("HIP error reading the Lanczos coefficients");
+            st = MM_ERR_HIP;
+        }
+        for (int r = 0; r < nb && st == MM_OK; ++r) {
+            double q = 0.0;
+            int ms = 0;
+            if (!column_logquad(hsc.data() + (size_t)r * NS, tl, W, r, &q, &ms, h0[(size_t)r * NS + 0])) {
+                set_error("probe %d: the Lanczos matrix did not converge to a positive spectrum", r0 + r);
+                st = MM_ERR_BREAKDOWN;
+                break;
+            }
+            if (quad) quad[r0 + r] = q;
+            if (lanczos_steps) lanczos_steps[r0 + r] = ms;
+            sum += q;
+        }
+        std::string msg = last_error_str();
+        mm_solver_destroy(sv);
+        if (st != MM_OK) set_error("%s", msg.c_str());
+    }
+    if (st != MM_OK) return st;
+    *logdet = ldp + sum / nprobes;
+    if (logdet_precond) *logdet_precond = ldp;
+    return MM_OK;
 }
 
 mm_status gp_lml(mm_plan plan, const double *y, double sigma2, const double *Zc, int64_t ldz, int32_t nprobes,

@@ -1291,6 +1291,9 @@ inline int tile_index(int T) { return T >= 1024 ? 3 : (T >= 512 ? 2 : (T >= 256 
 mm_status profile_begin(mm_plan p, int passes_covered, hipStream_t s, hipEvent_t *ev1) {
     *ev1 = nullptr;
     if (!p->profile) return MM_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    MM_HIP_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) return MM_OK;  // a captured launch is not bracketed
     if (p->prof_used >= 4096) {
         double ms = 0.0;
         int64_t cnt = 0;
@@ -1298,8 +1301,10 @@ mm_status profile_begin(mm_plan p, int passes_covered, hipStream_t s, hipEvent_t
     }
     if (p->prof_used >= p->prof_events.size()) {
         hipEvent_t e0, e1;
-        MM_HIP_TRY(hipEventCreate(&e0));
-        MM_HIP_TRY(hipEventCreate(&e1));
+        // timing events without the system-scope release fence: the fence writes
+        // back the L2 after the bracketed launch and would be timed with it
+        MM_HIP_TRY(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+        MM_HIP_TRY(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
         p->prof_events.push_back({e0, e1});
     }
     MM_HIP_TRY(hipEventRecord(p->prof_events[p->prof_used].first, s));
