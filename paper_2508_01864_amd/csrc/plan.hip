@@ -330,6 +330,69 @@ __global__ void part_scatter(const int32_t *src, int32_t *dst, int64_t n, int bi
     }
 }
 
+// d = 3: the orthant group of position p of pass (l1, l2): the x1 half of the
+// point xor its x2 half.  Sources of one group only meet targets of the same
+// group (their halves differ in both coordinates), so each segment is split
+// into its group-0 run and its group-1 run, each still in x3 order.
+__device__ __forceinline__ uint32_t pass_group(const int32_t *ord, const int32_t *ord2, int64_t p, int l1, int l2) {
+    const int64_t q = ord[p];
+    const int64_t c = ord2[q];
+    return (uint32_t)(((c >> l1) ^ (q >> l2)) & 1);
+}
+
+// per TILE block: the number of group-1 positions
+__global__ void group_count(const int32_t *ord, const int32_t *ord2, int64_t n, int l1, int l2, uint32_t *bsum) {
+    __shared__ uint32_t wsum[BS / WAVE];
+    const int64_t b0 = (int64_t)blockIdx.x * TILE + threadIdx.x * ITEMS;
+    uint32_t c = 0;
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t p = b0 + i;
+        if (p < n) c += pass_group(ord, ord2, p, l1, l2);
+    }
+    uint32_t tot;
+    (void)block_excl_scan(c, wsum, tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// pre[p] = group-1 positions before p (exclusive prefix over the whole pass;
+// pre[n] = the total), from the scanned block counts
+__global__ void group_prefix(const int32_t *ord, const int32_t *ord2, int64_t n, int l1, int l2,
+                             const uint32_t *boff, uint32_t *pre) {
+    __shared__ uint32_t wsum[BS / WAVE];
+    const int64_t b0 = (int64_t)blockIdx.x * TILE + threadIdx.x * ITEMS;
+    uint32_t f[ITEMS];
+    uint32_t c = 0;
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t p = b0 + i;
+        f[i] = p < n ? pass_group(ord, ord2, p, l1, l2) : 0u;
+        c += f[i];
+    }
+    uint32_t tot;
+    uint32_t run = boff[blockIdx.x] + block_excl_scan(c, wsum, tot);
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t p = b0 + i;
+        if (p < n) pre[p] = run;
+        if (p == n - 1) pre[n] = run + f[i];
+        run += f[i];
+    }
+}
+
+// dst: each aligned segment of 2^seglog2 positions as its group-0 positions
+// followed by its group-1 positions, both in input order (stable)
+__global__ void group_scatter(const int32_t *ord, const int32_t *ord2, int64_t n, int l1, int l2, int seglog2,
+                              const uint32_t *pre, int32_t *dst) {
+    const int64_t seg = int64_t(1) << seglog2;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s0 = p & ~(seg - 1);
+        const int64_t send = s0 + seg < n ? s0 + seg : n;
+        const int64_t ones_before = (int64_t)(pre[p] - pre[s0]);
+        const int64_t ones = (int64_t)(pre[send] - pre[s0]);
+        const int64_t zeros = (send - s0) - ones;
+        const int64_t d = pass_group(ord, ord2, p, l1, l2) ? s0 + zeros + ones_before : p - ones_before;
+        dst[d] = ord[p];
+    }
+}
+
 // iperm[perm[c]] = c: caller index -> canonical index
 __global__ void invert_perm(const int32_t *perm, int64_t n, int32_t *iperm) {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
@@ -452,6 +515,20 @@ mm_status partition(BuildTmp &tmp, const int32_t *src, int32_t *dst, int64_t n, 
     hipLaunchKernelGGL(part_count, dim3((unsigned)nb), dim3(BS), 0, s, src, n, bit, bs);
     hipLaunchKernelGGL(scan_single, dim3(1), dim3(1024), 0, s, bs, nb);
     hipLaunchKernelGGL(part_scatter, dim3((unsigned)nb), dim3(BS), 0, s, src, dst, n, bit, seglog2, bs);
+    MM_HIP_TRY(hipGetLastError());
+    return MM_OK;
+}
+
+// d = 3: split every segment of pass (l1, l2) by orthant group (see
+// pass_group) into dst; pre (n + 1 uint32) and the block counts are scratch.
+mm_status group_split(BuildTmp &tmp, const int32_t *ord, const int32_t *ord2, int64_t n, int l1, int l2,
+                      int seglog2, uint32_t *pre, int32_t *dst, hipStream_t s) {
+    const int64_t nb = (n + TILE - 1) / TILE;
+    uint32_t *bs = static_cast<uint32_t *>(tmp.counts.ptr);
+    hipLaunchKernelGGL(group_count, dim3((unsigned)nb), dim3(BS), 0, s, ord, ord2, n, l1, l2, bs);
+    hipLaunchKernelGGL(scan_single, dim3(1), dim3(1024), 0, s, bs, nb);
+    hipLaunchKernelGGL(group_prefix, dim3((unsigned)nb), dim3(BS), 0, s, ord, ord2, n, l1, l2, bs, pre);
+    hipLaunchKernelGGL(group_scatter, dim3(grid_for(n)), dim3(BS), 0, s, ord, ord2, n, l1, l2, seglog2, pre, dst);
     MM_HIP_TRY(hipGetLastError());
     return MM_OK;
 }
@@ -674,10 +751,15 @@ mm_status plan_build(mm_plan p, const double *x, int64_t ldx, hipStream_t s) {
                 hipLaunchKernelGGL(pass_geo_kernel<2>, dim3(grid_for(n)), dim3(BS), 0, s, ps.ord, ps.ord2, ps.l1,
                                    ps.l2, xc, n, const_cast<uint32_t *>(ps.cf), const_cast<double *>(ps.xs),
                                    const_cast<double *>(ps.w1), nullptr);
-            else
-                hipLaunchKernelGGL(pass_geo_kernel<3>, dim3(grid_for(n)), dim3(BS), 0, s, ps.ord, ps.ord2, ps.l1,
+            else {
+                // the segments split by orthant group first (tmp.k0 holds the prefix counts)
+                int32_t *split = static_cast<int32_t *>(tmp.v1.ptr);
+                BUILD_TRY(group_split(tmp, ps.ord, ps.ord2, n, ps.l1, ps.l2, ps.seg_log2,
+                                      static_cast<uint32_t *>(tmp.k0.ptr), split, s));
+                hipLaunchKernelGGL(pass_geo_kernel<3>, dim3(grid_for(n)), dim3(BS), 0, s, split, ps.ord2, ps.l1,
                                    ps.l2, xc, n, const_cast<uint32_t *>(ps.cf), const_cast<double *>(ps.xs),
                                    const_cast<double *>(ps.w1), const_cast<double *>(ps.w2));
+            }
         }
     }
     hipError_t e = hipStreamSynchronize(s);

@@ -37,11 +37,11 @@ size_t sweep_part_bytes(int64_t n, int npass, int W) {
 // Doubles of one tile aggregate per right-hand side: classes x channel rows
 // x scan channels (the configuration's FULLSLOT), for the kernel and, with
 // der, also for its lengthscale-derivative sweeps (one more channel in one
-// factor).  At most 4 x 9 x 3 = 108 for the kernel and 144 with der (d = 3,
+// factor).  At most 2 x 9 x 3 = 54 for the kernel and 72 with der (d = 3,
 // product form, nu = 5/2).
 int agg_per_rhs(int d, const mm_kernel &k, bool der) {
     const KParams kp = kparams(k, d);
-    const int ncls = d == 1 ? 1 : (d == 2 ? 2 : 4);
+    const int ncls = d == 1 ? 1 : 2;  // two classes (the x1 half) in d = 2 and, per orthant group, in d = 3
     int best = 0;
     for (int gj = -1; gj < (der ? d : 0); ++gj) {
         if (!kp.prod && gj >= 0 && gj != d - 1) continue;

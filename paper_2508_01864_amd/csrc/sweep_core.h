@@ -229,12 +229,15 @@ struct Cfg {
     static constexpr int PC0 = GJ_ == 0 && D_ > 1 ? P_ + 1 : P_;
     static constexpr int PC1 = GJ_ == 1 && D_ > 2 ? P_ + 1 : P_;
     static constexpr int NTH = PROD ? (D == 1 ? 1 : (D == 2 ? PC0 : PC0 * PC1)) : 1; // non-scan channel rows
-    // source classes (orthants of the non-scan coordinates) and how many
-    // sub-sweeps they are split over so that one state fits the register file
-    // (each sub-sweep repeats the scan for its classes)
-    static constexpr int NCLS_ALL = (D == 1) ? 1 : (D == 2 ? 2 : 4);
+    // source classes and how many sub-sweeps they are split over so that one
+    // state fits the register file (each sub-sweep repeats the scan for its
+    // classes).  Two classes in d >= 2, told apart by the x1 half: in d = 3
+    // every segment of a pass lists its two orthant groups (x1 half xor x2
+    // half) one after the other, the state restarting between them, and
+    // inside a group the x1 half fixes the x2 half.
+    static constexpr int NCLS_ALL = (D == 1) ? 1 : 2;
     static constexpr int FULLSLOT = NCLS_ALL * NTH * P;
-    static constexpr int NSUB = (D == 3) ? (FULLSLOT <= 16 ? 1 : (FULLSLOT <= 32 ? 2 : 4)) : 1;
+    static constexpr int NSUB = (D == 3 && FULLSLOT > 32) ? 2 : 1;
     static constexpr int NCLS = NCLS_ALL / NSUB;
     static constexpr int NSLOT = NCLS * NTH * P;             // doubles per state
     static constexpr int G = 2 * (D - 1);                    // staged geometry doubles
@@ -417,31 +420,23 @@ __device__ __forceinline__ double read_target(const State<C> &S, int cls, const 
 }
 
 // Source / target class of an element in sub-sweep `hh`.  d = 2: the x1 half
-// (sources of one half feed targets of the other).  d = 3: the (x1, x2)
-// halves; a source class feeds the targets in the opposite halves of both.
-// With NSUB > 1 each sub-sweep carries only part of the classes.
+// (sources of one half feed targets of the other).  d = 3: the same within
+// an orthant group (the x2 half is the x1 half xor the group), so a source
+// class feeds the targets in the opposite halves of both coordinates.  With
+// NSUB = 2 each sub-sweep carries one class.
 template <class C>
 __device__ __forceinline__ void classes(int flags, int hh, int &scls, int &tcls) {
     if constexpr (C::D == 1) {
         scls = 0;
         tcls = 0;
-    } else if constexpr (C::D == 2) {
-        const int s1 = flags & F_SIDE1;
-        scls = s1;
-        tcls = 1 - s1;
     } else {
         const int s1 = flags & F_SIDE1;
-        const int s2 = (flags & F_SIDE2) ? 1 : 0;
-        const int full = s1 * 2 + s2;
         if constexpr (C::NSUB == 1) {
-            scls = full;
-            tcls = 3 - full;
-        } else if constexpr (C::NSUB == 2) {
-            scls = (s1 == hh) ? s2 : -1;
-            tcls = (s1 == 1 - hh) ? 1 - s2 : -1;
+            scls = s1;
+            tcls = 1 - s1;
         } else {
-            scls = (full == hh) ? 0 : -1;
-            tcls = (3 - full == hh) ? 0 : -1;
+            scls = (s1 == hh) ? 0 : -1;
+            tcls = (1 - s1 == hh) ? 0 : -1;
         }
     }
     if (!(flags & F_VALID)) {
@@ -527,7 +522,14 @@ __device__ __forceinline__ void stage_tile(const SweepArgs &A, const PassDev &ps
         }
         // from the predecessor, including across the tile's edges (position p0
         // from p0 - 1, and the next tile's first position p0 + T from the last)
-        const bool has_prev = p < n && p > 0 && (p & segmask) != 0;
+        bool has_prev = p < n && p > 0 && (p & segmask) != 0;
+        if constexpr (C::D == 3) {
+            // the state also restarts where a segment's second orthant group begins
+            if (has_prev) {
+                const uint32_t c0 = gld(ps.cf + p), c1 = gld(ps.cf + p - 1);
+                has_prev = (((c0 ^ (c0 >> 1)) ^ (c1 ^ (c1 >> 1))) & (1u << 30)) == 0;
+            }
+        }
         double e = 0.0, t = 0.0, xprev = xcur;
         if (has_prev) {
             xprev = scan_coord<C>(A, ps, p - 1);
@@ -546,6 +548,57 @@ template <class C>
 __device__ __forceinline__ void load_geo(const Smem<C> &sm, int sj, double (&geo)[C::G > 0 ? C::G : 1]) {
 #pragma unroll
     for (int k = 0; k < C::G; ++k) geo[k] = sm.geo[k][sj];
+}
+
+// Restarts of the scan state inside a tile, for the transfers that join runs
+// and tiles (d = 3, where a segment's second orthant group begins mid-segment;
+// in d <= 2 restarts fall only on segment boundaries, which the run groups and
+// tile carries respect by construction).  A staged decay of exactly 0 marks a
+// position whose state does not come from its predecessor.  For this lane's
+// run r: f, a restart at one of its positions (the forward transfer from the
+// previous run's last position to r's last crosses them); b, a restart after
+// its first position up to the next run's first (the backward transfer from
+// the next run's first position to r's first).  mf / mb: the same over the
+// wave, one bit per lane (the run's WCOL lanes carry its flags).
+struct Cuts {
+    bool f = false, b = false;
+    uint64_t mf = 0, mb = 0;
+};
+
+template <class C>
+__device__ __forceinline__ Cuts tile_cuts(const Smem<C> &sm, int run) {
+    Cuts c;
+    if constexpr (C::D == 3) {
+        bool f = false, b = false;
+#pragma unroll
+        for (int e = 0; e < C::E; ++e) {
+            const bool z = sm.est[e * C::RUNS + run] == 0.0;
+            f = f || z;
+            if (e > 0) b = b || z;
+        }
+        b = b || (run + 1 < C::RUNS ? sm.est[run + 1] : sm.est[C::T]) == 0.0;
+        c.f = f;
+        c.b = b;
+        c.mf = __ballot(f);
+        c.mb = __ballot(b);
+    }
+    return c;
+}
+
+// Whether a restart lies between the previous tile's anchor and this run's
+// entry anchor in scan direction DIR (lanes of the runs before r forward,
+// after r backward).
+template <class C, int DIR>
+__device__ __forceinline__ bool cut_before_run(const Cuts &c, int run) {
+    if constexpr (C::D != 3) {
+        return false;
+    } else if constexpr (DIR == 0) {
+        const int lo = run * C::WCOL;
+        return (c.mf & (lo >= 64 ? ~0ull : ((1ull << lo) - 1))) != 0;
+    } else {
+        const int hi = (run + 1) * C::WCOL;
+        return (c.mb & (hi >= 64 ? 0ull : ~((1ull << hi) - 1))) != 0;
+    }
 }
 
 // First element of a wave's stored within-tile run carries (element k of lane
@@ -613,7 +666,7 @@ __device__ __forceinline__ double scan_elem(const Smem<C> &sm, State<C> &S, int 
     ElemVec<C> ev;
     elem_vectors<C>(geo, ev);
     double out = 0.0;
-    if constexpr (C::D == 2) {
+    if constexpr (C::D >= 2 && C::NCLS == 2) {
         // two classes, told apart by the x1 half alone: sources of half s
         // feed the targets of half 1 - s.  A position past the end has zero
         // staged geometry (a zero source vector), so it needs no class test.
@@ -638,7 +691,9 @@ __device__ __forceinline__ double scan_elem(const Smem<C> &sm, State<C> &S, int 
 // recurrence of the forward direction; Fb, anchored at its first position,
 // adds each source moved by its distance and decay from that position, which
 // accumulate along the walk.  Only for runs inside one segment (segments
-// longer than a tile), so no staged decay inside the run is a restart.
+// longer than a tile); a restart inside the run (d = 3, between orthant
+// groups) stages a zero decay, which zeroes the later sources' weights in Fb
+// (they do not reach the run's first position) and the earlier state in Ff.
 template <class C>
 __device__ __forceinline__ void run_aggregates(const SweepArgs &A, const Smem<C> &sm, int run, int col, int hh,
                                                State<C> &Ff, State<C> &Fb) {
@@ -673,7 +728,7 @@ __device__ __forceinline__ void run_aggregates(const SweepArgs &A, const Smem<C>
             ElemVec<C> ev;
             elem_vectors<C>(geo, ev);
             const int fl = sm.flags[sj];
-            if constexpr (C::D == 2) {
+            if constexpr (C::D >= 2 && C::NCLS == 2) {
                 const bool s1 = fl & F_SIDE1;
                 add_class_moved<C>(Fb, 0, ev, s1 ? 0.0 : vb[k], Ec, D, pw);
                 add_class_moved<C>(Fb, 1, ev, s1 ? vb[k] : 0.0, Ec, D, pw);
@@ -699,8 +754,9 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                                               int hh, int64_t tile, int pl, int col, int run,
                                               const double (&vr)[C::REGOUT ? C::E : 1],
                                               double (&outv)[C::SUMREG ? C::E : 1], double *slab, double *lout,
-                                              const State<C> *Fpre = nullptr) {
+                                              const Cuts &cu, const State<C> *Fpre = nullptr) {
     const int seg = 1 << (ps.seg_log2 < 30 ? ps.seg_log2 : 30);
+    const bool cut_run = DIR == 0 ? cu.f : cu.b;  // restart between the previous anchor and this run's
     // runs per segment group (1 when segments fit in a run)
     const int Gr = seg <= C::E ? 1 : (seg >= C::T ? C::RUNS : seg / C::E);
     const int lig = run & (Gr - 1);
@@ -770,6 +826,8 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                 if (has) {
                     tr = a * (DIR == 0 ? xend - xo : xo - xend);
                     Er = exp(-tr);
+                    if constexpr (C::D == 3)
+                        if (cut_run) Er = 0.0;
                 }
             }
 #pragma unroll 1
@@ -802,7 +860,7 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
             if (run == (DIR == 0 ? C::RUNS - 1 : 0)) {
                 State<C> tot = Ex;
                 const double t = a * (DIR == 0 ? xend - xex : xex - xend);
-                tot.shift(exp(-t), t);
+                tot.shift(cut_run ? 0.0 : exp(-t), t);
                 tot.add_shifted(Frun, 1.0, 0.0);
                 double *dst = A.agg + agg_index<C>(A, DIR, pl, tile, col, hh);
 #pragma unroll
@@ -815,7 +873,8 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                     const int64_t tps = seg / C::T;
                     const bool first = DIR == 0 ? (tile % tps) == 0 : (((tile + 1) % tps) == 0 || tile + 1 == A.ntile);
                     const double xo = sm.xedge[DIR == 0 ? 0 : 1];
-                    gst(A.dec + ai, first ? 1.0 : exp(-a * (DIR == 0 ? xend - xo : xo - xend)));
+                    const bool cut_tile = (DIR == 0 ? cu.mf : cu.mb) != 0;  // a restart inside the tile's span
+                    gst(A.dec + ai, first ? 1.0 : (cut_tile ? 0.0 : exp(-a * (DIR == 0 ? xend - xo : xo - xend))));
                 }
             }
             return;
@@ -832,7 +891,7 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                 const double anc = gld(A.anc + ((int64_t)DIR * A.G + pl) * A.ntile + (DIR == 0 ? tile - 1 : tile + 1));
                 if (run == (DIR == 0 ? 0 : C::RUNS - 1)) xex = anc;
                 const double t = a * (DIR == 0 ? xex - anc : anc - xex);
-                Ex.add_shifted(cf, exp(-t), t);
+                Ex.add_shifted(cf, cut_before_run<C, DIR>(cu, run) ? 0.0 : exp(-t), t);
             }
         }
     }
@@ -924,6 +983,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, doub
     const int run = lane / C::WCOL;
     const int64_t p0 = tile * C::T;
     stage_tile<C>(A, ps, sm, p0);
+    const Cuts cu = tile_cuts<C>(sm, run);
     double *slab = A.ypart + (int64_t)pl * A.n * A.W;
 
     double vr[C::REGOUT ? C::E : 1], outv[C::SUMREG ? C::E : 1];
@@ -945,11 +1005,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, doub
         if constexpr (MODE == 1) {
             State<C> Ff, Fb;
             run_aggregates<C>(A, sm, run, col, hh, Ff, Fb);
-            run_direction<C, MODE, 1>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout, &Fb);
-            run_direction<C, MODE, 0>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout, &Ff);
+            run_direction<C, MODE, 1>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout, cu, &Fb);
+            run_direction<C, MODE, 0>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout, cu, &Ff);
         } else {
-            run_direction<C, MODE, 1>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout);
-            run_direction<C, MODE, 0>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout);
+            run_direction<C, MODE, 1>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout, cu);
+            run_direction<C, MODE, 0>(A, ps, sm, hh, tile, pl, col, run, vr, outv, slab, lout, cu);
         }
     }
 
