@@ -153,6 +153,14 @@ def schedule_candidates(d: int, two_nu: int, form: str, width: int) -> List[Tupl
     return out
 
 
+def stores_run_carries(d: int, width: int, wb: int, e: int, runex) -> bool:
+    """Whether a product at padded width `width` on schedule (wb, e, runex)
+    stores the runs' within-tile carries in its pre-pass: d <= 2, fewer than
+    32 columns, at least 2 columns per wave and runs of 8 to 32 (the lane keeps
+    its run's sums in registers)."""
+    return bool(runex) and d <= 2 and width < 32 and wb >= 2 and 4 < e <= 32
+
+
 def schedule_key(n: int, d: int, two_nu: int, form: str, width: int) -> str:
     return "sched|d%d.nu%d.%s|N%d|w%d" % (d, two_nu, form, int(round(math.log2(max(n, 1)))), width)
 

@@ -8,6 +8,9 @@ advances all of them together: each tick runs ``chunk`` iterations of one
 launches), then polls.  Finished requests leave (their GLS estimate and
 posterior mean at z are computed, their memory is released) and waiting
 requests are admitted in arrival order as slots and device memory free up.
+A request admitted while a chunk is in flight has its plan, preconditioner
+and solver created on a side stream, beside that chunk; it joins the batch
+when the chunk's poll returns.
 Admission is by device footprint: the plan, the solver, the optional
 pivoted Cholesky preconditioner and the temporary prediction plan of a
 request are bounded on the host before anything is allocated, and a request is admitted only while the sum over admitted
@@ -105,16 +108,23 @@ def summary(resps: List[Response]) -> dict:
 
 
 class _Live:
-    def __init__(self, req: Request, device, admitted: float):
+    """An admitted request: its inputs, plan, preconditioner and solver, all
+    created on ``stream`` (the server's side stream), so that their creation
+    kernels run beside the iterations already in flight on the batch's own
+    stream."""
+
+    def __init__(self, req: Request, device, admitted: float, stream=None):
         import torch
         self.req = req
         self.admitted = admitted
-        self.x = torch.as_tensor(req.x, device=device)
-        self.y = torch.as_tensor(req.y, device=device)
-        self.z = torch.as_tensor(req.z, device=device)
-        self.plan = Plan(self.x, req.kernel)
-        self.pc = Precond(self.plan, max_rank=req.precond_rank) if req.precond_rank > 0 else None
-        self.solver = Solver(self.plan, self.y, req.sigma2, fixed_effects=True, rtol=req.rtol, precond=self.pc)
+        with torch.cuda.stream(stream) if stream is not None else _null():
+            self.x = torch.as_tensor(req.x, device=device)
+            self.y = torch.as_tensor(req.y, device=device)
+            self.z = torch.as_tensor(req.z, device=device)
+            self.plan = Plan(self.x, req.kernel, stream=stream)
+            self.pc = Precond(self.plan, max_rank=req.precond_rank, stream=stream) if req.precond_rank > 0 else None
+            self.solver = Solver(self.plan, self.y, req.sigma2, fixed_effects=True, rtol=req.rtol,
+                                 stream=stream, precond=self.pc)
         self.iters = 0
         self.bytes = request_bytes(len(req.y), req.x.shape[1], len(req.z), req.kernel, req.precond_rank)
 
@@ -125,11 +135,21 @@ class _Live:
         self.plan.close()
 
 
+class _null:
+    def __enter__(self):
+        return None
+
+    def __exit__(self, *a):
+        return False
+
+
 class Server:
     def __init__(self, budget_bytes: Optional[int] = None, max_slots: int = 64, chunk: int = 16,
-                 use_graph: bool = True, tune: bool = True, device=None):
+                 use_graph: bool = True, tune: bool = True, device=None, side_stream: bool = True):
         import torch
         self.device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        # admissions build on their own stream (default priority) while the batch iterates
+        self.side = torch.cuda.Stream(device=self.device) if side_stream else None
         self.budget = int(budget_bytes) if budget_bytes is not None else default_budget()
         self.max_slots = int(max_slots)
         self.chunk = int(chunk)
@@ -155,34 +175,40 @@ class Server:
         def now() -> float:
             return time.perf_counter() - wall0 + skipped
 
+        def admit(room: int):
+            """Admit queued requests in arrival order while slots and memory allow."""
+            nonlocal used
+            got = []
+            while queue and len(live) + len(got) < min(room, self.max_slots):
+                r = queue[0]
+                need = request_bytes(len(r.y), r.x.shape[1], len(r.z), r.kernel, r.precond_rank)
+                if need > self.budget:
+                    raise RuntimeError("request %d needs %d bytes, more than the whole budget %d"
+                                       % (r.rid, need, self.budget))
+                if used + need > self.budget:
+                    break
+                queue.popleft()
+                got.append(_Live(r, self.device, now(), stream=self.side))
+                used += need
+            return got
+
+        new: List[_Live] = []
         try:
             while pending or queue or live:
                 t = now()
                 while pending and pending[0].arrival <= t:
                     queue.append(pending.popleft())
-                changed = False
-                while queue and len(live) < self.max_slots:
-                    r = queue[0]
-                    need = request_bytes(len(r.y), r.x.shape[1], len(r.z), r.kernel, r.precond_rank)
-                    if need > self.budget:
-                        raise RuntimeError("request %d needs %d bytes, more than the whole budget %d"
-                                           % (r.rid, need, self.budget))
-                    if used + need > self.budget:
-                        break
-                    queue.popleft()
-                    live[r.rid] = _Live(r, self.device, now())
-                    used += need
-                    changed = True
-                self.peak_bytes = max(self.peak_bytes, used)
-                self.peak_slots = max(self.peak_slots, len(live))
                 if not live:
-                    # idle: jump to the next arrival
-                    if pending:
-                        skipped += max(0.0, pending[0].arrival - now())
-                    continue
-                if changed or batch is None:
-                    if batch is not None:
-                        batch.close()
+                    for lv in admit(self.max_slots):
+                        live[lv.req.rid] = lv
+                    self.peak_bytes = max(self.peak_bytes, used)
+                    self.peak_slots = max(self.peak_slots, len(live))
+                    if not live:
+                        # idle: jump to the next arrival
+                        if pending:
+                            skipped += max(0.0, pending[0].arrival - now())
+                        continue
+                if batch is None:
                     members = sorted(live)
                     batch = SolverBatch([live[i].solver for i in members], use_graph=self.use_graph)
                     self.rebuilds += 1
@@ -193,7 +219,14 @@ class Server:
                             batch.set_schedule(*sched)
                 k = min([self.chunk] + [live[i].req.maxit - live[i].iters for i in members])
                 k = max(k, 1)
+                if self.side is not None:
+                    # creation, check and restart work of the solvers was queued on the side
+                    # stream; the batch runs on its own stream, ordered after this point
+                    self.side.synchronize()
                 batch.iterate(k)
+                # requests that arrived meanwhile are admitted (plans built on the side
+                # stream) while the chunk runs; they join the batch at its next rebuild
+                new = admit(self.max_slots)
                 status = batch.poll()
                 self.ticks += 1
                 finished = []
@@ -206,22 +239,27 @@ class Server:
                             continue
                     if st <= 0 or live[i].iters >= live[i].req.maxit:
                         finished.append(i)
-                if finished:
+                if finished or new:
                     batch.close()
                     batch = None
-                    for i in finished:
-                        lv = live.pop(i)
-                        alpha, beta, info = lv.solver.finish(raise_on_error=False)
-                        mean = lv.plan.predict(alpha, lv.z, beta=beta)
-                        lv.close()
-                        out.append(Response(i, lv.req.arrival, lv.admitted, now(), alpha, beta, mean, info))
-                        used -= lv.bytes
-                        if on_done is not None:
-                            on_done(out[-1])
+                for i in finished:
+                    lv = live.pop(i)
+                    alpha, beta, info = lv.solver.finish(raise_on_error=False)
+                    mean = lv.plan.predict(alpha, lv.z, beta=beta)
+                    lv.close()
+                    out.append(Response(i, lv.req.arrival, lv.admitted, now(), alpha, beta, mean, info))
+                    used -= lv.bytes
+                    if on_done is not None:
+                        on_done(out[-1])
+                for lv in new:
+                    live[lv.req.rid] = lv
+                new = []
+                self.peak_bytes = max(self.peak_bytes, used)
+                self.peak_slots = max(self.peak_slots, len(live))
         finally:
             if batch is not None:
                 batch.close()
-            for lv in live.values():
+            for lv in list(live.values()) + [lv for lv in new if lv.req.rid not in live]:
                 lv.close()
         return sorted(out, key=lambda r: r.rid)
 
