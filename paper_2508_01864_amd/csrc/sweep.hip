@@ -288,7 +288,7 @@ mm_status sweep_batch_run(SweepBatch &b, hipStream_t s) {
             using C = typename decltype(t)::type;
             const SweepArgs *descs = static_cast<const SweepArgs *>(cl.descs.ptr);
             if (cl.n_agg > 0)
-                hipLaunchKernelGGL((sweep_batch_kernel<C, 1>), dim3(persist_grid(cl.n_agg, b.grid_per_cu)), dim3(WAVE), 0,
+                hipLaunchKernelGGL((sweep_batch_kernel<C, 1>), dim3(persist_grid(cl.n_agg, b.grid_per_cu)), dim3(C::BLOCK), 0,
                                    s, descs, static_cast<const int4 *>(cl.items_agg.ptr), cl.n_agg);
             if (cl.n_carry > 0)
                 hipLaunchKernelGGL((carry_batch_kernel<C>), dim3(persist_grid(cl.n_carry, b.grid_per_cu)), dim3(256),
@@ -296,7 +296,7 @@ mm_status sweep_batch_run(SweepBatch &b, hipStream_t s) {
             if (cl.n_main > 0) {
                 hipEvent_t ev1 = nullptr;
                 if (b.plans.size() == 1) MM_TRY(profile_begin(b.plans[0], (int)b.plans[0]->passes.size(), s, &ev1));
-                hipLaunchKernelGGL((sweep_batch_kernel<C, 0>), dim3(persist_grid(cl.n_main, b.grid_per_cu)), dim3(WAVE),
+                hipLaunchKernelGGL((sweep_batch_kernel<C, 0>), dim3(persist_grid(cl.n_main, b.grid_per_cu)), dim3(C::BLOCK),
                                    0, s, descs, static_cast<const int4 *>(cl.items_main.ptr), cl.n_main);
                 if (ev1) MM_HIP_TRY(hipEventRecord(ev1, s));
             }

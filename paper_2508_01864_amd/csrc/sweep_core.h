@@ -238,6 +238,12 @@ struct Cfg {
     static constexpr int NCLS_ALL = (D == 1) ? 1 : 2;
     static constexpr int FULLSLOT = NCLS_ALL * NTH * P;
     static constexpr int NSUB = (D == 3 && FULLSLOT > 32) ? 2 : 1;
+    // The sub-sweeps run side by side, one wave each, in one workgroup that
+    // stages the tile once: the staged tile's LDS is shared by the waves, and
+    // every element is a target of exactly one sub-sweep (the one carrying the
+    // other class), so each wave writes only its own targets' sums.
+    static constexpr int NWAVE = NSUB;
+    static constexpr int BLOCK = WAVE * NWAVE;
     static constexpr int NCLS = NCLS_ALL / NSUB;
     static constexpr int NSLOT = NCLS * NTH * P;             // doubles per state
     static constexpr int G = 2 * (D - 1);                    // staged geometry doubles
@@ -445,6 +451,14 @@ __device__ __forceinline__ void classes(int flags, int hh, int &scls, int &tcls)
     }
 }
 
+// Whether a staged element (its flags) is a target of sub-sweep hh.
+template <class C>
+__device__ __forceinline__ bool is_target(int flags, int hh) {
+    int sc, tc;
+    classes<C>(flags, hh, sc, tc);
+    return tc >= 0;
+}
+
 // Staged tile in LDS, stored [element of the run][run]: lanes of different
 // runs read different banks, lanes of the same run (different columns) read
 // the same address (broadcast).  Local position j lives at slot(j).
@@ -487,7 +501,7 @@ __device__ __forceinline__ void stage_tile(const SweepArgs &A, const PassDev &ps
                                            int64_t p0) {
     const int64_t n = A.n;
     const int64_t segmask = (int64_t(1) << ps.seg_log2) - 1;
-    for (int j = threadIdx.x; j <= C::T; j += WAVE) {
+    for (int j = threadIdx.x; j <= C::T; j += C::BLOCK) {
         const int64_t p = p0 + j;
         const int64_t pc = p < n ? p : n - 1;
         const double xcur = scan_coord<C>(A, ps, pc);
@@ -912,14 +926,18 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                 for (int k = 0; k < C::BLK; ++k) {
                     const int e = DIR == 0 ? b + k : C::E - 1 - b - k;
                     const int sj = e * C::RUNS + run;
-                    const bool valid = sm.flags[sj] & F_VALID;
+                    // with one wave per sub-sweep a wave writes only its own targets
+                    // (each element is a target of exactly one sub-sweep)
+                    const bool valid = C::NWAVE > 1 ? is_target<C>(sm.flags[sj], hh) : (sm.flags[sj] & F_VALID) != 0;
                     const int64_t ad = (int64_t)sm.c[sj] * A.W + col;  // clamped: always in range
                     addr[k] = valid ? ad : -1;
                     vb[k] = gld(A.vin + ad);  // unused past the end (no source class)
                     // the slab already holds this element's earlier values unless this is
-                    // the first write of the pass (backward direction of sub-sweep 0)
+                    // its first write of the pass (the backward direction of its first
+                    // sub-sweep: sub-sweep 0 when they run one after another, its own
+                    // wave's when they run side by side)
                     if constexpr (!C::LDSOUT && !C::OUTREG) {
-                        if (DIR == 0 || hh > 0) {
+                        if (DIR == 0 || (C::NWAVE == 1 && hh > 0)) {
                             const double lo = gld(slab + ad);
                             ob[k] = valid ? lo : 0.0;
                         } else {
@@ -936,9 +954,14 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                         const int q = DIR == 0 ? k : C::E - 1 - k;
                         outv[q] = (DIR == 0 || hh > 0) ? outv[q] + val : val;
                     } else if constexpr (C::LDSOUT) {
-                        // this lane's own entry: no other lane touches it
-                        double &o = lout[(e * C::RUNS + run) * C::WCOL + threadIdx.x % C::WCOL];
-                        o = (DIR == 0 || hh > 0) ? o + val : val;
+                        // this lane's own entry: no other lane of the wave touches it, and
+                        // with one wave per sub-sweep the other wave skips it
+                        double &o = lout[(e * C::RUNS + run) * C::WCOL + col % C::WCOL];
+                        if constexpr (C::NWAVE > 1) {
+                            if (is_target<C>(sm.flags[e * C::RUNS + run], hh)) o = DIR == 0 ? o + val : val;
+                        } else {
+                            o = (DIR == 0 || hh > 0) ? o + val : val;
+                        }
                     } else {
                         if (addr[k] >= 0) gst(slab + addr[k], ob[k] + val);
                     }
@@ -978,7 +1001,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, doub
     }
     const int pl = pass - A.g0;
     const PassDev ps = A.passes[pass];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % WAVE;
     const int col = by * C::WCOL + lane % C::WCOL;
     const int run = lane / C::WCOL;
     const int64_t p0 = tile * C::T;
@@ -1000,8 +1023,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, doub
         }
     }
 
+    // sub-sweeps: one per wave when they run side by side, else one after another
+    const int hh0 = C::NWAVE > 1 ? (int)(threadIdx.x / WAVE) : 0;
+    const int hh1 = C::NWAVE > 1 ? hh0 + 1 : C::NSUB;
 #pragma unroll 1
-    for (int hh = 0; hh < C::NSUB; ++hh) {
+    for (int hh = hh0; hh < hh1; ++hh) {
         if constexpr (MODE == 1) {
             State<C> Ff, Fb;
             run_aggregates<C>(A, sm, run, col, hh, Ff, Fb);
@@ -1021,8 +1047,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, doub
         }
     }
     if constexpr (MODE == 0 && C::LDSOUT) {
-        // one write of each target's sums to the pass's slab
-        for (int e = 0; e < C::E; ++e) {
+        // one write of each target's sums to the pass's slab (the waves of the
+        // sub-sweeps take alternate elements, after both have finished)
+        if constexpr (C::NWAVE > 1) __syncthreads();
+        for (int e = (int)(threadIdx.x / WAVE); e < C::E; e += C::NWAVE) {
             const int sj = e * C::RUNS + run;
             if (sm.flags[sj] & F_VALID) gst(slab + (int64_t)sm.c[sj] * A.W + col, lout[sj * C::WCOL + lane % C::WCOL]);
         }
@@ -1030,7 +1058,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, doub
 }
 
 template <class C, int MODE>
-__global__ __launch_bounds__(WAVE) void sweep_kernel(SweepArgs A) {
+__global__ __launch_bounds__(C::BLOCK) void sweep_kernel(SweepArgs A) {
     __shared__ Smem<C> sm;
     if constexpr (MODE == 0 && C::LDSOUT) {
         __shared__ Lout<C> lo;
@@ -1043,7 +1071,7 @@ __global__ __launch_bounds__(WAVE) void sweep_kernel(SweepArgs A) {
 // Batched: every item (problem, block x, block y) of a table runs the same body
 // with its problem's arguments; a fixed grid walks the table (persistent).
 template <class C, int MODE>
-__global__ __launch_bounds__(WAVE) void sweep_batch_kernel(const SweepArgs *descs, const int4 *items, int nitems) {
+__global__ __launch_bounds__(C::BLOCK) void sweep_batch_kernel(const SweepArgs *descs, const int4 *items, int nitems) {
     __shared__ Smem<C> sm;
     double *lout = nullptr;
     if constexpr (MODE == 0 && C::LDSOUT) {
@@ -1433,7 +1461,7 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
         A.k0 = k0;
         if (k1 > k0 && ntile > 1) {
             const dim3 gx((unsigned)((k1 - k0) * ntile), (unsigned)ncb);
-            hipLaunchKernelGGL((sweep_kernel<C, 1>), gx, dim3(WAVE), 0, s, A);
+            hipLaunchKernelGGL((sweep_kernel<C, 1>), gx, dim3(C::BLOCK), 0, s, A);
             // segments of the group's cross-tile passes: a contiguous range of the plan's table
             const std::vector<int> &so = p->seg_off[ti];
             const int s0 = so[k0], s1 = so[k1];
@@ -1446,7 +1474,7 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
         }
         hipEvent_t ev1 = nullptr;
         if (!ws) MM_TRY(profile_begin(p, G, s, &ev1));  // (profiling creates events: not with a caller workspace)
-        hipLaunchKernelGGL((sweep_kernel<C, 0>), dim3((unsigned)(G * ntile), (unsigned)ncb), dim3(WAVE), 0, s, A);
+        hipLaunchKernelGGL((sweep_kernel<C, 0>), dim3((unsigned)(G * ntile), (unsigned)ncb), dim3(C::BLOCK), 0, s, A);
         if (ev1) MM_HIP_TRY(hipEventRecord(ev1, s));
         if (tail && g0 + G >= npass) {
             tail[0] = G;

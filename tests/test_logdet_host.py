@@ -28,3 +28,17 @@ def test_quadrature_of_cg_coefficients(oracle_lib):
     q = mm.lanczos_logquad(al[:m], be[: m - 1]) * float(z @ z)
     exact = oracle.quad_log_exact(A, z)[0]
     assert abs(q - exact) <= 1e-6 * abs(exact)
+
+
+def test_quadrature_refuses_a_non_positive_spectrum():
+    """A Lanczos matrix with a non-positive eigenvalue (which a breakdown of CG
+    would leave) has no logarithm: MM_ERR_BREAKDOWN."""
+    with pytest.raises(mm.MaternError) as e:
+        mm.lanczos_logquad(np.array([-1.0]), np.array([]))
+    assert e.value.status == mm.MM_ERR_BREAKDOWN
+    # T = [[1, 3], [3, 1]]: eigenvalues 4 and -2
+    a0, b0 = 1.0, 9.0                      # T[0][1] = sqrt(b0) / a0 = 3
+    a1 = 1.0 / (1.0 - b0 / a0)             # T[1][1] = 1/a1 + b0/a0 = 1
+    with pytest.raises(mm.MaternError) as e:
+        mm.lanczos_logquad(np.array([a0, a1]), np.array([b0]))
+    assert e.value.status == mm.MM_ERR_BREAKDOWN
