@@ -244,6 +244,9 @@ struct Cfg {
     // other class), so each wave writes only its own targets' sums.
     static constexpr int NWAVE = NSUB;
     static constexpr int BLOCK = WAVE * NWAVE;
+    // at least 2 waves per SIMD for the two-wave workgroups (without the bound
+    // the compiler takes AGPRs as spill room and drops to one wave)
+    static constexpr int MINW = NWAVE > 1 ? 2 : 1;
     static constexpr int NCLS = NCLS_ALL / NSUB;
     static constexpr int NSLOT = NCLS * NTH * P;             // doubles per state
     static constexpr int G = 2 * (D - 1);                    // staged geometry doubles
@@ -1058,7 +1061,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, doub
 }
 
 template <class C, int MODE>
-__global__ __launch_bounds__(C::BLOCK) void sweep_kernel(SweepArgs A) {
+__global__ __launch_bounds__(C::BLOCK, C::MINW) void sweep_kernel(SweepArgs A) {
     __shared__ Smem<C> sm;
     if constexpr (MODE == 0 && C::LDSOUT) {
         __shared__ Lout<C> lo;
@@ -1071,7 +1074,7 @@ __global__ __launch_bounds__(C::BLOCK) void sweep_kernel(SweepArgs A) {
 // Batched: every item (problem, block x, block y) of a table runs the same body
 // with its problem's arguments; a fixed grid walks the table (persistent).
 template <class C, int MODE>
-__global__ __launch_bounds__(C::BLOCK) void sweep_batch_kernel(const SweepArgs *descs, const int4 *items, int nitems) {
+__global__ __launch_bounds__(C::BLOCK, C::MINW) void sweep_batch_kernel(const SweepArgs *descs, const int4 *items, int nitems) {
     __shared__ Smem<C> sm;
     double *lout = nullptr;
     if constexpr (MODE == 0 && C::LDSOUT) {
