@@ -659,6 +659,108 @@ __device__ __forceinline__ void scan_step(State<C> &F, double &t, double &E, int
     }
 }
 
+// One column per wave (lane = run): the lane scan's moves within rows of 16
+// lanes go through DPP instead of LDS permutes.  CTRL is a DPP row shift
+// (0x110 + n: from lane l - n, 0x100 + n: from lane l + n, within the row) or
+// a wave shift by one lane (0x138: from lane l - 1, 0x130: from lane l + 1);
+// lanes without a source read 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// F <- F + M(E, t) F(partner) with the partner O lanes away inside the row
+// (as scan_step).
+template <class C, bool UP, int O>
+__device__ __forceinline__ void scan_step_row(State<C> &F, double &t, double &E, bool ok) {
+    constexpr int CTRL = UP ? 0x110 + O : 0x100 + O;
+    const double tp = dpp_move<CTRL>(t);
+    const double Ep = dpp_move<CTRL>(E);
+#pragma unroll
+    for (int c = 0; c < C::NCLS; ++c)
+#pragma unroll
+        for (int h = 0; h < C::NTH; ++h) {
+            double q[C::P];
+#pragma unroll
+            for (int m = 0; m < C::P; ++m) q[m] = dpp_move<CTRL>(F.s[c][h][m]);
+            if (ok) madd(F.s[c][h], q, E, t);
+        }
+    if (ok) {
+        t += tp;
+        E *= Ep;
+    }
+}
+
+// F <- F + M(E, t) F(src) for a partner lane given by number (crossing rows).
+template <class C>
+__device__ __forceinline__ void scan_step_lane(State<C> &F, double &t, double &E, int src, bool ok) {
+    const double tp = __shfl(t, src, WAVE);
+    const double Ep = __shfl(E, src, WAVE);
+#pragma unroll
+    for (int c = 0; c < C::NCLS; ++c)
+#pragma unroll
+        for (int h = 0; h < C::NTH; ++h) {
+            double q[C::P];
+#pragma unroll
+            for (int m = 0; m < C::P; ++m) q[m] = __shfl(F.s[c][h][m], src, WAVE);
+            if (ok) madd(F.s[c][h], q, E, t);
+        }
+    if (ok) {
+        t += tp;
+        E *= Ep;
+    }
+}
+
+// Inclusive transfer-carrying scan of the run aggregates over the runs of
+// each segment group (Gr runs, a power of two; lig = the run's index in its
+// group), forward (DIR 0: over the runs before) or backward (over the runs
+// after).  With several columns per wave: Hillis-Steele over permutes.  With
+// one column per wave: Hillis-Steele within each row of 16 runs by DPP, then
+// the rows joined: for groups of 32 or 64 runs each odd row (forward; even,
+// backward) takes the total of its neighbour row, and for 64 runs the second
+// half (first half) takes the total of the other half.  Either way each run
+// ends with the sum over its group's runs up to it, moved to its anchor.
+template <class C, int DIR>
+__device__ __forceinline__ void lane_scan(State<C> &F, double &t, double &E, int lig, int Gr, int lane) {
+    if constexpr (C::WCOL == 1) {
+        const int pr = lane & 15, row = lane >> 4;
+        const int lim = Gr < 16 ? Gr : 16;
+        constexpr bool UP = DIR == 0;
+        if (lim > 1) scan_step_row<C, UP, 1>(F, t, E, UP ? (pr >= 1 && lig >= 1) : (pr + 1 < 16 && lig + 1 < Gr));
+        if (lim > 2) scan_step_row<C, UP, 2>(F, t, E, UP ? (pr >= 2 && lig >= 2) : (pr + 2 < 16 && lig + 2 < Gr));
+        if (lim > 4) scan_step_row<C, UP, 4>(F, t, E, UP ? (pr >= 4 && lig >= 4) : (pr + 4 < 16 && lig + 4 < Gr));
+        if (lim > 8) scan_step_row<C, UP, 8>(F, t, E, UP ? (pr >= 8 && lig >= 8) : (pr + 8 < 16 && lig + 8 < Gr));
+        if (Gr > 16) {
+            // rows in pairs: forward, an odd row takes the last run of the row before;
+            // backward, an even row takes the first run of the row after
+            const bool ok = UP ? (row & 1) == 1 : (row & 1) == 0;
+            scan_step_lane<C>(F, t, E, UP ? 16 * row - 1 : 16 * row + 16, ok);
+        }
+        if (Gr > 32) {
+            // halves: forward, rows 2-3 take run 31; backward, rows 0-1 take run 32
+            const bool ok = UP ? row >= 2 : row < 2;
+            scan_step_lane<C>(F, t, E, UP ? 31 : 32, ok);
+        }
+    } else {
+#pragma unroll 1
+        for (int o = 1; o < Gr; o <<= 1) {
+            const bool ok = DIR == 0 ? (lig >= o) : (lig + o < Gr);
+            scan_step<C, DIR == 0>(F, t, E, o, ok);
+        }
+    }
+}
+
+// The previous run's value in the scan direction (the same column's lane
+// WCOL lanes down for DIR 0, up for DIR 1).
+template <class C, int DIR>
+__device__ __forceinline__ double run_neighbour(double v) {
+    if constexpr (C::WCOL == 1) return dpp_move<DIR == 0 ? 0x138 : 0x130>(v);
+    else return DIR == 0 ? __shfl_up(v, C::WCOL, WAVE) : __shfl_down(v, C::WCOL, WAVE);
+}
+
 // Process element e of the lane's run in a scan step: move the state to the
 // element (or reset at a segment boundary), read the target value, add the
 // source.  Returns the target value.
@@ -838,7 +940,7 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
             // the previous run's anchor to this run's (none for a group's first run).
             double tr = 0.0, Er = 1.0;
             {
-                const double xo = DIR == 0 ? __shfl_up(xend, C::WCOL, WAVE) : __shfl_down(xend, C::WCOL, WAVE);
+                const double xo = run_neighbour<C, DIR>(xend);
                 const bool has = DIR == 0 ? (lig > 0) : (lig < Gr - 1);
                 if (has) {
                     tr = a * (DIR == 0 ? xend - xo : xo - xend);
@@ -847,19 +949,14 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                         if (cut_run) Er = 0.0;
                 }
             }
-#pragma unroll 1
-            for (int o = 1; o < Gr; o <<= 1) {
-                const bool ok = DIR == 0 ? (lig >= o) : (lig + o < Gr);
-                scan_step<C, DIR == 0>(F, tr, Er, o, ok);
-            }
+            lane_scan<C, DIR>(F, tr, Er, lig, Gr, (int)(threadIdx.x % WAVE));
             // exclusive value
             {
-                const int dl = C::WCOL;
-                const double xp = DIR == 0 ? __shfl_up(xend, dl, WAVE) : __shfl_down(xend, dl, WAVE);
+                const double xp = run_neighbour<C, DIR>(xend);
                 const bool has = DIR == 0 ? (lig > 0) : (lig < Gr - 1);
 #pragma unroll
                 for (int k = 0; k < C::NSLOT; ++k) {
-                    const double q = DIR == 0 ? __shfl_up(F.flat()[k], dl, WAVE) : __shfl_down(F.flat()[k], dl, WAVE);
+                    const double q = run_neighbour<C, DIR>(F.flat()[k]);
                     Ex.flat()[k] = has ? q : 0.0;
                 }
                 if (has) xex = xp;
