@@ -424,7 +424,7 @@ def bench_config3(dev, steps, rank, maxit):
                              "seconds": time.perf_counter() - t0}
             log("config 3 log det ~ %.6e (%d steps)" % (est, int(msteps.max())))
             y = torch.as_tensor(p.y, device=dev)
-            s1 = autotune.tune_schedule(plan, 1, reps=3)       # the single column's schedule
+            s1 = autotune.tune_schedule(plan, 1, reps=5)       # the single column's schedule
             out["cg_solve"] = c3_solve(mm, plan, y, rank, maxit, s1)
         plan.close()
     return out
@@ -565,6 +565,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup-seconds", type=float, default=1.0,
+                    help="keep warming up (untimed) until this much time has passed")
     ap.add_argument("--nrhs", type=int, default=32, help="right-hand sides of the headline product")
     ap.add_argument("--mvm-reps", type=int, default=21)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -640,10 +642,18 @@ def main():
     yy = torch.empty_like(vv)
     head_sched = autotune.tune_schedule(plan, R, vectors=vv)
     log("headline schedule (columns per wave, run length, stored run carries): %s" % (head_sched,))
-    for _ in range(args.warmup):
+    # untimed warm-up: the W steps, continued until the GPU has run the product for
+    # at least --warmup-seconds (its clocks settle; a schedule read from the tuning
+    # cache skips the tuning runs that otherwise warm it)
+    t0 = time.perf_counter()
+    done = 0
+    while done < args.warmup or time.perf_counter() - t0 < args.warmup_seconds:
         plan.mvm_raw(vv, yy, R)
+        done += 1
+        if done % 16 == 0:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
-    log("timed steps: %d" % args.steps)
+    log("warm-up: %d products in %.2f s; timed steps: %d" % (done, time.perf_counter() - t0, args.steps))
     plan.profile_enable(True)
     plan.profile_read(reset=True)
     torch.cuda.synchronize()

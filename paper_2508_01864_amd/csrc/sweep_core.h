@@ -659,11 +659,10 @@ __device__ __forceinline__ void scan_step(State<C> &F, double &t, double &E, int
     }
 }
 
-// One column per wave (lane = run): the lane scan's moves within rows of 16
-// lanes go through DPP instead of LDS permutes.  CTRL is a DPP row shift
-// (0x110 + n: from lane l - n, 0x100 + n: from lane l + n, within the row) or
-// a wave shift by one lane (0x138: from lane l - 1, 0x130: from lane l + 1);
-// lanes without a source read 0.
+// The lane scan's moves inside rows of 16 lanes go through DPP instead of LDS
+// permutes.  CTRL is a DPP row shift (0x110 + n: from lane l - n, 0x100 + n:
+// from lane l + n, within the row) or a wave shift by one lane (0x138: from
+// lane l - 1, 0x130: from lane l + 1); lanes without a source read 0.
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
@@ -672,11 +671,11 @@ __device__ __forceinline__ double dpp_move(double v) {
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
-// F <- F + M(E, t) F(partner) with the partner O lanes away inside the row
+// F <- F + M(E, t) F(partner) with the partner N lanes away inside the row
 // (as scan_step).
-template <class C, bool UP, int O>
+template <class C, bool UP, int N>
 __device__ __forceinline__ void scan_step_row(State<C> &F, double &t, double &E, bool ok) {
-    constexpr int CTRL = UP ? 0x110 + O : 0x100 + O;
+    constexpr int CTRL = UP ? 0x110 + N : 0x100 + N;
     const double tp = dpp_move<CTRL>(t);
     const double Ep = dpp_move<CTRL>(E);
 #pragma unroll
@@ -714,35 +713,50 @@ __device__ __forceinline__ void scan_step_lane(State<C> &F, double &t, double &E
     }
 }
 
+// One within-row step of the lane scan over runs O apart (O WCOL lanes).
+template <class C, int DIR, int O>
+__device__ __forceinline__ void row_step(State<C> &F, double &t, double &E, int lig, int Gr, int rr) {
+    constexpr int RR = 16 / C::WCOL;  // runs per row
+    if constexpr (O < RR) {
+        if (O < Gr) {
+            const bool ok = DIR == 0 ? (rr >= O && lig >= O) : (rr + O < RR && lig + O < Gr);
+            scan_step_row<C, DIR == 0, O * C::WCOL>(F, t, E, ok);
+        }
+    }
+}
+
 // Inclusive transfer-carrying scan of the run aggregates over the runs of
 // each segment group (Gr runs, a power of two; lig = the run's index in its
 // group), forward (DIR 0: over the runs before) or backward (over the runs
-// after).  With several columns per wave: Hillis-Steele over permutes.  With
-// one column per wave: Hillis-Steele within each row of 16 runs by DPP, then
-// the rows joined: for groups of 32 or 64 runs each odd row (forward; even,
-// backward) takes the total of its neighbour row, and for 64 runs the second
-// half (first half) takes the total of the other half.  Either way each run
-// ends with the sum over its group's runs up to it, moved to its anchor.
+// after); a run's lanes are its WCOL columns.  Up to 8 columns per wave:
+// Hillis-Steele inside each row of 16 lanes by DPP, then the rows joined --
+// for groups spanning two rows each odd row (forward; even, backward) takes
+// the total of its neighbour row's last (first) run, and for groups spanning
+// four rows the second half (first half) takes the total of the other half.
+// Wider waves (a run per row or more): Hillis-Steele over permutes.  Either
+// way each run ends with the sum over its group's runs up to it, moved to its
+// anchor.
 template <class C, int DIR>
 __device__ __forceinline__ void lane_scan(State<C> &F, double &t, double &E, int lig, int Gr, int lane) {
-    if constexpr (C::WCOL == 1) {
-        const int pr = lane & 15, row = lane >> 4;
-        const int lim = Gr < 16 ? Gr : 16;
+    if constexpr (C::WCOL <= 8) {
+        constexpr int RR = 16 / C::WCOL;
+        const int rr = (lane & 15) / C::WCOL, row = lane >> 4, cc = lane % C::WCOL;
+        row_step<C, DIR, 1>(F, t, E, lig, Gr, rr);
+        row_step<C, DIR, 2>(F, t, E, lig, Gr, rr);
+        row_step<C, DIR, 4>(F, t, E, lig, Gr, rr);
+        row_step<C, DIR, 8>(F, t, E, lig, Gr, rr);
         constexpr bool UP = DIR == 0;
-        if (lim > 1) scan_step_row<C, UP, 1>(F, t, E, UP ? (pr >= 1 && lig >= 1) : (pr + 1 < 16 && lig + 1 < Gr));
-        if (lim > 2) scan_step_row<C, UP, 2>(F, t, E, UP ? (pr >= 2 && lig >= 2) : (pr + 2 < 16 && lig + 2 < Gr));
-        if (lim > 4) scan_step_row<C, UP, 4>(F, t, E, UP ? (pr >= 4 && lig >= 4) : (pr + 4 < 16 && lig + 4 < Gr));
-        if (lim > 8) scan_step_row<C, UP, 8>(F, t, E, UP ? (pr >= 8 && lig >= 8) : (pr + 8 < 16 && lig + 8 < Gr));
-        if (Gr > 16) {
+        if (Gr > RR) {
             // rows in pairs: forward, an odd row takes the last run of the row before;
             // backward, an even row takes the first run of the row after
             const bool ok = UP ? (row & 1) == 1 : (row & 1) == 0;
-            scan_step_lane<C>(F, t, E, UP ? 16 * row - 1 : 16 * row + 16, ok);
+            scan_step_lane<C>(F, t, E, UP ? 16 * row - C::WCOL + cc : 16 * row + 16 + cc, ok);
         }
-        if (Gr > 32) {
-            // halves: forward, rows 2-3 take run 31; backward, rows 0-1 take run 32
+        if (Gr > 2 * RR) {
+            // halves: forward, rows 2-3 take the last run of row 1; backward, rows
+            // 0-1 take the first run of row 2
             const bool ok = UP ? row >= 2 : row < 2;
-            scan_step_lane<C>(F, t, E, UP ? 31 : 32, ok);
+            scan_step_lane<C>(F, t, E, UP ? 32 - C::WCOL + cc : 32 + cc, ok);
         }
     } else {
 #pragma unroll 1
