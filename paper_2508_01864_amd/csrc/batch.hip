@@ -124,9 +124,18 @@ struct mm_mvm_batch_s {
 
 namespace {
 
-void mvm_batch_release(mm_mvm_batch b) {
-    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+// Release the executable graph once its last launch (on the batch's private
+// stream) has finished: a graph whose branches run side by side owns the
+// streams they run on, so it must not go while it executes.
+void drop_graph(mm_mvm_batch b) {
+    if (!b->graph) return;
+    if (b->bs) (void)hipStreamSynchronize(b->bs);
+    (void)hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
+}
+
+void mvm_batch_release(mm_mvm_batch b) {
+    drop_graph(b);
     sweep_batch_free(b->sweep);
     dev_free(b->work);
     dev_free(b->desc);
@@ -255,8 +264,7 @@ mm_status mm_mvm_batch_set_schedule(mm_mvm_batch batch, int32_t sweep_wg_per_cu,
     }
     batch->sweep.grid_per_cu = sweep_wg_per_cu;
     batch->grid_cap = grid;
-    if (batch->graph) (void)hipGraphExecDestroy(batch->graph);
-    batch->graph = nullptr;
+    drop_graph(batch);
     return MM_OK;
 }
 
@@ -284,10 +292,7 @@ mm_status mm_mvm_batch_run(mm_mvm_batch b, const double *const *v, const int64_t
     for (size_t k = 0; k < count; ++k) b->io_host[k] = MvmIo{v[k], y[k], ldv[k], ldy[k]};
     MM_HIP_TRY(hipMemcpyAsync(b->io_dev.ptr, b->io_host, count * sizeof(MvmIo), hipMemcpyHostToDevice, s));
     MM_HIP_TRY(hipEventRecord(b->io_done, s));
-    if (diag_shift != b->shift && b->graph) {
-        (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
-    }
+    if (diag_shift != b->shift) drop_graph(b);
     b->shift = diag_shift;
     if (!b->use_graph) return mvm_batch_enqueue(b, s);
     if (!b->bs) {

@@ -916,9 +916,18 @@ mm_status batch_build(mm_solver_batch b) {
     return MM_OK;
 }
 
-void batch_free(mm_solver_batch b) {
-    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+// Release a batch's executable graph once its last launch (on the batch's
+// private stream) has finished: a graph whose branches run side by side owns
+// the streams they run on, so it must not go while it executes.
+void drop_graph(mm_solver_batch b) {
+    if (!b->graph) return;
+    if (b->bs) (void)hipStreamSynchronize(b->bs);
+    (void)hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
+}
+
+void batch_free(mm_solver_batch b) {
+    drop_graph(b);
     for (SweepBatch &sb : b->sweeps) sweep_batch_free(sb);
     b->sweeps.clear();
     dev_free(b->cg_desc);
@@ -947,8 +956,7 @@ mm_status solver_batch_iterate(mm_solver_batch b, int iters, hipStream_t user) {
             MM_HIP_TRY(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
         }
         if (!b->graph || b->graph_iters != iters) {
-            if (b->graph) (void)hipGraphExecDestroy(b->graph);
-            b->graph = nullptr;
+            drop_graph(b);
             hipGraph_t g = nullptr;
             MM_HIP_TRY(hipStreamBeginCapture(b->bs, hipStreamCaptureModeThreadLocal));
             mm_status st = batch_enqueue(b, iters, b->bs);
@@ -1695,8 +1703,7 @@ mm_status mm_solver_batch_set_schedule(mm_solver_batch batch, int32_t sweep_wg_p
     batch->wg_per_cu = sweep_wg_per_cu;
     for (SweepBatch &sb : batch->sweeps) sb.grid_per_cu = sweep_wg_per_cu;
     batch->grid_cap = cg_grid;
-    if (batch->graph) (void)hipGraphExecDestroy(batch->graph);
-    batch->graph = nullptr;
+    drop_graph(batch);
     return MM_OK;
 }
 
