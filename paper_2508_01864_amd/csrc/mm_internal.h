@@ -197,11 +197,6 @@ struct SweepBatch {
     int W = 1, WB = 1;
     int grid_per_cu = 16;  // persistent grid: workgroups per compute unit (tuned)
     bool skip_accum = false;  // leave the per-pass partials unsummed (the consumer sums them)
-    // With several kernel classes, each class's launches run on a stream of its
-    // own (default priority), forked from and joined back into the caller's
-    // stream, so that independent classes overlap (also inside a captured graph).
-    std::vector<hipStream_t> cls_streams;
-    std::vector<hipEvent_t> cls_events;  // [0]: fork, [1 + k]: class k done
 };
 mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB, SweepBatch &out);
 mm_status sweep_batch_run(SweepBatch &b, hipStream_t s);

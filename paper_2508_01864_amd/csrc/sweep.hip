@@ -198,24 +198,6 @@ inline unsigned persist_grid(int nitems, int per_cu) {
 }
 }  // namespace
 
-namespace {
-// streams and events for running the classes side by side (created once per batch)
-mm_status class_streams(SweepBatch &b) {
-    const size_t nc = b.classes.size();
-    while (b.cls_streams.size() < nc) {
-        hipStream_t cs = nullptr;
-        MM_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        b.cls_streams.push_back(cs);
-    }
-    while (b.cls_events.size() < nc + 1) {
-        hipEvent_t e = nullptr;
-        MM_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        b.cls_events.push_back(e);
-    }
-    return MM_OK;
-}
-}  // namespace
-
 mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB, SweepBatch &out) {
     sweep_batch_free(out);
     out.W = W;
@@ -297,42 +279,30 @@ mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB,
             return MM_OK;
         }));
     }
-    if (out.classes.size() > 1) MM_TRY(class_streams(out));
     return MM_OK;
 }
 
 mm_status sweep_batch_run(SweepBatch &b, hipStream_t s) {
-    const bool fork = b.classes.size() > 1 && b.cls_streams.size() >= b.classes.size();
-    if (fork) MM_HIP_TRY(hipEventRecord(b.cls_events[0], s));
-    for (size_t k = 0; k < b.classes.size(); ++k) {
-        auto &cl = b.classes[k];
-        hipStream_t cs = s;
-        if (fork) {
-            cs = b.cls_streams[k];
-            MM_HIP_TRY(hipStreamWaitEvent(cs, b.cls_events[0], 0));
-        }
+    for (auto &cl : b.classes) {
         MM_TRY(with_cfg(cl.d, cl.kp, cl.sc, b.W, [&](auto t) {
             using C = typename decltype(t)::type;
             const SweepArgs *descs = static_cast<const SweepArgs *>(cl.descs.ptr);
             if (cl.n_agg > 0)
                 hipLaunchKernelGGL((sweep_batch_kernel<C, 1>), dim3(persist_grid(cl.n_agg, b.grid_per_cu)), dim3(C::BLOCK), 0,
-                                   cs, descs, static_cast<const int4 *>(cl.items_agg.ptr), cl.n_agg);
+                                   s, descs, static_cast<const int4 *>(cl.items_agg.ptr), cl.n_agg);
             if (cl.n_carry > 0)
                 hipLaunchKernelGGL((carry_batch_kernel<C>), dim3(persist_grid(cl.n_carry, b.grid_per_cu)), dim3(256),
-                                   0, cs, descs, static_cast<const int4 *>(cl.items_carry.ptr), cl.n_carry);
+                                   0, s, descs, static_cast<const int4 *>(cl.items_carry.ptr), cl.n_carry);
             if (cl.n_main > 0) {
                 hipEvent_t ev1 = nullptr;
                 if (b.plans.size() == 1) MM_TRY(profile_begin(b.plans[0], (int)b.plans[0]->passes.size(), s, &ev1));
                 hipLaunchKernelGGL((sweep_batch_kernel<C, 0>), dim3(persist_grid(cl.n_main, b.grid_per_cu)), dim3(C::BLOCK),
-                                   0, cs, descs, static_cast<const int4 *>(cl.items_main.ptr), cl.n_main);
+                                   0, s, descs, static_cast<const int4 *>(cl.items_main.ptr), cl.n_main);
                 if (ev1) MM_HIP_TRY(hipEventRecord(ev1, s));
             }
             return MM_OK;
         }));
-        if (fork) MM_HIP_TRY(hipEventRecord(b.cls_events[1 + k], cs));
     }
-    if (fork)
-        for (size_t k = 0; k < b.classes.size(); ++k) MM_HIP_TRY(hipStreamWaitEvent(s, b.cls_events[1 + k], 0));
     if (b.n_acc > 0 && !b.skip_accum)
         hipLaunchKernelGGL(accum_batch_kernel, dim3(persist_grid(b.n_acc, 16)), dim3(256), 0, s,
                            static_cast<const AccumDesc *>(b.acc_desc.ptr), static_cast<const int2 *>(b.acc_items.ptr),
@@ -350,13 +320,6 @@ void sweep_batch_free(SweepBatch &b) {
     }
     b.classes.clear();
     b.plans.clear();
-    for (hipStream_t cs : b.cls_streams) {
-        (void)hipStreamSynchronize(cs);
-        (void)hipStreamDestroy(cs);
-    }
-    for (hipEvent_t e : b.cls_events) (void)hipEventDestroy(e);
-    b.cls_streams.clear();
-    b.cls_events.clear();
     dev_free(b.acc_desc);
     dev_free(b.acc_items);
     b.n_acc = 0;

@@ -179,3 +179,25 @@ def test_config3_full_size_sampled(oracle_lib):
         comp, nrm = run_case(p.x, p.probes, 5, form, 0.3, rows=rows)
         say("config3", form, comp, nrm)
         assert comp <= MVM_TOL and nrm <= MVM_TOL
+
+
+@pytest.mark.parametrize("nrhs", [100, 256])
+@pytest.mark.parametrize("d,two_nu", [(2, 3), (3, 5)])
+def test_widest_products(oracle_lib, nrhs, d, two_nu):
+    """The widest products: 100 columns (padded to 128, four 32-column blocks) and the
+    limit of 256; 1500 points, several tiles; oracle on 60 sampled rows."""
+    p = workloads.random_problem(700 + nrhs + d, 1500, d, two_nu, "product", 0.15, nrhs=nrhs)
+    rows = np.random.default_rng(701 + nrhs).choice(1500, 60, replace=False)
+    say("widest product nrhs=%d d=%d nu=%d/2" % (nrhs, d, two_nu))
+    comp, nrm = run_case(p.x, p.v, two_nu, "product", 0.15, rows=rows, shift=0.02)
+    say("  comp %.2e nrm %.2e" % (comp, nrm))
+    assert comp <= MVM_TOL and nrm <= MVM_TOL
+
+
+def test_width_beyond_the_limit_is_refused(oracle_lib):
+    p = workloads.random_problem(799, 200, 2, 3, "product", 0.2, nrhs=257)
+    plan = mm.Plan(to_gpu(p.x), mm.Kernel(3, "product", 0.2))
+    with pytest.raises(mm.MaternError) as e:
+        plan.mvm(to_gpu(p.v))
+    assert e.value.status == mm.MM_ERR_ARG
+    plan.close()

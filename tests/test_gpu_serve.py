@@ -46,6 +46,19 @@ def _alone(r):
     return out
 
 
+def test_side_stream_admission_changes_nothing(oracle_lib):
+    """Admissions built on the server's side stream while a chunk runs give the same
+    bits as admissions built on the caller's stream between chunks."""
+    reqs = _requests(15, 6, 300, 3000, 0.001)
+    a = serve.Server(max_slots=4, chunk=8, side_stream=True).run(reqs)
+    b = serve.Server(max_slots=4, chunk=8, side_stream=False).run(reqs)
+    assert len(a) == len(b) == len(reqs)
+    for ra, rb in zip(a, b):
+        assert np.array_equal(to_np(ra.alpha), to_np(rb.alpha))
+        assert np.array_equal(to_np(ra.mean), to_np(rb.mean))
+        assert np.array_equal(ra.beta, rb.beta)
+
+
 def test_served_equals_alone_with_admission_and_overlap(oracle_lib):
     reqs = _requests(5, 10, 300, 4000, 0.002)
     sizes = [serve.request_bytes(len(r.y), r.x.shape[1], len(r.z), r.kernel) for r in reqs]
