@@ -416,8 +416,9 @@ mm_status mm_solver_batch_create(mm_solver *solvers, int32_t count, int32_t use_
                                  mm_solver_batch *out);
 
 /* Launch schedule of a batch: workgroups per compute unit of the persistent
- * sweep grids (>= 1) and the grid of the vector-update kernels (>= 1).
- * Results do not depend on it. */
+ * carry-scan grids (>= 1; the sweep launches run one workgroup per work item)
+ * and the grid of the vector-update kernels (>= 1).  Results do not depend
+ * on it. */
 mm_status mm_solver_batch_set_schedule(mm_solver_batch batch, int32_t sweep_wg_per_cu,
                                        int32_t cg_grid);
 
@@ -549,9 +550,9 @@ typedef struct mm_mvm_batch_s *mm_mvm_batch;
 mm_status mm_mvm_batch_create(const mm_plan *plans, int32_t count, int32_t nrhs, int32_t use_graph,
                               mm_mvm_batch *out);
 
-/* Launch schedule: workgroups per compute unit of the persistent sweep grids
- * and the grid of the gather/scatter kernels (both >= 1; results do not
- * depend on them). */
+/* Launch schedule: workgroups per compute unit of the persistent carry-scan
+ * grids (the sweep launches run one workgroup per work item) and the grid of
+ * the gather/scatter kernels (both >= 1; results do not depend on them). */
 mm_status mm_mvm_batch_set_schedule(mm_mvm_batch batch, int32_t sweep_wg_per_cu, int32_t grid);
 
 /* Run the batch.  v, y: host arrays of count device pointers (n_k x nrhs

@@ -1,8 +1,9 @@
 """Launch-schedule autotuner for batched products and solver batches.
 
 A batch runs persistent grids whose size is a free parameter: the workgroups
-per compute unit of the sweep launches and the grid of the vector-update (or
-gather/scatter) launches.  Results never depend on them (every work item runs
+per compute unit of the carry-scan launches and the grid of the vector-update
+(or gather/scatter) launches.  (The sweep launches run one workgroup per work
+item and take no grid parameter.)  Results never depend on them (every work item runs
 the same arithmetic), so tuning only changes speed.  The tuner times each
 candidate with HIP events on the caller's stream, keeps the fastest, and
 caches the choice in a JSON file keyed by the batch's shape (its kernel
@@ -19,7 +20,7 @@ import os
 from typing import Callable, Dict, Iterable, List, Sequence, Tuple
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SWEEP_WG_PER_CU = (1, 2, 4, 8, 16, 24, 32)
+SWEEP_WG_PER_CU = (1, 4, 16)
 SIDE_GRID = (512, 2048, 8192)
 DEFAULT = (16, 2048)
 
@@ -79,10 +80,10 @@ def _time(step: Callable[[], None], reps: int) -> float:
 def tune(batch, key: str, step: Callable[[], None], reps: int = 2,
          sweep_candidates: Sequence[int] = SWEEP_WG_PER_CU,
          side_candidates: Sequence[int] = SIDE_GRID, use_cache: bool = True) -> Tuple[int, int]:
-    """Pick (sweep workgroups per CU, side grid) for ``batch`` (an MvmBatch or
-    SolverBatch: anything with ``set_schedule``) by timing ``step`` (one or a
-    few batch launches).  The sweep parameter is tuned first with the default
-    side grid, then the side grid with the chosen sweep parameter."""
+    """Pick (carry-scan workgroups per CU, side grid) for ``batch`` (an
+    MvmBatch or SolverBatch: anything with ``set_schedule``) by timing ``step``
+    (one or a few batch launches).  The carry parameter is tuned first with the
+    default side grid, then the side grid with the chosen carry parameter."""
     if use_cache:
         hit = _load().get(key)
         if hit:

@@ -195,7 +195,7 @@ struct SweepBatch {
     DevBuf acc_desc, acc_items;
     int n_acc = 0;
     int W = 1, WB = 1;
-    int grid_per_cu = 16;  // persistent grid: workgroups per compute unit (tuned)
+    int grid_per_cu = 16;  // persistent carry-scan grid: workgroups per compute unit (tuned)
     bool skip_accum = false;  // leave the per-pass partials unsummed (the consumer sums them)
 };
 mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB, SweepBatch &out);

@@ -269,6 +269,10 @@ mm_status sweep_batch_build(const std::vector<BatchEntry> &probs, int W, int WB,
                 for (int64_t bx = 0; bx < (int64_t)npass * A.ntile; ++bx)
                     for (int by = 0; by < ncb; ++by) im.push_back(make_int4((int)m, (int)bx, by, 0));
             }
+            if (ia.size() > (size_t)INT32_MAX || ic.size() > (size_t)INT32_MAX || im.size() > (size_t)INT32_MAX) {
+                set_error("batched product: more than 2^31-1 work items in one kernel class");
+                return MM_ERR_ARG;
+            }
             MM_TRY(upload(cl.descs, descs));
             MM_TRY(upload(cl.items_agg, ia));
             MM_TRY(upload(cl.items_carry, ic));
@@ -288,7 +292,7 @@ mm_status sweep_batch_run(SweepBatch &b, hipStream_t s) {
             using C = typename decltype(t)::type;
             const SweepArgs *descs = static_cast<const SweepArgs *>(cl.descs.ptr);
             if (cl.n_agg > 0)
-                hipLaunchKernelGGL((sweep_batch_kernel<C, 1>), dim3(persist_grid(cl.n_agg, b.grid_per_cu)), dim3(C::BLOCK), 0,
+                hipLaunchKernelGGL((sweep_batch_kernel<C, 1>), dim3(cl.n_agg), dim3(C::BLOCK), 0,
                                    s, descs, static_cast<const int4 *>(cl.items_agg.ptr), cl.n_agg);
             if (cl.n_carry > 0)
                 hipLaunchKernelGGL((carry_batch_kernel<C>), dim3(persist_grid(cl.n_carry, b.grid_per_cu)), dim3(256),
@@ -296,7 +300,7 @@ mm_status sweep_batch_run(SweepBatch &b, hipStream_t s) {
             if (cl.n_main > 0) {
                 hipEvent_t ev1 = nullptr;
                 if (b.plans.size() == 1) MM_TRY(profile_begin(b.plans[0], (int)b.plans[0]->passes.size(), s, &ev1));
-                hipLaunchKernelGGL((sweep_batch_kernel<C, 0>), dim3(persist_grid(cl.n_main, b.grid_per_cu)), dim3(C::BLOCK),
+                hipLaunchKernelGGL((sweep_batch_kernel<C, 0>), dim3(cl.n_main), dim3(C::BLOCK),
                                    0, s, descs, static_cast<const int4 *>(cl.items_main.ptr), cl.n_main);
                 if (ev1) MM_HIP_TRY(hipEventRecord(ev1, s));
             }
