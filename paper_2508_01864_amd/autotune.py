@@ -148,7 +148,7 @@ def schedule_candidates(d: int, two_nu: int, form: str, width: int) -> List[Tupl
     for wb, e in pairs:
         if width % wb:
             continue
-        stores = d <= 2 and width < 32 and wb >= 2 and e <= 32   # the pre-pass can store run carries
+        stores = d <= 2 and wb >= 2 and e <= 32   # the pre-pass can store run carries
         for rx in ((1, 0) if stores else (1,)):
             out.append((wb, e, rx))
     return out
@@ -156,10 +156,10 @@ def schedule_candidates(d: int, two_nu: int, form: str, width: int) -> List[Tupl
 
 def stores_run_carries(d: int, width: int, wb: int, e: int, runex) -> bool:
     """Whether a product at padded width `width` on schedule (wb, e, runex)
-    stores the runs' within-tile carries in its pre-pass: d <= 2, fewer than
-    32 columns, at least 2 columns per wave and runs of 8 to 32 (the lane keeps
-    its run's sums in registers)."""
-    return bool(runex) and d <= 2 and width < 32 and wb >= 2 and 4 < e <= 32
+    stores the runs' within-tile carries in its pre-pass: d <= 2, at least 2
+    columns per wave and runs of 8 to 32 (the lane keeps its run's sums in
+    registers)."""
+    return bool(runex) and d <= 2 and wb >= 2 and 4 < e <= 32
 
 
 def schedule_key(n: int, d: int, two_nu: int, form: str, width: int) -> str:

@@ -56,14 +56,15 @@ int agg_per_rhs(int d, const mm_kernel &k, bool der) {
 
 // Aggregates and carries: agg_per_rhs doubles per tile and right-hand side,
 // two directions, per pass of a group; anchors and decays 2 each per tile and
-// pass.  The smallest tile (128 positions) gives the most tiles.  For d <= 2
-// below 32 columns, also the runs' within-tile carries of the cross-tile
-// passes: agg_per_rhs doubles per lane, two directions, per tile of at least
-// 256 positions and block of at least two columns (32 lanes per column).
+// pass.  The smallest tile (128 positions) gives the most tiles.  For d <= 2,
+// also the runs' within-tile carries of the cross-tile passes: agg_per_rhs
+// doubles per lane, two directions, per run of at least 8 positions -- at most
+// 32 lanes per column per 256 positions.  (The slab budget caps G n W, so this
+// stays below agg_per_rhs / 4 GiB at any width.)
 static size_t agg_bytes_for(int64_t n, int d, int W, int64_t G, int per_rhs) {
     const int64_t ntile = (n + 127) / 128;
     size_t dbl = (size_t)(2 * (2 * G * ntile * (int64_t)W * per_rhs) + 4 * G * ntile + 16);
-    if (d <= 2 && W < 32) dbl += (size_t)2 * G * ((n + 255) / 256) * 32 * W * per_rhs;
+    if (d <= 2) dbl += (size_t)2 * G * ((n + 255) / 256) * 32 * W * per_rhs;
     return dbl * sizeof(double);
 }
 

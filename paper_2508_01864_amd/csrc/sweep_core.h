@@ -193,7 +193,8 @@ struct SweepArgs {
     const int4 *segs;      // the plan's cross-tile segments (pass, first tile, end tile)
     const int32_t *xtpos;  // each pass's position in xt (-1: its segments fit in a tile)
     double *runex;         // the runs' within-tile carries of the cross-tile passes (Cfg::RUNEX; null
-                           //   when the workspace has no room: below d = 3 and 32 columns it has):
+                           //   in d = 3, whose workspace has no room for them, or when the schedule
+                           //   declines them):
                            //   [2 dirs][xt pass of the group][ntile][column block][NSUB][NSLOT][lane]
     double a;
 };
@@ -1562,7 +1563,7 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
     A.car = A.agg + aggslab;
     A.anc = A.car + aggslab;
     A.dec = A.anc + (size_t)2 * gmax * ntile;
-    A.runex = (p->d <= 2 && W < 32 && runex) ? A.dec + (size_t)2 * gmax * ntile : nullptr;  // see agg_bytes_for
+    A.runex = (p->d <= 2 && runex) ? A.dec + (size_t)2 * gmax * ntile : nullptr;  // see agg_bytes_for
     A.xtpos = static_cast<const int32_t *>(p->pass_xtpos[ti].ptr);
     for (int g0 = 0; g0 < npass; g0 += gmax) {
         const int G = npass - g0 < gmax ? npass - g0 : gmax;
@@ -1703,7 +1704,7 @@ SweepArgs make_args(mm_plan p, const double *vin, double *agg, double *part, int
     A.car = A.agg + aggslab;
     A.anc = A.car + aggslab;
     A.dec = A.anc + (size_t)2 * gmax * ntile;
-    A.runex = (p->d <= 2 && W < 32 && runex) ? A.dec + (size_t)2 * gmax * ntile : nullptr;  // see agg_bytes_for
+    A.runex = (p->d <= 2 && runex) ? A.dec + (size_t)2 * gmax * ntile : nullptr;  // see agg_bytes_for
     A.xtpos = static_cast<const int32_t *>(p->pass_xtpos[ti].ptr);
     A.nslice = C::NSUB * C::NCLS * C::NTH * W;
     A.segs = static_cast<const int4 *>(p->seg_tab[ti].ptr);

@@ -98,9 +98,9 @@ def test_gaussian_points_l1_and_product(oracle_lib, d):
                                            (2, 3, "l1")])
 def test_stored_run_carry_widths(oracle_lib, nrhs, d, two_nu, form):
     """Column counts on both sides of the stored within-tile run carries (d <= 2):
-    2 and 5 columns (blocks of 2 and 4, tiles of 256) and 12 (tiles of 512 in d = 2) use
-    them; 31 pads to 32 columns in blocks of 4 and sweeps without them.  3001
-    points: 12 or 6 tiles and several passes whose segments span tiles."""
+    2 and 5 columns (blocks of 2 and 4, tiles of 256), 12 (tiles of 512 in d = 2) and 31
+    (padded to 32 columns in blocks of 4) use them.  3001 points: 12 or 6 tiles and
+    several passes whose segments span tiles."""
     p = workloads.random_problem(600 + nrhs + 10 * d + two_nu, 3001, d, two_nu, form, 0.1, nrhs=nrhs)
     say("stored run carries: nrhs=%d d=%d nu=%d/2 %s" % (nrhs, d, two_nu, form))
     comp, nrm = run_case(p.x, p.v, two_nu, form, 0.1)
