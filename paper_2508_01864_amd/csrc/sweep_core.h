@@ -269,6 +269,13 @@ struct Cfg {
     // the state spills (d = 3).  Long runs take blocks of 4 in d <= 2 (8 lifts
     // the d = 2 kernels past 128 registers) and of 8 in d = 3.
     static constexpr int BLK = E <= 8 ? E / 2 : (D <= 2 ? 4 : 8);
+    // blocks per iteration of the main scan's block loop when the run's sums
+    // stay in registers: unrolling lets consecutive turns of the sums' ring
+    // (see run_direction) become renames instead of moves.  Runs of 32 in
+    // waves of 8 or more columns take 4 (two iterations: a fully unrolled run
+    // hoists every gather and spills); with fewer columns per wave the
+    // unrolled loop needs more registers than it saves moves.
+    static constexpr int OUTU = (OUTREG && E == 32 && WCOL >= 8 && E / BLK >= 8) ? 4 : 1;
 };
 
 template <class C>
@@ -1094,7 +1101,7 @@ __device__ __forceinline__ void run_direction(const SweepArgs &A, const PassDev 
                     for (int i = 0; i < C::E; ++i) outv[i] = r[i];
                 }
             };
-#pragma unroll 1
+#pragma unroll C::OUTU
             for (int b = 0; b < C::E; b += C::BLK) block(b);
         }
     }
