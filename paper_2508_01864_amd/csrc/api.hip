@@ -83,6 +83,21 @@ __global__ void gather_caller_kernel(const double *v, int64_t ldv, int nrhs, con
     }
 }
 
+// acc + the G slabs' entries at q, added in pass order; the loads go out 8
+// at a time ahead of their additions.
+__device__ __forceinline__ double slab_sum(const double *part, int G, int64_t len, int64_t q, double acc) {
+    int g = 0;
+    for (; g + 8 <= G; g += 8) {
+        double t[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t[k] = part[(int64_t)(g + k) * len + q];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += t[k];
+    }
+    for (; g < G; ++g) acc += part[(int64_t)g * len + q];
+    return acc;
+}
+
 // y[r * ldy + i] = s2 (vin[c, r] + sum_g part_g[c, r]) + shift vin[c, r] with
 // c = iperm[i]; the pass slabs are added in pass order (after yacc when not
 // first).  Threads take (caller point i, column r) with r fastest: reads are
@@ -99,8 +114,7 @@ __global__ void finish_caller_kernel(const double *vin, const double *part, int 
         const int r = (int)(e - i * w);
         if (r >= nrhs) continue;
         const int64_t q = (int64_t)iperm[i] * W + r;
-        double acc = first ? 0.0 : yacc[q];
-        for (int g = 0; g < G; ++g) acc += part[(int64_t)g * len + q];
+        const double acc = slab_sum(part, G, len, q, first ? 0.0 : yacc[q]);
         const double vv = vin[q];
         y[(int64_t)r * ldy + i] = fma(shift, vv, s2 * (vv + acc));
     }
@@ -119,8 +133,7 @@ __global__ void finish_canon_kernel(const double *vin, const double *part, int G
         const I c = q / w;
         const int r = (int)(q - c * w);
         if (r >= nrhs) continue;
-        double acc = first ? 0.0 : yacc[q];
-        for (int g = 0; g < G; ++g) acc += part[(int64_t)g * len + q];
+        const double acc = slab_sum(part, G, len, (int64_t)q, first ? 0.0 : yacc[q]);
         const double vv = vin[q];
         y[(int64_t)r * ldy + perm[c]] = fma(shift, vv, s2 * (vv + acc));
     }
@@ -220,6 +233,7 @@ void plan_free(mm_plan plan) {
     for (auto &b : plan->pass_xt) dev_free(b);
     for (auto &b : plan->pass_xtpos) dev_free(b);
     for (auto &b : plan->seg_tab) dev_free(b);
+    for (auto &b : plan->seg_big) dev_free(b);
     for (auto &e : plan->prof_events) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);

@@ -120,6 +120,9 @@ struct mm_plan_s {
     mm::DevBuf seg_tab[NTS];        // per tile size: (pass, first tile, end tile) of those segments
     std::vector<int> seg_off[NTS];  //   offset of each cross-tile pass's first segment
     std::vector<int4> seg_host[NTS];  // host copy of seg_tab
+    mm::DevBuf seg_big[NTS];        // per tile size: indices into seg_tab of the segments of more
+                                    //   than CARRY_SMALL tiles (the carry scan's wave-per-slice path)
+    std::vector<int> big_off[NTS];  //   offset of each cross-tile pass's first such segment
 
     // scan schedules chosen for particular widths (mm_plan_set_schedule; others: the default)
     std::vector<std::pair<int, mm::Sched>> sched;

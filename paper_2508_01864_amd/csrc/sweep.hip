@@ -136,6 +136,20 @@ mm_status upload_pass_tables(mm_plan p) {
             MM_TRY(dev_alloc(p->seg_tab[ti], tab4.size() * sizeof(int4)));
             MM_HIP_TRY(hipMemcpy(p->seg_tab[ti].ptr, tab4.data(), tab4.size() * sizeof(int4), hipMemcpyHostToDevice));
         }
+        // the segments the carry scan gives a wave per slice (more than CARRY_SMALL
+        // tiles), listed apart so that a product's carry launch sizes each kind's blocks
+        std::vector<int32_t> big;
+        p->big_off[ti].clear();
+        for (size_t k = 0; k + 1 < p->seg_off[ti].size(); ++k) {
+            p->big_off[ti].push_back((int)big.size());
+            for (int sg = p->seg_off[ti][k]; sg < p->seg_off[ti][k + 1]; ++sg)
+                if (tab4[sg].z - tab4[sg].y > CARRY_SMALL) big.push_back(sg);
+        }
+        p->big_off[ti].push_back((int)big.size());
+        if (!big.empty()) {
+            MM_TRY(dev_alloc(p->seg_big[ti], big.size() * sizeof(int32_t)));
+            MM_HIP_TRY(hipMemcpy(p->seg_big[ti].ptr, big.data(), big.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        }
     }
     return MM_OK;
 }

@@ -1453,9 +1453,25 @@ __device__ __forceinline__ void carry_body(const SweepArgs &A, int64_t bx, int b
     }
 }
 
+// A product's carry scans over a group's cross-tile segments (A.segs: the
+// group's first): blocks [0, nsmall) give each segment ysmall slice groups of
+// 256 threads and serve the segments of at most CARRY_SMALL tiles (the others
+// return); the next blocks give the wider segments, listed in `big` (indices
+// into the plan's table, first s0), ybig slice groups of 4 waves each.
 template <class C>
-__global__ __launch_bounds__(256) void carry_kernel(SweepArgs A) {
-    carry_body<C>(A, blockIdx.x, blockIdx.y);
+__global__ __launch_bounds__(256) void carry_kernel(SweepArgs A, int64_t nsmall, int ysmall, int ybig,
+                                                    const int32_t *big, int s0) {
+    const int64_t b = blockIdx.x;
+    if (b < nsmall) {
+        const int64_t sg = b / ysmall;
+        const int4 g = A.segs[sg];
+        if (g.z - g.y > CARRY_SMALL) return;
+        carry_body<C>(A, sg, (int)(b - sg * ysmall));
+    } else {
+        const int64_t j = b - nsmall;
+        const int64_t k = j / ybig;
+        carry_body<C>(A, (int64_t)gld(big + k) - s0, (int)(j - k * ybig));
+    }
 }
 
 // Batched carry scans: items (problem, segment, slice group).
@@ -1591,9 +1607,20 @@ mm_status run_passes(mm_plan p, const double *vin, double *yacc, int W, hipStrea
             const int nslice = C::NSUB * C::NCLS * C::NTH * W;
             A.nslice = nslice;
             A.segs = static_cast<const int4 *>(p->seg_tab[ti].ptr) + s0;
-            if (s1 > s0)
-                hipLaunchKernelGGL((carry_kernel<C>), dim3((unsigned)(s1 - s0), (unsigned)((2 * nslice + 3) / 4)),
-                                   dim3(256), 0, s, A);
+            if (s1 > s0) {
+                const std::vector<int> &bo = p->big_off[ti];
+                const int b0 = bo[k0], b1 = bo[k1];
+                const int ysmall = (2 * nslice + 255) / 256, ybig = (2 * nslice + 3) / 4;
+                const int64_t nsmall = (int64_t)(s1 - s0) * ysmall;
+                const int64_t nblk = nsmall + (int64_t)(b1 - b0) * ybig;
+                const int32_t *big = static_cast<const int32_t *>(p->seg_big[ti].ptr);
+                if (nblk > INT32_MAX) {
+                    set_error("carry scan: %lld blocks exceed the grid limit", (long long)nblk);
+                    return MM_ERR_ARG;
+                }
+                hipLaunchKernelGGL((carry_kernel<C>), dim3((unsigned)nblk), dim3(256), 0, s, A, nsmall, ysmall, ybig,
+                                   big ? big + b0 : nullptr, s0);
+            }
         }
         hipEvent_t ev1 = nullptr;
         if (!ws) MM_TRY(profile_begin(p, G, s, &ev1));  // (profiling creates events: not with a caller workspace)
