@@ -273,9 +273,11 @@ struct Cfg {
     // stay in registers: unrolling lets consecutive turns of the sums' ring
     // (see run_direction) become renames instead of moves.  Runs of 32 in
     // waves of 8 or more columns take 4 (two iterations: a fully unrolled run
-    // hoists every gather and spills); with fewer columns per wave the
-    // unrolled loop needs more registers than it saves moves.
-    static constexpr int OUTU = (OUTREG && E == 32 && WCOL >= 8 && E / BLK >= 8) ? 4 : 1;
+    // hoists every gather and spills); runs of 16 in d = 2 waves of 4 columns
+    // take 2; elsewhere the unrolled loop needs more registers than it saves
+    // moves.
+    static constexpr int OUTU = (OUTREG && E == 32 && WCOL >= 8 && E / BLK >= 8) ? 4
+                                : (OUTREG && D == 2 && E == 16 && WCOL == 4 && E / BLK >= 4) ? 2 : 1;
 };
 
 template <class C>
