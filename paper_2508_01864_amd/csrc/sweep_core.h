@@ -1222,7 +1222,7 @@ __global__ __launch_bounds__(C::BLOCK, C::MINW) void sweep_batch_kernel(const Sw
 // Segments of at most CARRY_SMALL tiles: one thread per (direction, slice)
 // scans the segment's tiles serially (loads issued in blocks of 8 ahead of the
 // updates).
-constexpr int CARRY_SMALL = 16;
+constexpr int CARRY_SMALL = 32;
 
 template <class C>
 __device__ __forceinline__ void carry_small(const SweepArgs &A, int pass, int64_t t0, int64_t t1, int by) {
