@@ -103,3 +103,24 @@ def test_batch_and_solver_follow_the_plan_schedule(oracle_lib):
     batch.close()
     for pl in plans:
         pl.close()
+
+
+@pytest.mark.parametrize("runex", [True, False])
+def test_carry_scan_paths_at_the_threshold(oracle_lib, runex):
+    """A lone 32-column product on 128-position tiles (16 columns per wave, runs of
+    32) whose passes have segments of exactly 32 tiles (scanned one thread per
+    slice), 64 tiles (a wave per slice) and a ragged top segment of 97 tiles:
+    12365 points."""
+    import torch
+    n, nrhs = 12365, 32
+    p = workloads.random_problem(1700 + int(runex), n, 2, 3, "product", 0.1, nrhs=nrhs)
+    yref, yabs = oracle_lib.mvm(p.x, p.v, 3, "product", p.ell, with_abs=True, shared_kernel=True)
+    plan = mm.Plan(to_gpu(p.x), mm.Kernel(3, "product", p.ell))
+    plan.set_schedule(32, 16, 32, runex)
+    vc = to_gpu(np.ascontiguousarray(p.v.T))
+    yc = torch.empty_like(vc)
+    plan.mvm_raw(vc, yc, nrhs)
+    comp, nrm = mvm_errors(to_np(yc).T, yref, yabs)
+    say("carry threshold: n=%d runex=%d comp %.2e nrm %.2e" % (n, runex, comp, nrm))
+    assert comp <= MVM_TOL and nrm <= MVM_TOL
+    plan.close()
