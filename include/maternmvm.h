@@ -139,7 +139,7 @@ mm_status mm_plan_create(const double *x, int64_t n, int32_t d, int64_t ldx,
  * below 32, multiples of 32): columns per wavefront `wb`, positions per lane
  * run `e` (tiles of 64 / wb * e positions, 128 to 1024), and whether the
  * tile-aggregate pre-pass stores every run's within-tile carry for the main
- * launch (`runex`; d <= 2 below 32 columns).  Every product of the plan at
+ * launch (`runex`; d <= 2).  Every product of the plan at
  * that width uses it: matern_mvm, solvers and batches (a problem gives the
  * same bits alone and batched whenever their schedules agree).  The
  * schedules are an implementation choice of the divide-and-conquer sweeps
