@@ -1164,10 +1164,20 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &A, Smem<C> &sm, doub
     }
 
     if constexpr (MODE == 0 && C::SUMREG) {
+        // With 16 or more columns per wave a run's lanes write whole 128-byte lines
+        // of the slab, which a later launch reads once: streaming stores keep them
+        // from displacing the gathered weight rows in L2.  Narrower rows are
+        // partial lines, which need L2 to merge them.
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
             const int sj = e * C::RUNS + run;
-            if (sm.flags[sj] & F_VALID) gst(slab + (int64_t)sm.c[sj] * A.W + col, outv[e]);
+            if (sm.flags[sj] & F_VALID) {
+                double *o = slab + (int64_t)sm.c[sj] * A.W + col;
+                if constexpr (C::WCOL >= 16)
+                    __builtin_nontemporal_store(outv[e], (__attribute__((address_space(1))) double *)o);
+                else
+                    gst(o, outv[e]);
+            }
         }
     }
     if constexpr (MODE == 0 && C::LDSOUT) {
