@@ -124,3 +124,29 @@ def test_carry_scan_paths_at_the_threshold(oracle_lib, runex):
     say("carry threshold: n=%d runex=%d comp %.2e nrm %.2e" % (n, runex, comp, nrm))
     assert comp <= MVM_TOL and nrm <= MVM_TOL
     plan.close()
+
+
+def test_streamed_slabs_across_reused_buffers(oracle_lib):
+    """Products on the 16-column schedule write their pass slabs with streaming
+    stores.  Alternating inputs on one plan (the slab buffers reused each time)
+    must reproduce each product bit for bit and match the oracle."""
+    import torch
+    n, nrhs = 9001, 32
+    p = workloads.random_problem(1800, n, 2, 3, "product", 0.1, nrhs=nrhs)
+    q = workloads.random_problem(1801, n, 2, 3, "product", 0.1, nrhs=nrhs)
+    plan = mm.Plan(to_gpu(p.x), mm.Kernel(3, "product", p.ell))
+    plan.set_schedule(32, 16, 32, True)
+    va = to_gpu(np.ascontiguousarray(p.v.T))
+    vb = to_gpu(np.ascontiguousarray(q.v.T))
+    outs = []
+    for v in (va, vb, va, vb, va):
+        y = torch.empty_like(v)
+        plan.mvm_raw(v, y, nrhs)
+        outs.append(to_np(y))
+    assert np.array_equal(outs[0], outs[2]) and np.array_equal(outs[0], outs[4])
+    assert np.array_equal(outs[1], outs[3])
+    for v, y in ((p.v, outs[4]), (q.v, outs[3])):
+        yref, yabs = oracle_lib.mvm(p.x, v, 3, "product", p.ell, with_abs=True, shared_kernel=True)
+        comp, nrm = mvm_errors(y.T, yref, yabs)
+        assert comp <= MVM_TOL and nrm <= MVM_TOL, (comp, nrm)
+    plan.close()
