@@ -83,6 +83,28 @@ __global__ void gather_caller_kernel(const double *v, int64_t ldv, int nrhs, con
     }
 }
 
+// gather_caller_kernel for W = WT (16 or 32) through LDS: a workgroup reads 64
+// consecutive caller points of every column (contiguous loads), then writes
+// each point's WT-column row of vin (whole rows).
+template <int WT>
+__global__ __launch_bounds__(256) void gather_tile_kernel(const double *v, int64_t ldv, int nrhs, const int32_t *iperm,
+                                                          int64_t n, double *vin) {
+    constexpr int TI = 64;
+    __shared__ double tile[WT][TI + 1];
+    const int64_t i0 = (int64_t)blockIdx.x * TI;
+    for (int k = threadIdx.x; k < WT * TI; k += 256) {
+        const int r = k / TI, ii = k % TI;
+        const int64_t i = i0 + ii;
+        tile[r][ii] = (r < nrhs && i < n) ? v[(int64_t)r * ldv + i] : 0.0;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < WT * TI; k += 256) {
+        const int ii = k / WT, r = k % WT;
+        const int64_t i = i0 + ii;
+        if (i < n) vin[(int64_t)iperm[i] * WT + r] = tile[r][ii];
+    }
+}
+
 // acc + the G slabs' entries at q, added in pass order; the loads go out 8
 // at a time ahead of their additions.
 __device__ __forceinline__ double slab_sum(const double *part, int G, int64_t len, int64_t q, double acc) {
@@ -145,7 +167,13 @@ inline bool fits32(int64_t n, int W) { return (uint64_t)n * (uint64_t)W + 65536u
 
 void launch_gather_caller(mm_plan p, const double *v, int64_t ldv, int nrhs, double *vin, int W, hipStream_t s) {
     const int32_t *ip = static_cast<const int32_t *>(p->iperm.ptr);
-    if (fits32(p->n, W))
+    const int64_t ntile = (p->n + 63) / 64;
+    if ((W == 32 || W == 16) && ntile <= INT32_MAX) {
+        if (W == 32)
+            hipLaunchKernelGGL(gather_tile_kernel<32>, dim3((unsigned)ntile), dim3(256), 0, s, v, ldv, nrhs, ip, p->n, vin);
+        else
+            hipLaunchKernelGGL(gather_tile_kernel<16>, dim3((unsigned)ntile), dim3(256), 0, s, v, ldv, nrhs, ip, p->n, vin);
+    } else if (fits32(p->n, W))
         hipLaunchKernelGGL(gather_caller_kernel<uint32_t>, dim3(grid1(p->n * W)), dim3(BS), 0, s, v, ldv, nrhs, ip,
                            p->n, vin, W);
     else
