@@ -152,27 +152,35 @@ def test_streamed_slabs_across_reused_buffers(oracle_lib):
     plan.close()
 
 
-def test_every_schedule_at_the_headline_size(oracle_lib):
-    """d = 2, N = 100 000, nu = 3/2 product form, lengthscale 0.1, 32 columns: every
-    compiled schedule of the timed product (the autotuner picks among exactly these)
-    against the oracle on 480 sampled target rows, and each schedule's product
-    bitwise equal when repeated."""
+@pytest.mark.parametrize("cfg", ["config2", "config3"])
+def test_every_schedule_at_the_headline_size(oracle_lib, cfg):
+    """The two timed 32-column products at full size: d = 2, N = 100 000, nu = 3/2,
+    lengthscale 0.1 (x ~ U[0,1]^2), and d = 3, N = 500 000, nu = 5/2, lengthscale 0.3
+    (x ~ N(0, I3), Rademacher columns), product form.  Every compiled schedule (the
+    autotuner picks among exactly these) against the oracle on sampled target rows,
+    and each schedule's product bitwise equal when repeated."""
     import torch
-    p = workloads.config2(nrhs=32)
-    rows = np.random.default_rng(11).choice(p.n, 480, replace=False)
-    yref, yabs = oracle_lib.mvm(p.x, p.v, 3, "product", 0.1, z=p.x[rows], with_abs=True, shared_kernel=True)
-    plan = mm.Plan(to_gpu(p.x), mm.Kernel(3, "product", 0.1))
-    vc = to_gpu(np.ascontiguousarray(p.v.T))
+    if cfg == "config2":
+        p = workloads.config2(nrhs=32)
+        d, v, nrows = 2, p.v, 480
+    else:
+        p = workloads.config3()
+        d, v, nrows = 3, p.probes, 200
+    rows = np.random.default_rng(11).choice(p.n, nrows, replace=False)
+    yref, yabs = oracle_lib.mvm(p.x, v, p.two_nu, "product", p.ell, z=p.x[rows], with_abs=True,
+                                shared_kernel=True)
+    plan = mm.Plan(to_gpu(p.x), mm.Kernel(p.two_nu, "product", p.ell))
+    vc = to_gpu(np.ascontiguousarray(v.T))
     yc = torch.empty_like(vc)
     y2 = torch.empty_like(vc)
-    cands = autotune.schedule_candidates(2, 3, "product", 32)
-    assert (16, 32, 1) in cands
+    cands = autotune.schedule_candidates(d, p.two_nu, "product", 32)
+    assert (16, 32, 1) in cands if d == 2 else (32, 128, 1) in cands
     for wb, e, rx in cands:
         plan.set_schedule(32, wb, e, bool(rx))
         plan.mvm_raw(vc, yc, 32)
         plan.mvm_raw(vc, y2, 32)
         comp, nrm = mvm_errors(to_np(yc).T[rows], yref, yabs)
-        say("headline size, schedule (%d, %d, %d): comp %.2e nrm %.2e" % (wb, e, rx, comp, nrm))
+        say("%s, schedule (%d, %d, %d): comp %.2e nrm %.2e" % (cfg, wb, e, rx, comp, nrm))
         assert comp <= MVM_TOL and nrm <= MVM_TOL, (wb, e, rx)
         assert torch.equal(yc, y2), (wb, e, rx)
     plan.close()
