@@ -184,3 +184,25 @@ def test_every_schedule_at_the_headline_size(oracle_lib, cfg):
         assert comp <= MVM_TOL and nrm <= MVM_TOL, (wb, e, rx)
         assert torch.equal(yc, y2), (wb, e, rx)
     plan.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 31, 127, 128, 129, 255, 256, 257, 513])
+def test_every_schedule_at_tile_edges(oracle_lib, n):
+    """Plans of one point up to a few tiles, sized at and around the 128- to 512-position
+    tiles of the tuned d = 2, nu = 3/2 class (no cross-tile pass, exactly one full tile,
+    a one-position last tile): every schedule at 4 and 32 columns against the whole
+    oracle product."""
+    import torch
+    p = workloads.random_problem(7000 + n, n, 2, 3, "product", 0.1, nrhs=32)
+    plan = mm.Plan(to_gpu(p.x), mm.Kernel(3, "product", p.ell))
+    for nrhs in (4, 32):
+        v = p.v[:, :nrhs]
+        yref, yabs = oracle_lib.mvm(p.x, v, 3, "product", p.ell, with_abs=True, shared_kernel=True)
+        vc = to_gpu(np.ascontiguousarray(v.T))
+        yc = torch.empty_like(vc)
+        for wb, e, rx in autotune.schedule_candidates(2, 3, "product", nrhs):
+            plan.set_schedule(nrhs, wb, e, bool(rx))
+            plan.mvm_raw(vc, yc, nrhs)
+            comp, nrm = mvm_errors(to_np(yc).T, yref, yabs)
+            assert comp <= MVM_TOL and nrm <= MVM_TOL, (n, nrhs, wb, e, rx, comp, nrm)
+    plan.close()
