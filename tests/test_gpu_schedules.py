@@ -186,21 +186,25 @@ def test_every_schedule_at_the_headline_size(oracle_lib, cfg):
     plan.close()
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 31, 127, 128, 129, 255, 256, 257, 513])
-def test_every_schedule_at_tile_edges(oracle_lib, n):
-    """Plans of one point up to a few tiles, sized at and around the 128- to 512-position
-    tiles of the tuned d = 2, nu = 3/2 class (no cross-tile pass, exactly one full tile,
-    a one-position last tile): every schedule at 4 and 32 columns against the whole
-    oracle product."""
+EDGE_CASES = [(2, 3, n) for n in (1, 2, 3, 31, 127, 128, 129, 255, 256, 257, 513)] + \
+             [(3, 5, n) for n in (1, 2, 129, 511, 512, 513, 1025)]
+
+
+@pytest.mark.parametrize("d,two_nu,n", EDGE_CASES)
+def test_every_schedule_at_tile_edges(oracle_lib, d, two_nu, n):
+    """Plans of one point up to a few tiles, sized at and around the 128- to 1024-position
+    tiles of the tuned classes (d = 2, nu = 3/2 and d = 3, nu = 5/2; no cross-tile pass,
+    exactly one full tile, a one-position last tile): every schedule at 4 and 32 columns
+    against the whole oracle product."""
     import torch
-    p = workloads.random_problem(7000 + n, n, 2, 3, "product", 0.1, nrhs=32)
-    plan = mm.Plan(to_gpu(p.x), mm.Kernel(3, "product", p.ell))
+    p = workloads.random_problem(7000 + 10 * d + n, n, d, two_nu, "product", 0.1 * (d - 1), nrhs=32)
+    plan = mm.Plan(to_gpu(p.x), mm.Kernel(two_nu, "product", p.ell))
     for nrhs in (4, 32):
         v = p.v[:, :nrhs]
-        yref, yabs = oracle_lib.mvm(p.x, v, 3, "product", p.ell, with_abs=True, shared_kernel=True)
+        yref, yabs = oracle_lib.mvm(p.x, v, two_nu, "product", p.ell, with_abs=True, shared_kernel=True)
         vc = to_gpu(np.ascontiguousarray(v.T))
         yc = torch.empty_like(vc)
-        for wb, e, rx in autotune.schedule_candidates(2, 3, "product", nrhs):
+        for wb, e, rx in autotune.schedule_candidates(d, two_nu, "product", nrhs):
             plan.set_schedule(nrhs, wb, e, bool(rx))
             plan.mvm_raw(vc, yc, nrhs)
             comp, nrm = mvm_errors(to_np(yc).T, yref, yabs)
