@@ -186,25 +186,26 @@ def test_every_schedule_at_the_headline_size(oracle_lib, cfg):
     plan.close()
 
 
-EDGE_CASES = [(2, 3, n) for n in (1, 2, 3, 31, 127, 128, 129, 255, 256, 257, 513)] + \
-             [(3, 5, n) for n in (1, 2, 129, 511, 512, 513, 1025)]
+EDGE_CASES = [(2, 3, "product", n) for n in (1, 2, 3, 31, 127, 128, 129, 255, 256, 257, 513)] + \
+             [(3, 5, "product", n) for n in (1, 2, 129, 511, 512, 513, 1025)] + \
+             [(d, 3, "l1", n) for d in (2, 3) for n in (1, 129, 256, 257, 1025)]
 
 
-@pytest.mark.parametrize("d,two_nu,n", EDGE_CASES)
-def test_every_schedule_at_tile_edges(oracle_lib, d, two_nu, n):
+@pytest.mark.parametrize("d,two_nu,form,n", EDGE_CASES)
+def test_every_schedule_at_tile_edges(oracle_lib, d, two_nu, form, n):
     """Plans of one point up to a few tiles, sized at and around the 128- to 1024-position
-    tiles of the tuned classes (d = 2, nu = 3/2 and d = 3, nu = 5/2; no cross-tile pass,
-    exactly one full tile, a one-position last tile): every schedule at 4 and 32 columns
-    against the whole oracle product."""
+    tiles (no cross-tile pass, exactly one full tile, a one-position last tile): every
+    schedule of the tuned classes (product form, d = 2 nu = 3/2 and d = 3 nu = 5/2) and
+    of the L1 form at 4 and 32 columns against the whole oracle product."""
     import torch
-    p = workloads.random_problem(7000 + 10 * d + n, n, d, two_nu, "product", 0.1 * (d - 1), nrhs=32)
-    plan = mm.Plan(to_gpu(p.x), mm.Kernel(two_nu, "product", p.ell))
+    p = workloads.random_problem(7000 + 10 * d + n, n, d, two_nu, form, 0.1 * (d - 1), nrhs=32)
+    plan = mm.Plan(to_gpu(p.x), mm.Kernel(two_nu, form, p.ell))
     for nrhs in (4, 32):
         v = p.v[:, :nrhs]
-        yref, yabs = oracle_lib.mvm(p.x, v, two_nu, "product", p.ell, with_abs=True, shared_kernel=True)
+        yref, yabs = oracle_lib.mvm(p.x, v, two_nu, form, p.ell, with_abs=True, shared_kernel=True)
         vc = to_gpu(np.ascontiguousarray(v.T))
         yc = torch.empty_like(vc)
-        for wb, e, rx in autotune.schedule_candidates(d, two_nu, "product", nrhs):
+        for wb, e, rx in autotune.schedule_candidates(d, two_nu, form, nrhs):
             plan.set_schedule(nrhs, wb, e, bool(rx))
             plan.mvm_raw(vc, yc, nrhs)
             comp, nrm = mvm_errors(to_np(yc).T, yref, yabs)
