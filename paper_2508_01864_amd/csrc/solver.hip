@@ -789,6 +789,8 @@ struct mm_solver_s {
     mm_precond pc = nullptr;         // preconditioner (pinned while the solver lives)
     double true_rel = -1.0;          // residual recomputed by the last check (-1: none)
     int64_t checked_iters = -1;      // iterations at that check
+    int2 *poll_host = nullptr;       // pinned: the status after each of two chunks in flight
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
 };
 
 struct mm_solver_batch_s {
@@ -1316,16 +1318,35 @@ mm_status solver_summary(mm_solver sv, hipStream_t s, int *conv, int *brk, doubl
 }
 
 // Iterate a single solver until convergence, breakdown or maxit.
+// The host reads the convergence status of every chunk of 8 iterations while the
+// next chunk is already queued, so the stream does not drain at each check.  A
+// chunk queued after the last active column has met its tolerance changes
+// nothing: converged columns are frozen (no update, their iteration counts stay).
 mm_status solver_run(mm_solver sv, int maxit, hipStream_t s) {
     const int check_every = 8;
-    int2 st{1, 0};
-    while (sv->iters < maxit) {
+    if (sv->iters >= maxit) return MM_OK;
+    if (!sv->poll_host) {
+        MM_HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&sv->poll_host), 2 * sizeof(int2), hipHostMallocDefault));
+        for (hipEvent_t &e : sv->poll_ev) MM_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    auto enqueue = [&](int slot) -> mm_status {
         const int k = (int)(maxit - sv->iters < check_every ? maxit - sv->iters : check_every);
         MM_TRY(solver_batch_iterate(sv->self, k, s));
-        MM_HIP_TRY(hipMemcpyAsync(&st, sv->self->status.ptr, sizeof st, hipMemcpyDeviceToHost, s));
-        MM_HIP_TRY(hipStreamSynchronize(s));
-        if (st.y || st.x == 0) break;
+        MM_HIP_TRY(hipMemcpyAsync(sv->poll_host + slot, sv->self->status.ptr, sizeof(int2), hipMemcpyDeviceToHost, s));
+        MM_HIP_TRY(hipEventRecord(sv->poll_ev[slot], s));
+        return MM_OK;
+    };
+    int slot = 0;  // the oldest chunk whose status is not read yet
+    MM_TRY(enqueue(slot));
+    for (;;) {
+        const bool ahead = sv->iters < maxit;
+        if (ahead) MM_TRY(enqueue(slot ^ 1));
+        MM_HIP_TRY(hipEventSynchronize(sv->poll_ev[slot]));
+        const int2 st = sv->poll_host[slot];
+        if (st.y || st.x == 0 || !ahead) break;
+        slot ^= 1;
     }
+    MM_HIP_TRY(hipStreamSynchronize(s));
     return MM_OK;
 }
 
@@ -1657,6 +1678,9 @@ mm_status mm_solver_destroy(mm_solver solver) {
     }
     solver->plan->npins--;
     if (solver->pc) solver->pc->npins--;
+    for (hipEvent_t e : solver->poll_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (solver->poll_host) (void)hipHostFree(solver->poll_host);
     dev_free(solver->ws);
     dev_free(solver->buf);
     delete solver;
